@@ -314,7 +314,9 @@ def mean_cov(Y: np.ndarray):
 
 
 def cholesky(S: np.ndarray) -> np.ndarray:
-    """Cholesky-Banachiewicz, row by row; raises on a non-positive pivot."""
+    """Cholesky-Banachiewicz, row by row.  Raises when a pivot is not above
+    M * 2^-52 * S_ii: the matrix is then singular to working precision (an
+    exactly rank-deficient covariance leaves pivots of rounding size)."""
     M = S.shape[0]
     L = np.zeros_like(S)
     for i in range(M):
@@ -323,7 +325,7 @@ def cholesky(S: np.ndarray) -> np.ndarray:
             for k in range(j):
                 s -= L[i, k] * L[j, k]
             if i == j:
-                if not (s > 0.0):
+                if not (s > M * 2.0 ** -52 * S[i, i]):
                     raise np.linalg.LinAlgError("not positive definite")
                 L[i, i] = math.sqrt(s)
             else:

@@ -417,6 +417,10 @@ def test_nonspd_covariance_reports_failure(oracle_mod):
     o = oracle_mod
     g = np.random.default_rng(14)
     z = g.standard_normal(100)
-    Y = np.stack([z, 2 * z, g.standard_normal(100)], 1)      # rank-deficient
-    r = o.gaussian_cost(Y, np.zeros(3))
-    assert not r["ok"] or r["f"] > 1e10
+    for Y in (np.stack([z, 2 * z, g.standard_normal(100)], 1),      # rank-deficient
+              np.stack([z, z, g.standard_normal(100)], 1),
+              np.stack([z, g.standard_normal(100), z - 0.5], 1)):
+        r = o.gaussian_cost(Y, np.zeros(3))
+        assert not r["ok"] and math.isnan(r["f"])
+    with pytest.raises(np.linalg.LinAlgError):
+        o.cholesky(np.array([[1.0, 2.0], [2.0, 1.0]]))          # indefinite
