@@ -1,0 +1,242 @@
+/*
+ * cil.h -- C ABI of the MI355X (gfx950) implementation of the Correlation
+ * Integral Likelihood hot path (Kazarnikov, Scheichl, Haario,
+ * Marciniak-Czochra, arXiv 2203.14742).
+ *
+ * The hot path: many reaction-diffusion solves run from randomised initial
+ * states to stationary patterns (Sec. 4.1, App. B.1.1), then the correlation
+ * integral statistic over pattern sets (Sec. 2.1 eqs. eCDF and CIL), its
+ * bootstrap resampling (Alg. 2bst, Alg. 3bst) and the Gaussian synthetic
+ * likelihood (eqs. cil:CF and cil:CF_synth).
+ *
+ * Conventions for every entry point:
+ *   - Return value: CIL_OK (0) or a negative CIL_E* code; no exceptions cross
+ *     the ABI.  cil_last_error() gives a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - "device" pointers are HIP device memory of the current device
+ *     (hipGetDevice at call time), owned by the caller; the library never
+ *     frees or reallocates them.  "host" pointers are ordinary host memory.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  Work is
+ *     stream-ordered on it.  A call that returns results in host memory
+ *     synchronises that stream before it returns; a call whose outputs are
+ *     all device memory returns without synchronising.
+ *   - The library keeps internal device workspaces, DCT tables and tuning
+ *     state per device; cil_shutdown() frees them.
+ *   - Pattern layout (Sec. 2.1 "patterns s in R^d", App. B.1.1 grid values):
+ *     one pattern is [species v: n x n row-major][species w: n x n row-major],
+ *     d = 2 n^2; a pattern set is nA rows of d contiguous elements.
+ */
+#ifndef CIL_H
+#define CIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    CIL_OK = 0,
+    CIL_EINVAL = -1,        /* bad argument (message in cil_last_error)        */
+    CIL_EUNSUPPORTED = -2,  /* valid but not supported by this build           */
+    CIL_ENOMEM = -3,        /* device workspace allocation failed              */
+    CIL_EDEVICE = -4,       /* HIP runtime error, or no gfx950 device          */
+    CIL_ENOTSPD = -5,       /* covariance not positive definite                */
+    CIL_ENONFINITE = -6     /* a solve produced a non-finite value             */
+};
+const char *cil_strerror(int status);
+const char *cil_last_error(void);
+
+/* ---------------------------------------------------------------- models */
+/* Reaction-diffusion kinetics of Sec. 4.1 (eq. rdgen:
+ * v_t = nu1 Lap v + f(v,w), w_t = nu2 Lap w + g(v,w)); parameter vector p:
+ *   CIL_FHN          p = {mu, eps, alpha}: f = eps (w - alpha v), g = -v + mu w - w^3
+ *   CIL_GM           p = {mu_v, mu_w}:     f = -mu_v v + v^2/w,  g = -mu_w w + v^2
+ *   CIL_GM_SOURCE    p = {a, b}:           f = a - b v + v^2/w,  g = v^2 - w
+ *                    (Gierer-Meinhardt with a source term; nu = {1, d})
+ *   CIL_BRUSSELATOR  p = {A, B}:           f = A - (B+1) v + v^2 w, g = B v - v^2 w
+ *   CIL_HEAT         no kinetics (f = g = 0); pure diffusion, for testing     */
+typedef enum {
+    CIL_FHN = 0,
+    CIL_GM = 1,
+    CIL_GM_SOURCE = 2,
+    CIL_BRUSSELATOR = 3,
+    CIL_HEAT = 4
+} cil_model;
+
+typedef enum {
+    CIL_FP64 = 0,   /* state / patterns are double                           */
+    CIL_FP32 = 1    /* state / patterns are float                            */
+} cil_precision;
+
+/* One solve: grid side n (n x n nodes, h = L/(n-1), App. B.1.1), domain
+ * length L, diffusion coefficients nu = {nu1, nu2}, kinetic parameters p. */
+typedef struct {
+    int32_t n;
+    int32_t reserved;
+    double L;
+    double nu[2];
+    double p[4];
+} cil_problem;
+
+typedef enum {
+    CIL_PATH_AUTO = 0,   /* fused LDS-resident stepper where supported, else plain */
+    CIL_PATH_PLAIN = 1,  /* one kernel per stage, host-driven step loop           */
+    CIL_PATH_FUSED = 2   /* fused stepper; CIL_EUNSUPPORTED where not available    */
+} cil_path;
+
+/* Time stepping: IMEX Euler with step dt.  tol <= 0: exactly max_steps steps.
+ * tol > 0: a solve stops at the first step s with s % check_every == 0 whose
+ * residual max|u^s - u^{s-1}|/dt (both species, all nodes, evaluated in
+ * FP64) is < tol, or at max_steps.  FP32 only: when the residual falls below
+ * the FP32 floor fp32_floor_ulps * 2^-24 * max|u| / dt (the state can no
+ * longer resolve the residual) and tol is below that floor, polish != 0
+ * promotes the solve to FP64 stepping on the GPU until tol is met (the result
+ * is rounded back to FP32); polish == 0 stops it there with status
+ * CIL_SOLVE_FP32_FLOOR. */
+typedef struct {
+    double dt;
+    int64_t max_steps;
+    double tol;
+    int32_t check_every;      /* >= 1 */
+    int32_t path;             /* cil_path */
+    int32_t polish;           /* FP32 only, see above */
+    int32_t fp32_floor_ulps;  /* <= 0 selects the default 8 */
+} cil_stepping;
+
+typedef enum {
+    CIL_SOLVE_OK = 0,
+    CIL_SOLVE_NONFINITE = 1,   /* non-finite value seen at a residual evaluation */
+    CIL_SOLVE_MAXSTEPS = 2,    /* tol > 0 not met within max_steps               */
+    CIL_SOLVE_FP32_FLOOR = 3   /* FP32 stopped at its floor (polish == 0)        */
+} cil_solve_status;
+
+typedef struct {
+    int64_t steps_taken;   /* steps applied to this solve                     */
+    int64_t steps_fp64;    /* of which in FP64 polish (FP32 calls)            */
+    double final_resid;    /* residual of the last evaluated step (NaN if non-finite) */
+    int32_t status;        /* cil_solve_status                                */
+    int32_t reserved;
+} cil_solve_report;
+
+/* Homogeneous steady state (v0, w0) with f = g = 0 (Sec. 4.1): FHN (0,0);
+ * GM (mu_w/mu_v, mu_w/mu_v^2); GM_SOURCE ((a+1)/b, ((a+1)/b)^2);
+ * Brusselator (A, B/A); HEAT (0,0).  Host only. */
+int cil_homogeneous_state(cil_model model, const double *p /*host[4]*/, double *v0w0 /*host[2]*/);
+
+/* Run B independent solves in place (App. B.1.1 method-of-lines system,
+ * integrated by IMEX Euler: explicit pointwise reaction from the old step,
+ * implicit diffusion (I - dt nu Lap_h) solved exactly in the cosine basis
+ * that diagonalises the ghost-copy Neumann Laplacian).
+ *   probs        host[B]; grid sides may differ between solves.
+ *   state        device; element type by prec; solve b occupies 2 n_b^2
+ *                elements at element offset elem_offsets[b]; in: initial
+ *                states, out: states after the last step taken.
+ *   elem_offsets host[B] or NULL (then solves are packed back to back).
+ *   reports      host[B] or NULL.
+ * Returns CIL_ENONFINITE if any solve ended with status NONFINITE (the other
+ * solves are still completed), CIL_EINVAL for n < 2, dt <= 0, max_steps < 0,
+ * check_every < 1, unknown model, NULL state. */
+int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B,
+                          void *state, const int64_t *elem_offsets, const cil_stepping *stepping,
+                          cil_solve_report *reports, void *hip_stream);
+
+/* ------------------------------------------------------- CIL statistic */
+/* Squared distances are compared with squared radii: a pair counts under
+ * radius R when D < fl(R*R) (strict, eq. eCDF).  D is the canonical squared
+ * distance: with d_k = fl64(a_k - b_k) (inputs converted to double), D is the
+ * exact sum of the d_k^2 rounded once to double.  Fast paths (an FP64 direct
+ * sum, or for FP32 sets a split-bf16x3 Gram on the matrix cores) compute an
+ * approximation with a rigorous error bound; every pair whose approximation
+ * is within that bound of some fl(R_m^2) is recomputed canonically, so all
+ * counts are exact.  radii: host[M], > 0, strictly decreasing, M <= 255. */
+
+/* counts[m] = #{(i,j) : D(A_i, B_j) < fl(R_m^2)}, m = 0..M-1 (the paper's
+ * m = 1..M); y[m] = counts[m] / (nA nB)  (eqs. eCDF, CIL).
+ *   setA device[nA][dim], setB device[nB][dim], element type by prec.
+ *   counts host[M] (required); y host[M] or NULL. */
+int cil_features(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                 cil_precision prec, const double *radii, int32_t M, int64_t *counts, double *y,
+                 void *hip_stream);
+
+/* Per-pair bin matrix: bins[i*nB + j] = #{m : D(A_i,B_j) < fl(R_m^2)}
+ * (device uint8[nA][nB]).  counts host[M] or NULL as in cil_features. */
+int cil_pair_bins(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                  cil_precision prec, const double *radii, int32_t M, uint8_t *bins,
+                  int64_t *counts, void *hip_stream);
+
+/* Smallest and largest canonical squared distance over the pairs (i, j);
+ * exclude_diagonal != 0 skips i == j (requires nA == nB).  The radii of the
+ * paper's experiments are fitted to this range (Sec. 2.1, Sec. 3.2). */
+int cil_distance_range(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                       cil_precision prec, int32_t exclude_diagonal, double *d2min /*host*/,
+                       double *d2max /*host*/, void *hip_stream);
+
+/* Canonical squared distances of selected pairs: d2[t] = D(A_ia[t], B_jb[t]).
+ * ia, jb, d2 device[npairs].  Indices are checked on the device against nA,
+ * nB: a pair with an index out of range gets d2 = NaN and the call returns
+ * CIL_EINVAL (the call synchronises the stream to report this). */
+int cil_canonical_d2(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                     cil_precision prec, const int64_t *ia, const int64_t *jb, int64_t npairs,
+                     double *d2, void *hip_stream);
+
+/* Radii ladder from a squared-distance range (Sec. 2.1, Sec. 3.2):
+ * R_0 = sqrt(d2max), R_M = sqrt(d2min); law 0: R_m = R_0 b^-m with
+ * b = (R_0/R_M)^(1/M); law 1: R_m = R_0 - m (R_0 - R_M)/M; m = 1..M.
+ * Host only; radii host[M]. */
+int cil_radii(double d2min, double d2max, int32_t M, int32_t law, double *radii);
+
+/* Diagnostics of the last distance call on this thread: pairs evaluated,
+ * pairs recomputed canonically, pairs whose canonical value needed the exact
+ * (slow) summation.  Host only. */
+int cil_last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact_fallbacks);
+
+/* Bootstrap correlation integral vectors (Alg. 2bst / Alg. 3bst step 2):
+ * resample r pairs the kA rows idxA[r][*] with the kB columns idxB[r][*]
+ * (repeats allowed) and counts Ycount[r][m] = #{(a,b) : bins[idxA][idxB] > m},
+ * Y[r][m] = Ycount[r][m] / (kA kB).
+ *   bins device uint8[nA][nB] (from cil_pair_bins); idxA device int32[n_boot][kA];
+ *   idxB device int32[n_boot][kB]; Ycount device int64[n_boot][M] or NULL;
+ *   Y device double[n_boot][M] or NULL.  Indices are checked on the device;
+ *   an out-of-range index makes the call return CIL_EINVAL. */
+int cil_bootstrap_features(const uint8_t *bins, int64_t nA, int64_t nB, int32_t M,
+                           const int32_t *idxA, int32_t kA, const int32_t *idxB, int32_t kB,
+                           int32_t n_boot, int64_t *Ycount, double *Y, void *hip_stream);
+
+/* Gaussian synthetic likelihood, batched over P independent problems
+ * (eqs. cil:CF, cil:CF_synth): per problem p, mu = mean of the n_boot rows of
+ * Y[p] (device double[P][n_boot][M]), Sigma = their covariance (1/(n_boot-1),
+ * two-pass), bins whose sample variance is exactly 0 are dropped (m_eff
+ * kept), Sigma = L L^T (Cholesky), z = L^-1 (y_obs[p] - mu),
+ *   f[p] = |z|^2,  loglik[p] = -f/2 - sum log L_ii - (m_eff/2) log(2 pi).
+ * All in FP64 on the GPU.  f, loglik device double[P]; m_eff, status device
+ * int32[P] (status CIL_OK or CIL_ENOTSPD, then f = loglik = NaN). M <= 64. */
+int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
+                        const double *y_obs, double *f, double *loglik, int32_t *m_eff,
+                        int32_t *status, void *hip_stream);
+
+/* Library options.  CIL_OPT_FORCE_EXACT_SUM (value 0/1): every canonical
+ * distance is taken by the exact (slow) summation instead of the certified
+ * double-double one; for testing that path.  Host only. */
+enum { CIL_OPT_FORCE_EXACT_SUM = 1 };
+int cil_set_option(int32_t option, int64_t value);
+
+/* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:
+ * every hot kernel launch is then bracketed by two HIP events recorded on the
+ * stream it is launched on; cil_profile(0) stops.  cil_profile_read gives the
+ * number of timed launches and their total duration in milliseconds for one
+ * kernel name (0 and 0.0 if none); cil_profile_names writes the timed kernel
+ * names, comma-separated, NUL-terminated, into buf[len].  Reading waits for
+ * the recorded events.  Host only. */
+int cil_profile(int32_t enable);
+int cil_profile_read(const char *name, int64_t *count, double *total_ms);
+int cil_profile_names(char *buf, int64_t len);
+
+/* Free every internal workspace, table and cached state on all devices. */
+int cil_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CIL_H */

@@ -1,0 +1,317 @@
+"""Python binding of libcil, the gfx950 implementation of the Correlation
+Integral Likelihood hot path (arXiv 2203.14742).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libcil.so`` (built in-tree by ``paper_2203_14742_amd.build``).  Device
+buffers are torch tensors on the current HIP device; calls run on torch's
+current stream.  The functions carry the names of the C entry points in
+``include/cil.h``; see there for the contract of each.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcil.so")
+
+CIL_OK, CIL_EINVAL, CIL_EUNSUPPORTED, CIL_ENOMEM, CIL_EDEVICE, CIL_ENOTSPD, CIL_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+CIL_FHN, CIL_GM, CIL_GM_SOURCE, CIL_BRUSSELATOR, CIL_HEAT = 0, 1, 2, 3, 4
+CIL_FP64, CIL_FP32 = 0, 1
+CIL_PATH_AUTO, CIL_PATH_PLAIN, CIL_PATH_FUSED = 0, 1, 2
+CIL_SOLVE_OK, CIL_SOLVE_NONFINITE, CIL_SOLVE_MAXSTEPS, CIL_SOLVE_FP32_FLOOR = 0, 1, 2, 3
+CIL_OPT_FORCE_EXACT_SUM = 1
+
+
+class CilError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, msg))
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("L", ctypes.c_double),
+                ("nu", ctypes.c_double * 2), ("p", ctypes.c_double * 4)]
+
+
+class Stepping(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("max_steps", ctypes.c_int64), ("tol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("path", ctypes.c_int32), ("polish", ctypes.c_int32),
+                ("fp32_floor_ulps", ctypes.c_int32)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("steps_taken", ctypes.c_int64), ("steps_fp64", ctypes.c_int64),
+                ("final_resid", ctypes.c_double), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcil.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcil.so is not built: run `python -m paper_2203_14742_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.cil_strerror.restype = ctypes.c_char_p
+        L.cil_strerror.argtypes = [ctypes.c_int]
+        L.cil_last_error.restype = ctypes.c_char_p
+        L.cil_homogeneous_state.argtypes = [ctypes.c_int, vp, vp]
+        L.cil_simulate_patterns.argtypes = [ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, vp, vp]
+        L.cil_features.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, i32, vp, vp, vp]
+        L.cil_pair_bins.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, i32, vp, vp, vp]
+        L.cil_distance_range.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, vp, vp, vp]
+        L.cil_canonical_d2.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, vp, i64, vp, vp]
+        L.cil_radii.argtypes = [dbl, dbl, i32, i32, vp]
+        L.cil_last_distance_stats.argtypes = [vp, vp, vp]
+        L.cil_bootstrap_features.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+        L.cil_gaussian_loglik.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.cil_set_option.argtypes = [i32, i64]
+        L.cil_profile.argtypes = [i32]
+        L.cil_profile_read.argtypes = [ctypes.c_char_p, vp, vp]
+        L.cil_profile_names.argtypes = [vp, i64]
+        for name in ("cil_homogeneous_state", "cil_simulate_patterns", "cil_features", "cil_pair_bins",
+                     "cil_distance_range", "cil_canonical_d2", "cil_radii", "cil_last_distance_stats",
+                     "cil_bootstrap_features", "cil_gaussian_loglik", "cil_set_option", "cil_shutdown",
+                     "cil_profile", "cil_profile_read", "cil_profile_names"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().cil_strerror(code).decode()
+    except Exception:
+        return "error"
+
+
+def _check(rc: int):
+    if rc != CIL_OK:
+        raise CilError(rc, lib().cil_last_error().decode())
+
+
+def _stream(t=None):
+    import torch
+    dev = t.device if t is not None else torch.device("cuda", torch.cuda.current_device())
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _prec(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return CIL_FP64
+    if t.dtype == torch.float32:
+        return CIL_FP32
+    raise TypeError("patterns must be float32 or float64, got %s" % t.dtype)
+
+
+def _dev(t, what: str):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _arr(x, dtype):
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+# ------------------------------------------------------------------ models
+
+def cil_homogeneous_state(model: int, p: Sequence[float]):
+    pp = np.zeros(4)
+    pp[: len(p)] = p
+    out = np.zeros(2)
+    _check(lib().cil_homogeneous_state(model, pp.ctypes.data, out.ctypes.data))
+    return float(out[0]), float(out[1])
+
+
+def make_problems(n, L, nu, p, count: int | None = None):
+    """Problem array; each argument a scalar/tuple for all solves or one row per solve."""
+    n_arr = np.atleast_1d(np.asarray(n, dtype=np.int64))
+    L_arr = np.atleast_1d(np.asarray(L, dtype=np.float64))
+    nu_arr = np.atleast_2d(np.asarray(nu, dtype=np.float64))
+    p_arr = np.atleast_2d(np.asarray(p, dtype=np.float64))
+    B = count or max(n_arr.size, L_arr.size, nu_arr.shape[0], p_arr.shape[0])
+    probs = (Problem * B)()
+    for b in range(B):
+        pr = probs[b]
+        pr.n = int(n_arr[b % n_arr.size])
+        pr.L = float(L_arr[b % L_arr.size])
+        nu_b = nu_arr[b % nu_arr.shape[0]]
+        pr.nu[0], pr.nu[1] = float(nu_b[0]), float(nu_b[1])
+        p_b = p_arr[b % p_arr.shape[0]]
+        for k in range(min(4, p_b.size)):
+            pr.p[k] = float(p_b[k])
+    return probs
+
+
+def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int, tol: float = 0.0,
+                          check_every: int = 1, path: int = CIL_PATH_AUTO, polish: int = 1,
+                          fp32_floor_ulps: int = 0, offsets=None, raise_on_nonfinite: bool = True):
+    """Run the solves in place on ``state`` (float32/float64 device tensor).
+    Returns a dict of numpy arrays: steps_taken, steps_fp64, final_resid, status."""
+    B = len(problems)
+    st = Stepping(dt=dt, max_steps=int(max_steps), tol=tol, check_every=int(check_every), path=int(path),
+                  polish=int(polish), fp32_floor_ulps=int(fp32_floor_ulps))
+    reps = (SolveReport * max(B, 1))()
+    offs = None
+    sizes = np.array([2 * problems[b].n * problems[b].n for b in range(B)], dtype=np.int64)
+    if offsets is not None:
+        offs = _arr(offsets, np.int64)
+        need = int((offs + sizes).max()) if B else 0
+    else:
+        need = int(sizes.sum())
+    if state.numel() < need:
+        raise ValueError("state holds %d elements, the solves need %d" % (state.numel(), need))
+    rc = lib().cil_simulate_patterns(model, _prec(state), ctypes.cast(problems, ctypes.c_void_p), B,
+                                     _dev(state, "state"), None if offs is None else offs.ctypes.data,
+                                     ctypes.byref(st), ctypes.cast(reps, ctypes.c_void_p), _stream(state))
+    out = dict(steps_taken=np.array([r.steps_taken for r in reps[:B]], dtype=np.int64),
+               steps_fp64=np.array([r.steps_fp64 for r in reps[:B]], dtype=np.int64),
+               final_resid=np.array([r.final_resid for r in reps[:B]]),
+               status=np.array([r.status for r in reps[:B]], dtype=np.int32))
+    if rc == CIL_ENONFINITE and not raise_on_nonfinite:
+        return out
+    _check(rc)
+    return out
+
+
+# ------------------------------------------------------- CIL statistic
+
+def _sets(A, B):
+    if A.dtype != B.dtype:
+        raise TypeError("sets must share a dtype")
+    A2 = A.reshape(A.shape[0], int(np.prod(A.shape[1:])))
+    B2 = B.reshape(B.shape[0], int(np.prod(B.shape[1:])))
+    if A2.shape[1] != B2.shape[1]:
+        raise ValueError("sets must share the pattern dimension")
+    return A2, B2
+
+
+def cil_features(A, B, radii):
+    """counts[m] = #{(i,j) : D(A_i,B_j) < R_m^2} and y = counts / (nA nB)."""
+    A2, B2 = _sets(A, B)
+    r = _arr(radii, np.float64)
+    counts = np.zeros(r.size, dtype=np.int64)
+    y = np.zeros(r.size)
+    _check(lib().cil_features(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1], _prec(A2),
+                              r.ctypes.data, r.size, counts.ctypes.data, y.ctypes.data, _stream(A2)))
+    return counts, y
+
+
+def cil_pair_bins(A, B, radii, bins=None, want_counts: bool = True):
+    import torch
+    A2, B2 = _sets(A, B)
+    r = _arr(radii, np.float64)
+    if bins is None:
+        bins = torch.empty((A2.shape[0], B2.shape[0]), dtype=torch.uint8, device=A2.device)
+    counts = np.zeros(r.size, dtype=np.int64)
+    _check(lib().cil_pair_bins(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1], _prec(A2),
+                               r.ctypes.data, r.size, _dev(bins, "bins"),
+                               counts.ctypes.data if want_counts else None, _stream(A2)))
+    return bins, counts
+
+
+def cil_distance_range(A, B, exclude_diagonal: bool = False):
+    A2, B2 = _sets(A, B)
+    lo = ctypes.c_double()
+    hi = ctypes.c_double()
+    _check(lib().cil_distance_range(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1],
+                                    _prec(A2), int(bool(exclude_diagonal)), ctypes.byref(lo), ctypes.byref(hi),
+                                    _stream(A2)))
+    return lo.value, hi.value
+
+
+def cil_canonical_d2(A, B, ia, jb):
+    import torch
+    A2, B2 = _sets(A, B)
+    ia = ia.to(device=A2.device, dtype=torch.int64).contiguous()
+    jb = jb.to(device=A2.device, dtype=torch.int64).contiguous()
+    out = torch.empty(ia.numel(), dtype=torch.float64, device=A2.device)
+    _check(lib().cil_canonical_d2(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1], _prec(A2),
+                                  _dev(ia, "ia"), _dev(jb, "jb"), ia.numel(), _dev(out, "d2"), _stream(A2)))
+    return out
+
+
+def cil_radii(d2min: float, d2max: float, M: int, law: int = 0):
+    out = np.zeros(M)
+    _check(lib().cil_radii(float(d2min), float(d2max), int(M), int(law), out.ctypes.data))
+    return out
+
+
+def cil_last_distance_stats():
+    v = np.zeros(3, dtype=np.int64)
+    _check(lib().cil_last_distance_stats(v.ctypes.data, v[1:].ctypes.data, v[2:].ctypes.data))
+    return dict(pairs=int(v[0]), rechecked=int(v[1]), exact_fallbacks=int(v[2]))
+
+
+def cil_bootstrap_features(bins, idxA, idxB, M: int, want_counts: bool = True):
+    """Returns (Ycount int64 [n_boot, M] or None, Y float64 [n_boot, M]) device tensors."""
+    import torch
+    nA, nB = bins.shape
+    idxA = idxA.to(device=bins.device, dtype=torch.int32).contiguous()
+    idxB = idxB.to(device=bins.device, dtype=torch.int32).contiguous()
+    n_boot, kA = idxA.shape
+    kB = idxB.shape[1]
+    if idxB.shape[0] != n_boot:
+        raise ValueError("index lists must have the same number of resamples")
+    Y = torch.empty((n_boot, M), dtype=torch.float64, device=bins.device)
+    Yc = torch.empty((n_boot, M), dtype=torch.int64, device=bins.device) if want_counts else None
+    _check(lib().cil_bootstrap_features(_dev(bins, "bins"), nA, nB, M, _dev(idxA, "idxA"), kA, _dev(idxB, "idxB"),
+                                        kB, n_boot, None if Yc is None else _dev(Yc, "Ycount"), _dev(Y, "Y"),
+                                        _stream(bins)))
+    return Yc, Y
+
+
+def cil_gaussian_loglik(Y, y_obs):
+    """Y [P, n_boot, M] (or [n_boot, M]) and y_obs [P, M] float64 device tensors."""
+    import torch
+    if Y.dim() == 2:
+        Y = Y.unsqueeze(0)
+        y_obs = y_obs.reshape(1, -1)
+    Y = Y.contiguous()
+    y_obs = y_obs.to(dtype=torch.float64).contiguous()
+    P, n, M = Y.shape
+    f = torch.empty(P, dtype=torch.float64, device=Y.device)
+    ll = torch.empty(P, dtype=torch.float64, device=Y.device)
+    me = torch.empty(P, dtype=torch.int32, device=Y.device)
+    stt = torch.empty(P, dtype=torch.int32, device=Y.device)
+    _check(lib().cil_gaussian_loglik(_dev(Y, "Y"), P, n, M, _dev(y_obs, "y_obs"), _dev(f, "f"), _dev(ll, "loglik"),
+                                     _dev(me, "m_eff"), _dev(stt, "status"), _stream(Y)))
+    return f, ll, me, stt
+
+
+def cil_set_option(option: int, value: int):
+    _check(lib().cil_set_option(int(option), int(value)))
+
+
+def cil_profile(enable: bool):
+    _check(lib().cil_profile(int(bool(enable))))
+
+
+def cil_profile_read(name: str):
+    """(number of timed launches, total milliseconds) for one kernel name."""
+    c = ctypes.c_int64()
+    t = ctypes.c_double()
+    _check(lib().cil_profile_read(name.encode(), ctypes.byref(c), ctypes.byref(t)))
+    return int(c.value), float(t.value)
+
+
+def cil_profile_names():
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().cil_profile_names(ctypes.cast(buf, ctypes.c_void_p), 4096))
+    s = buf.value.decode()
+    return s.split(",") if s else []
+
+
+def cil_shutdown():
+    _check(lib().cil_shutdown())

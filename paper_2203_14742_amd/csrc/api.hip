@@ -1,0 +1,493 @@
+// extern "C" entry points of libcil: argument validation, device checks,
+// workspaces and dispatch to the kernels.  See include/cil.h for the
+// contract of every function.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "cil_internal.hpp"
+
+namespace cil {
+
+// implemented in the other translation units
+int simulate_impl(cil_model, cil_precision, const cil_problem *, int, void *, const int64_t *,
+                  const cil_stepping *, cil_solve_report *, hipStream_t);
+template <typename T>
+int pair_bins_impl(const T *, long long, const T *, long long, long long, const double *, int, uint8_t *,
+                   std::vector<unsigned long long> &, hipStream_t);
+template <typename T>
+int distance_range_impl(const T *, long long, const T *, long long, long long, int, double *, double *,
+                        hipStream_t);
+template <typename T>
+int canonical_pairs_impl(const T *, long long, const T *, long long, long long, const long long *,
+                         const long long *, long long, double *, hipStream_t);
+int bootstrap_impl(const uint8_t *, long long, long long, int, const int *, int, const int *, int, int,
+                   long long *, double *, hipStream_t);
+int loglik_impl(const double *, int, int, int, const double *, double *, double *, int *, int *,
+                hipStream_t);
+int last_distance_stats(int64_t *, int64_t *, int64_t *);
+void set_force_exact(int);
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string t_err;
+}
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+void clear_error() { t_err.clear(); }
+
+// -------------------------------------------------------------- workspaces
+namespace {
+std::mutex g_ws_mu;
+struct WsEntry {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::map<std::pair<int, int>, WsEntry> g_ws;
+std::map<int, bool> g_dev_ok;
+}  // namespace
+
+int current_device(int *dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return set_error(CIL_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    return CIL_OK;
+}
+
+static int check_device()
+{
+    int dev;
+    CIL_TRY(current_device(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_dev_ok.find(dev);
+    if (it != g_dev_ok.end()) return it->second ? CIL_OK : set_error(CIL_EDEVICE, "device %d is not gfx950", dev);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return set_error(CIL_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    g_dev_ok[dev] = ok;
+    if (!ok) return set_error(CIL_EDEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    return CIL_OK;
+}
+
+int ws_get(int slot, size_t bytes, void **ptr)
+{
+    int dev;
+    CIL_TRY(current_device(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsEntry &w = g_ws[std::make_pair(dev, slot)];
+    if (w.bytes < bytes) {
+        if (w.ptr) (void)hipFree(w.ptr);
+        w.ptr = nullptr;
+        w.bytes = 0;
+        size_t want = bytes + bytes / 4 + 256;
+        if (hipMalloc(&w.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            w.ptr = nullptr;
+            return set_error(CIL_ENOMEM, "workspace allocation of %zu bytes failed", want);
+        }
+        w.bytes = want;
+    }
+    *ptr = w.ptr;
+    return CIL_OK;
+}
+
+int release_all()
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_ws) {
+        if (kv.second.ptr) {
+            (void)hipSetDevice(kv.first.first);
+            (void)hipFree(kv.second.ptr);
+        }
+    }
+    (void)hipSetDevice(cur);
+    g_ws.clear();
+    return CIL_OK;
+}
+
+// ---------------------------------------------------------------- profiler
+namespace {
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+struct PendingEv {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::vector<PendingEv> g_pending;
+std::vector<hipEvent_t> g_ev_pool;
+struct ProfAcc {
+    long long count = 0;
+    double total_ms = 0.0;
+};
+std::map<std::string, ProfAcc> g_prof;
+
+hipEvent_t take_event()
+{
+    if (!g_ev_pool.empty()) {
+        hipEvent_t e = g_ev_pool.back();
+        g_ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+}  // namespace
+
+bool prof_enabled() { return g_prof_on; }
+
+ProfMark prof_begin(const char *name, hipStream_t st)
+{
+    ProfMark m;
+    if (!g_prof_on) return m;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b) return m;
+    if (hipEventRecord(a, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return m;
+    }
+    g_pending.push_back(PendingEv{name, a, b});
+    m.slot = (int)g_pending.size() - 1;
+    return m;
+}
+
+void prof_end(ProfMark m, hipStream_t st)
+{
+    if (m.slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (m.slot < (int)g_pending.size()) (void)hipEventRecord(g_pending[m.slot].b, st);
+}
+
+void prof_flush()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &p : g_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ProfAcc &acc = g_prof[p.name];
+            acc.count += 1;
+            acc.total_ms += ms;
+        } else {
+            (void)hipGetLastError();
+        }
+        g_ev_pool.push_back(p.a);
+        g_ev_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+__global__ void k_fill_zero(unsigned char *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n8 = n / 8;
+    if (i < n8) ((unsigned long long *)p)[i] = 0ull;
+    if (i < n - 8 * n8) p[8 * n8 + i] = 0;
+}
+
+// Zero device memory with a kernel (no memset nodes, so callers may capture).
+int fill_zero(void *p, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return CIL_OK;
+    if (((uintptr_t)p & 7) != 0) return set_error(CIL_EINVAL, "fill_zero: unaligned pointer");
+    const size_t n8 = bytes / 8 + 8;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, st, (unsigned char *)p, bytes);
+    return check_launch("k_fill_zero");
+}
+
+}  // namespace cil
+
+using namespace cil;
+
+#define API_BEGIN() clear_error()
+
+static bool radii_ok(const double *radii, int M, int maxM)
+{
+    if (!radii || M < 1 || M > maxM) return false;
+    for (int m = 0; m < M; ++m) {
+        if (!(radii[m] > 0.0) || !std::isfinite(radii[m])) return false;
+        if (m > 0 && !(radii[m] < radii[m - 1])) return false;
+    }
+    return true;
+}
+
+extern "C" {
+
+const char *cil_strerror(int status)
+{
+    switch (status) {
+    case CIL_OK: return "success";
+    case CIL_EINVAL: return "invalid argument";
+    case CIL_EUNSUPPORTED: return "unsupported";
+    case CIL_ENOMEM: return "out of device memory";
+    case CIL_EDEVICE: return "device error";
+    case CIL_ENOTSPD: return "covariance not positive definite";
+    case CIL_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+    }
+}
+
+const char *cil_last_error(void) { return cil::t_err.c_str(); }
+
+int cil_homogeneous_state(cil_model model, const double *p, double *v0w0)
+{
+    API_BEGIN();
+    if (!p || !v0w0) return set_error(CIL_EINVAL, "null pointer");
+    switch (model) {
+    case CIL_FHN:
+    case CIL_HEAT: v0w0[0] = 0.0; v0w0[1] = 0.0; return CIL_OK;
+    case CIL_GM:
+        if (!(p[0] != 0.0)) return set_error(CIL_EINVAL, "mu_v must be non-zero");
+        v0w0[0] = p[1] / p[0];
+        v0w0[1] = p[1] / (p[0] * p[0]);
+        return CIL_OK;
+    case CIL_GM_SOURCE:
+        if (!(p[1] != 0.0)) return set_error(CIL_EINVAL, "b must be non-zero");
+        v0w0[0] = (p[0] + 1.0) / p[1];
+        v0w0[1] = v0w0[0] * v0w0[0];
+        return CIL_OK;
+    case CIL_BRUSSELATOR:
+        if (!(p[0] != 0.0)) return set_error(CIL_EINVAL, "A must be non-zero");
+        v0w0[0] = p[0];
+        v0w0[1] = p[1] / p[0];
+        return CIL_OK;
+    default: return set_error(CIL_EINVAL, "unknown model %d", (int)model);
+    }
+}
+
+int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B, void *state,
+                          const int64_t *elem_offsets, const cil_stepping *stepping, cil_solve_report *reports,
+                          void *hip_stream)
+{
+    API_BEGIN();
+    if ((int)model < CIL_FHN || (int)model > CIL_HEAT) return set_error(CIL_EINVAL, "unknown model %d", (int)model);
+    if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
+    if (B < 0) return set_error(CIL_EINVAL, "B < 0");
+    if (B == 0) return CIL_OK;
+    if (!probs || !state || !stepping) return set_error(CIL_EINVAL, "null pointer");
+    if (!(stepping->dt > 0.0) || !std::isfinite(stepping->dt)) return set_error(CIL_EINVAL, "dt must be > 0");
+    if (stepping->max_steps < 0) return set_error(CIL_EINVAL, "max_steps < 0");
+    if (stepping->check_every < 1) return set_error(CIL_EINVAL, "check_every < 1");
+    if (stepping->path < CIL_PATH_AUTO || stepping->path > CIL_PATH_FUSED)
+        return set_error(CIL_EINVAL, "unknown path");
+    for (int b = 0; b < B; ++b) {
+        const cil_problem &p = probs[b];
+        if (p.n < 2 || p.n > 4096) return set_error(CIL_EINVAL, "solve %d: n = %d out of range [2, 4096]", b, p.n);
+        if (!(p.L > 0.0) || !std::isfinite(p.L)) return set_error(CIL_EINVAL, "solve %d: L must be > 0", b);
+        if (!(p.nu[0] >= 0.0) || !(p.nu[1] >= 0.0)) return set_error(CIL_EINVAL, "solve %d: nu must be >= 0", b);
+        if (elem_offsets && elem_offsets[b] < 0) return set_error(CIL_EINVAL, "solve %d: negative offset", b);
+    }
+    CIL_TRY(check_device());
+    if (stepping->max_steps == 0) {
+        if (reports)
+            for (int b = 0; b < B; ++b) reports[b] = cil_solve_report{0, 0, 0.0, CIL_SOLVE_OK, 0};
+        return CIL_OK;
+    }
+    return simulate_impl(model, prec, probs, B, state, elem_offsets, stepping, reports, (hipStream_t)hip_stream);
+}
+
+static int check_sets(const void *A, int64_t nA, const void *B, int64_t nB, int64_t dim, cil_precision prec)
+{
+    if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
+    if (nA < 0 || nB < 0 || dim < 0) return set_error(CIL_EINVAL, "negative size");
+    if (nA > 0x7fffffffLL || nB > 0x7fffffffLL) return set_error(CIL_EINVAL, "set too large");
+    if ((nA > 0 && !A) || (nB > 0 && !B)) return set_error(CIL_EINVAL, "null set pointer");
+    return CIL_OK;
+}
+
+int cil_pair_bins(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                  const double *radii, int32_t M, uint8_t *bins, int64_t *counts, void *hip_stream)
+{
+    API_BEGIN();
+    CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
+    if (!radii_ok(radii, M, 255)) return set_error(CIL_EINVAL, "radii must be > 0, finite, strictly decreasing, 1 <= M <= 255");
+    CIL_TRY(check_device());
+    std::vector<unsigned long long> hist;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == CIL_FP64)
+        CIL_TRY(pair_bins_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim, radii, M, bins, hist, st));
+    else
+        CIL_TRY(pair_bins_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, radii, M, bins, hist, st));
+    if (counts) {
+        unsigned long long run = 0;
+        for (int m = M; m >= 1; --m) {       // counts[m-1] = #{bin >= m}
+            run += hist[m];
+            counts[m - 1] = (int64_t)run;
+        }
+    }
+    return CIL_OK;
+}
+
+int cil_features(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                 const double *radii, int32_t M, int64_t *counts, double *y, void *hip_stream)
+{
+    API_BEGIN();
+    if (!counts) return set_error(CIL_EINVAL, "counts must not be NULL");
+    CIL_TRY(cil_pair_bins(setA, nA, setB, nB, dim, prec, radii, M, nullptr, counts, hip_stream));
+    if (y) {
+        const double np = (double)nA * (double)nB;
+        for (int m = 0; m < M; ++m) y[m] = np > 0 ? (double)counts[m] / np : 0.0;
+    }
+    return CIL_OK;
+}
+
+int cil_distance_range(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                       int32_t exclude_diagonal, double *d2min, double *d2max, void *hip_stream)
+{
+    API_BEGIN();
+    CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
+    if (!d2min || !d2max) return set_error(CIL_EINVAL, "null output");
+    if (exclude_diagonal && nA != nB) return set_error(CIL_EINVAL, "exclude_diagonal needs nA == nB");
+    const long long np = nA * nB - (exclude_diagonal ? nA : 0);
+    if (np <= 0) return set_error(CIL_EINVAL, "no pairs");
+    CIL_TRY(check_device());
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == CIL_FP64)
+        return distance_range_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim,
+                                           exclude_diagonal, d2min, d2max, st);
+    return distance_range_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, exclude_diagonal,
+                                      d2min, d2max, st);
+}
+
+int cil_canonical_d2(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                     const int64_t *ia, const int64_t *jb, int64_t npairs, double *d2, void *hip_stream)
+{
+    API_BEGIN();
+    CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
+    if (npairs < 0) return set_error(CIL_EINVAL, "negative size");
+    if (npairs == 0) return CIL_OK;
+    if (!setA || !setB || !ia || !jb || !d2) return set_error(CIL_EINVAL, "null pointer");
+    CIL_TRY(check_device());
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == CIL_FP64)
+        return canonical_pairs_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim,
+                                            (const long long *)ia, (const long long *)jb, npairs, d2, st);
+    return canonical_pairs_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, (const long long *)ia,
+                                       (const long long *)jb, npairs, d2, st);
+}
+
+int cil_radii(double d2min, double d2max, int32_t M, int32_t law, double *radii)
+{
+    API_BEGIN();
+    if (!radii || M < 1) return set_error(CIL_EINVAL, "bad arguments");
+    const double R0 = std::sqrt(d2max), RM = std::sqrt(d2min);
+    if (!(RM > 0.0) || !(R0 > RM) || !std::isfinite(R0))
+        return set_error(CIL_EINVAL, "degenerate distance range [%g, %g]", d2min, d2max);
+    if (law == 0) {
+        const double b = std::pow(R0 / RM, 1.0 / M);
+        for (int m = 1; m <= M; ++m) radii[m - 1] = R0 * std::pow(b, (double)-m);
+    } else if (law == 1) {
+        const double h = (R0 - RM) / M;
+        for (int m = 1; m <= M; ++m) radii[m - 1] = R0 - m * h;
+    } else {
+        return set_error(CIL_EINVAL, "unknown radius law %d", law);
+    }
+    return CIL_OK;
+}
+
+int cil_last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact_fallbacks)
+{
+    return last_distance_stats(pairs, rechecked, exact_fallbacks);
+}
+
+int cil_bootstrap_features(const uint8_t *bins, int64_t nA, int64_t nB, int32_t M, const int32_t *idxA, int32_t kA,
+                           const int32_t *idxB, int32_t kB, int32_t n_boot, int64_t *Ycount, double *Y,
+                           void *hip_stream)
+{
+    API_BEGIN();
+    if (M < 1 || M > 255) return set_error(CIL_EINVAL, "M must be in [1, 255]");
+    if (nA <= 0 || nB <= 0 || kA <= 0 || kB <= 0 || n_boot < 0) return set_error(CIL_EINVAL, "bad sizes");
+    if (!bins || !idxA || !idxB) return set_error(CIL_EINVAL, "null pointer");
+    CIL_TRY(check_device());
+    return bootstrap_impl(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, (long long *)Ycount, Y,
+                          (hipStream_t)hip_stream);
+}
+
+int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M, const double *y_obs, double *f,
+                        double *loglik, int32_t *m_eff, int32_t *status, void *hip_stream)
+{
+    API_BEGIN();
+    if (P < 0 || n_boot < 2 || M < 1 || M > 64) return set_error(CIL_EINVAL, "need P >= 0, n_boot >= 2, 1 <= M <= 64");
+    if (P > 0 && (!Y || !y_obs || !f || !loglik || !m_eff || !status)) return set_error(CIL_EINVAL, "null pointer");
+    CIL_TRY(check_device());
+    return loglik_impl(Y, P, n_boot, M, y_obs, f, loglik, m_eff, status, (hipStream_t)hip_stream);
+}
+
+int cil_set_option(int32_t option, int64_t value)
+{
+    API_BEGIN();
+    if (option == 1) {
+        set_force_exact((int)value);
+        return CIL_OK;
+    }
+    return set_error(CIL_EINVAL, "unknown option %d", option);
+}
+
+int cil_profile(int32_t enable)
+{
+    API_BEGIN();
+    prof_flush();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    if (enable) g_prof.clear();
+    return CIL_OK;
+}
+
+int cil_profile_read(const char *name, int64_t *count, double *total_ms)
+{
+    API_BEGIN();
+    if (!name || !count || !total_ms) return set_error(CIL_EINVAL, "null pointer");
+    prof_flush();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    auto it = g_prof.find(name);
+    *count = it == g_prof.end() ? 0 : it->second.count;
+    *total_ms = it == g_prof.end() ? 0.0 : it->second.total_ms;
+    return CIL_OK;
+}
+
+int cil_profile_names(char *buf, int64_t len)
+{
+    API_BEGIN();
+    if (!buf || len < 1) return set_error(CIL_EINVAL, "bad buffer");
+    prof_flush();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::string s;
+    for (auto &kv : g_prof) {
+        if (!s.empty()) s += ",";
+        s += kv.first;
+    }
+    if ((int64_t)s.size() + 1 > len) return set_error(CIL_EINVAL, "buffer too small (%zu)", s.size() + 1);
+    memcpy(buf, s.c_str(), s.size() + 1);
+    return CIL_OK;
+}
+
+int cil_shutdown(void)
+{
+    API_BEGIN();
+    prof_flush();
+    return release_all();
+}
+
+}  // extern "C"

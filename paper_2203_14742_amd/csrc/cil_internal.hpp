@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP translation units of libcil.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <type_traits>
+#include <utility>
+
+#include "../../include/cil.h"
+
+namespace cil {
+
+// ------------------------------------------------------------------ errors
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
+#define CIL_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return ::cil::set_error(CIL_EDEVICE, "%s failed: %s (%s:%d)", #expr,         \
+                                    hipGetErrorString(_e), __FILE__, __LINE__);         \
+    } while (0)
+
+#define CIL_TRY(expr)                                                                   \
+    do {                                                                                \
+        int _rc = (expr);                                                               \
+        if (_rc != CIL_OK) return _rc;                                                  \
+    } while (0)
+
+// -------------------------------------------------------------- workspaces
+// Grow-only device buffers, one per (device, slot).  Contents are not kept
+// across calls unless the caller says so.  Freed by cil_shutdown().
+enum WsSlot {
+    WS_STEP_SOLVES = 0, WS_STEP_LIST, WS_STEP_RESID, WS_STEP_TABLES, WS_STEP_WORK_A,
+    WS_STEP_WORK_B, WS_STEP_STATE64, WS_STEP_LIST64, WS_STEP_DCT,
+    WS_DIST_NORMS, WS_DIST_SPLIT_A, WS_DIST_SPLIT_B, WS_DIST_RECHECK, WS_DIST_COUNTS,
+    WS_DIST_MISC, WS_DIST_SAMPLE, WS_BOOT_MISC, WS_STATS_MISC,
+    WS_NUM_SLOTS
+};
+int ws_get(int slot, size_t bytes, void **ptr);
+int current_device(int *dev);
+int release_all();
+// Zero device memory with a kernel (keeps memset nodes out of captured graphs).
+int fill_zero(void *p, size_t bytes, hipStream_t st);
+
+// ---------------------------------------------------------------- profiler
+// When enabled (cil_profile), hot kernel launches are bracketed by HIP events
+// recorded on the launch stream; durations are accumulated per kernel name.
+bool prof_enabled();
+struct ProfMark {
+    int slot = -1;
+};
+ProfMark prof_begin(const char *name, hipStream_t st);
+void prof_end(ProfMark m, hipStream_t st);
+void prof_flush();
+
+// --------------------------------------------------------- launch checks
+inline int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(CIL_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return CIL_OK;
+}
+
+// ------------------------------------------------- compile-time cos / sin
+// cos(pi p / q) and sin(pi p / q) for integers p, q > 0, evaluated at
+// compile time: exact octant reduction in integers, then a Taylor series on
+// [0, pi/4].  Accurate to about one ulp in double; used for FFT twiddles,
+// which then become instruction literals.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ce_sin_series(double x)
+{
+    double x2 = x * x, term = x, sum = x;
+    for (int k = 1; k < 15; ++k) {
+        term *= -x2 / (double)((2 * k) * (2 * k + 1));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr double ce_cos_series(double x)
+{
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 15; ++k) {
+        term *= -x2 / (double)((2 * k - 1) * (2 * k));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr double ce_cospi(long p, long q)
+{
+    long r = p % (2 * q);
+    if (r < 0) r += 2 * q;          // [0, 2q)
+    if (r > q) r = 2 * q - r;       // cos is even about pi: [0, q]
+    double sign = 1.0;
+    if (2 * r > q) {                // (pi/2, pi]: cos(t) = -cos(pi - t)
+        r = q - r;
+        sign = -1.0;
+    }
+    if (4 * r > q)                  // (pi/4, pi/2]: cos(t) = sin(pi/2 - t)
+        return sign * ce_sin_series(kPi * (double)(q - 2 * r) / (double)(2 * q));
+    return sign * ce_cos_series(kPi * (double)r / (double)q);
+}
+
+constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
+
+// ------------------------------------------------------------ static_for
+template <int I, int N, typename F>
+__host__ __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int x, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; ++i)
+        if (x & (1 << i)) r |= 1 << (bits - 1 - i);
+    return r;
+}
+
+}  // namespace cil

@@ -1,0 +1,805 @@
+// Batched IMEX-Euler reaction-diffusion stepper (App. B.1.1 method-of-lines
+// system of the Sec. 4.1 models) on gfx950.
+//
+// One step of one solve, both species s in {v, w}:
+//   r_s   = u_s + dt F_s(u_v, u_w)                   (explicit, old values)
+//   u_s'  = (I - dt nu_s Lap_h)^{-1} r_s              (implicit diffusion)
+// Lap_h is the five-point Laplacian with ghost-copy Neumann boundaries; its
+// eigenvectors are the cosine modes cos(pi k (i+1/2)/n) with eigenvalues
+// -(4/h^2)(sin^2(pi k/2n) + sin^2(pi l/2n)), so the solve is: 2D DCT-II,
+// divide by 1 + dt nu_s Lambda_kl, inverse 2D DCT.
+//
+// Two back-ends:
+//   plain  one kernel per stage (reaction, row DCT, column DCT + divide,
+//          column inverse, row inverse + residual), dense cosine matrices,
+//          state streamed through HBM, host-driven step loop; any n >= 2.
+//   fused  one workgroup per solve, the whole n x n x 2 state resident in
+//          LDS for K steps per launch, every line transformed in registers
+//          by the FFT-based DCT of dct_reg.hpp; n in {32, 64, 128} (FP32),
+//          {32, 64} (FP64).
+// Both evaluate the stationarity residual max |u^s - u^{s-1}| / dt in FP64
+// at the last step of each launch, per solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "cil_internal.hpp"
+#include "dct_reg.hpp"
+
+namespace cil {
+
+struct DevSolve {
+    int64_t off;     // element offset of the solve's state
+    int32_t n;
+    int32_t tab;     // spectral-table index (fused back-end)
+    double inv_h2;   // 1/h^2, h = L/(n-1)
+    double nu[2];
+    double p[4];
+};
+
+struct StepResults {               // indexed by solve
+    unsigned long long *resid;     // bits of a non-negative double: max |du|
+    unsigned long long *maxabs;    // bits of max |u|
+    int *bad;                      // non-finite value seen
+};
+
+// -------------------------------------------------------------- kinetics
+// Sec. 4.1 reaction terms; the model is uniform over a launch.
+template <int MODEL, typename T>
+__device__ __forceinline__ void kinetics(const T *p, T v, T w, T &f, T &g)
+{
+    if constexpr (MODEL == CIL_FHN) {
+        f = p[1] * (w - p[2] * v);
+        g = -v + p[0] * w - w * w * w;
+    } else if constexpr (MODEL == CIL_GM) {
+        f = -p[0] * v + v * v / w;
+        g = -p[1] * w + v * v;
+    } else if constexpr (MODEL == CIL_GM_SOURCE) {
+        f = p[0] - p[1] * v + v * v / w;
+        g = v * v - w;
+    } else if constexpr (MODEL == CIL_BRUSSELATOR) {
+        f = p[0] - (p[1] + T(1)) * v + v * v * w;
+        g = p[1] * v - v * v * w;
+    } else {
+        f = T(0);
+        g = T(0);
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ void dispatch_model(int model, F &&f)
+{
+    switch (model) {
+    case CIL_FHN: f(std::integral_constant<int, CIL_FHN>{}); break;
+    case CIL_GM: f(std::integral_constant<int, CIL_GM>{}); break;
+    case CIL_GM_SOURCE: f(std::integral_constant<int, CIL_GM_SOURCE>{}); break;
+    case CIL_BRUSSELATOR: f(std::integral_constant<int, CIL_BRUSSELATOR>{}); break;
+    default: f(std::integral_constant<int, CIL_HEAT>{}); break;
+    }
+}
+
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_or(int x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+    return x;
+}
+
+__global__ void k_clear_results(const int *list, int nlist, StepResults R)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nlist) {
+        int b = list[t];
+        R.resid[b] = 0ull;
+        R.maxabs[b] = 0ull;
+        R.bad[b] = 0;
+    }
+}
+
+// ======================================================================
+// Plain back-end.  Work buffers are [slot][2][n][n] in T.  Tables per n:
+// C[k][j] = cos(pi k (2j+1)/2n), Ct = C^T, Cw[k][j] = w_k C[k][j] with
+// w_0 = 1/n, w_k = 2/n (so Cw^T inverts C), lam[k] = 4 sin^2(pi k/2n).
+
+template <typename T>
+__global__ void k_plain_reaction(const DevSolve *S, const int *list, const T *state, T *R,
+                                 int n, int model, double dt)
+{
+    const int slot = blockIdx.y;
+    const DevSolve s = S[list[slot]];
+    const int N2 = n * n;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N2) return;
+    const T *u = state + s.off;
+    T *r = R + (size_t)slot * 2 * N2;
+    T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
+    const T v = u[q], w = u[N2 + q];
+    dispatch_model(model, [&](auto MD) {
+        T f, g;
+        kinetics<MD>(p, v, w, f, g);
+        r[q] = v + T(dt) * f;
+        r[N2 + q] = w + T(dt) * g;
+    });
+}
+
+// out[i][l] = sum_j in[i][j] C[l][j]   (row forward)
+template <typename T>
+__global__ void k_plain_rows_fwd(const int *list, const T *in, T *out, const T *Ct, int n)
+{
+    const int slot = blockIdx.y;
+    const int N2 = n * n;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * N2) return;
+    (void)list;
+    const int sp = e / N2, i = (e / n) % n, l = e % n;
+    const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2 + (size_t)i * n;
+    T acc = T(0);
+    for (int j = 0; j < n; ++j) acc += x[j] * Ct[j * n + l];
+    out[(size_t)slot * 2 * N2 + e] = acc;
+}
+
+// out[k][l] = S_kl * sum_i C[k][i] in[i][l],  S_kl = 1/(1 + dt nu (lam_k+lam_l)/h^2)
+template <typename T>
+__global__ void k_plain_cols_fwd_div(const DevSolve *S, const int *list, const T *in, T *out,
+                                     const T *C, const double *lam, int n, double dt)
+{
+    const int slot = blockIdx.y;
+    const DevSolve s = S[list[slot]];
+    const int N2 = n * n;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * N2) return;
+    const int sp = e / N2, k = (e / n) % n, l = e % n;
+    const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2;
+    T acc = T(0);
+    for (int i = 0; i < n; ++i) acc += C[k * n + i] * x[i * n + l];
+    const double fac = 1.0 / (1.0 + dt * s.nu[sp] * (lam[k] + lam[l]) * s.inv_h2);
+    out[(size_t)slot * 2 * N2 + e] = acc * T(fac);
+}
+
+// out[i][l] = sum_k Cw[k][i] in[k][l]   (column inverse)
+template <typename T>
+__global__ void k_plain_cols_inv(const int *list, const T *in, T *out, const T *Cw, int n)
+{
+    const int slot = blockIdx.y;
+    (void)list;
+    const int N2 = n * n;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * N2) return;
+    const int sp = e / N2, i = (e / n) % n, l = e % n;
+    const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2;
+    T acc = T(0);
+    for (int k = 0; k < n; ++k) acc += Cw[k * n + i] * x[k * n + l];
+    out[(size_t)slot * 2 * N2 + e] = acc;
+}
+
+// u'[i][j] = sum_l in[i][l] Cw[l][j]   (row inverse), written to the state;
+// at an evaluation step also the residual against the old state.
+template <typename T>
+__global__ void k_plain_rows_inv(const DevSolve *S, const int *list, const T *in, T *state,
+                                 const T *Cw, int n, int check, StepResults R)
+{
+    const int slot = blockIdx.y;
+    const int b = list[slot];
+    const DevSolve s = S[b];
+    const int N2 = n * n;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0, a = 0.0;
+    int bad = 0;
+    if (e < 2 * N2) {
+        const int sp = e / N2, i = (e / n) % n, j = e % n;
+        const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2 + (size_t)i * n;
+        T acc = T(0);
+        for (int l = 0; l < n; ++l) acc += x[l] * Cw[l * n + j];
+        T *u = state + s.off;
+        if (check) {
+            const double old = (double)u[e];
+            d = fabs((double)acc - old);
+            a = fabs((double)acc);
+            bad = !isfinite((double)acc);
+        }
+        u[e] = acc;
+    }
+    if (check) {
+        d = wave_max(isnan(d) ? 0.0 : d);
+        a = wave_max(isnan(a) ? 0.0 : a);
+        bad = wave_or(bad);
+        if ((threadIdx.x & 63) == 0) {
+            atomicMax(&R.resid[b], (unsigned long long)__double_as_longlong(d));
+            atomicMax(&R.maxabs[b], (unsigned long long)__double_as_longlong(a));
+            if (bad) atomicOr(&R.bad[b], 1);
+        }
+    }
+}
+
+// ======================================================================
+// Fused back-end: one workgroup of 2N threads per solve; thread t handles
+// species t / N and line t % N.  LDS holds u[2][N][N+1] (padded rows).
+
+template <typename T, int N>
+struct FusedCfg {
+    static constexpr int LD = N + 1;
+    static constexpr int SP = N * LD;
+    static constexpr int THREADS = 2 * N;
+    static constexpr size_t LDS_BYTES = sizeof(T) * 2 * SP;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *list, T *state,
+                                                 const T *tables, int model, double dt, int K,
+                                                 StepResults R)
+{
+    using Cfg = FusedCfg<T, N>;
+    using D = DctLine<T, N>;
+    __shared__ T sm[2 * Cfg::SP];
+    __shared__ double red[2 * Cfg::THREADS / 64 + 2];
+
+    const int b = list[blockIdx.x];
+    const DevSolve s = S[b];
+    T *u = state + s.off;
+    const T *tab = tables + (size_t)s.tab * 2 * N * N;
+    const int tid = threadIdx.x;
+    const int sp = tid / N, ln = tid % N;
+    T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
+    const T tdt = T(dt);
+
+    for (int q = tid; q < 2 * N * N; q += Cfg::THREADS) {
+        const int c = q / (N * N), rem = q % (N * N);
+        sm[c * Cfg::SP + (rem / N) * Cfg::LD + rem % N] = u[q];
+    }
+    __syncthreads();
+
+    for (int step = 0; step < K; ++step) {
+        if (step == K - 1) {          // keep u^{K-1} in HBM for the residual
+            for (int q = tid; q < 2 * N * N; q += Cfg::THREADS) {
+                const int c = q / (N * N), rem = q % (N * N);
+                u[q] = sm[c * Cfg::SP + (rem / N) * Cfg::LD + rem % N];
+            }
+        }
+        // explicit reaction, pointwise, both species from the old values
+        dispatch_model(model, [&](auto MD) {
+            for (int q = tid; q < N * N; q += Cfg::THREADS) {
+                const int a = (q / N) * Cfg::LD + q % N;
+                const T v = sm[a], w = sm[Cfg::SP + a];
+                T f, g;
+                kinetics<MD>(p, v, w, f, g);
+                sm[a] = v + tdt * f;
+                sm[Cfg::SP + a] = w + tdt * g;
+            }
+        });
+        __syncthreads();
+        T *ms = sm + sp * Cfg::SP;
+        {   // forward DCT along rows
+            T x[N], X[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) x[j] = ms[ln * Cfg::LD + j];
+            D::forward(x, X);
+#pragma unroll
+            for (int j = 0; j < N; ++j) ms[ln * Cfg::LD + j] = X[j];
+        }
+        __syncthreads();
+        {   // forward DCT along columns, spectral divide, inverse along columns
+            T x[N], X[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[i] = ms[i * Cfg::LD + ln];
+            D::forward(x, X);
+            const T *tb = tab + (size_t)sp * N * N + ln;
+#pragma unroll
+            for (int k = 0; k < N; ++k) X[k] *= tb[k * N];
+            D::inverse(X, x);
+#pragma unroll
+            for (int i = 0; i < N; ++i) ms[i * Cfg::LD + ln] = x[i];
+        }
+        __syncthreads();
+        {   // inverse DCT along rows
+            T x[N], X[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) X[j] = ms[ln * Cfg::LD + j];
+            D::inverse(X, x);
+#pragma unroll
+            for (int j = 0; j < N; ++j) ms[ln * Cfg::LD + j] = x[j];
+        }
+        __syncthreads();
+    }
+
+    // write back, residual against u^{K-1} (FP64), max |u|, non-finite flag
+    double d = 0.0, a = 0.0;
+    int bad = 0;
+    for (int q = tid; q < 2 * N * N; q += Cfg::THREADS) {
+        const int c = q / (N * N), rem = q % (N * N);
+        const T nv = sm[c * Cfg::SP + (rem / N) * Cfg::LD + rem % N];
+        const double dv = fabs((double)nv - (double)u[q]);
+        const double av = fabs((double)nv);
+        if (!isfinite((double)nv)) bad = 1;
+        d = fmax(d, isnan(dv) ? 0.0 : dv);
+        a = fmax(a, isnan(av) ? 0.0 : av);
+        u[q] = nv;
+    }
+    d = wave_max(d);
+    a = wave_max(a);
+    bad = wave_or(bad);
+    const int wv = tid / 64;
+    if ((tid & 63) == 0) {
+        red[wv] = d;
+        red[Cfg::THREADS / 64 + wv] = a;
+        if (bad) R.bad[b] = 1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double dm = 0.0, am = 0.0;
+        for (int w = 0; w < Cfg::THREADS / 64; ++w) {
+            dm = fmax(dm, red[w]);
+            am = fmax(am, red[Cfg::THREADS / 64 + w]);
+        }
+        R.resid[b] = (unsigned long long)__double_as_longlong(dm);
+        R.maxabs[b] = (unsigned long long)__double_as_longlong(am);
+    }
+}
+
+// Spectral tables for the fused back-end:
+// tab[s][k][l] = 1 / (4 N^2 (1 + dt nu_s (lam_k + lam_l) / h^2)), in FP64 then T.
+struct TabSpec {
+    double inv_h2, nu0, nu1;
+};
+template <typename T>
+__global__ void k_make_tables(const TabSpec *specs, int ntab, int n, double dt, T *out)
+{
+    const int t = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntab || e >= 2 * n * n) return;
+    const int sp = e / (n * n), k = (e / n) % n, l = e % n;
+    const TabSpec ts = specs[t];
+    const double sk = sinpi((double)k / (2.0 * n)), sl = sinpi((double)l / (2.0 * n));
+    const double lam = 4.0 * (sk * sk + sl * sl) * ts.inv_h2;
+    const double nu = sp ? ts.nu1 : ts.nu0;
+    out[(size_t)t * 2 * n * n + e] = T(1.0 / (4.0 * n * (double)n * (1.0 + dt * nu * lam)));
+}
+
+template <typename S, typename D>
+__global__ void k_convert_solves(const DevSolve *Ssrc, const DevSolve *Sdst, const int *list,
+                                 const S *src, D *dst)
+{
+    const int b = list[blockIdx.y];
+    const DevSolve a = Ssrc[b], c = Sdst[b];
+    const int sz = 2 * a.n * a.n;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < sz; e += gridDim.x * blockDim.x)
+        dst[c.off + e] = D(src[a.off + e]);
+}
+
+// ======================================================================
+// Host side.
+
+namespace {
+
+struct PlainTables {
+    void *C = nullptr, *Ct = nullptr, *Cw = nullptr;   // T[n*n]
+    double *lam = nullptr;                              // double[n]
+};
+std::map<std::tuple<int, int, int>, PlainTables> g_plain_tables;   // (device, n, is_f32)
+
+template <typename T>
+int plain_tables(int n, PlainTables *out)
+{
+    int dev;
+    CIL_TRY(current_device(&dev));
+    auto key = std::make_tuple(dev, n, (int)std::is_same<T, float>::value);
+    auto it = g_plain_tables.find(key);
+    if (it != g_plain_tables.end()) {
+        *out = it->second;
+        return CIL_OK;
+    }
+    std::vector<T> C(n * n), Ct(n * n), Cw(n * n);
+    std::vector<double> lam(n);
+    for (int k = 0; k < n; ++k) {
+        const double wk = (k == 0 ? 1.0 : 2.0) / n;
+        for (int j = 0; j < n; ++j) {
+            const double c = std::cos(M_PI * k * (2.0 * j + 1.0) / (2.0 * n));
+            C[k * n + j] = T(c);
+            Ct[j * n + k] = T(c);
+            Cw[k * n + j] = T(wk * c);
+        }
+        const double sk = std::sin(M_PI * k / (2.0 * n));
+        lam[k] = 4.0 * sk * sk;
+    }
+    PlainTables t;
+    size_t bytes = sizeof(T) * n * n;
+    if (hipMalloc(&t.C, bytes) != hipSuccess || hipMalloc(&t.Ct, bytes) != hipSuccess ||
+        hipMalloc(&t.Cw, bytes) != hipSuccess || hipMalloc(&t.lam, sizeof(double) * n) != hipSuccess)
+        return set_error(CIL_ENOMEM, "table allocation failed");
+    CIL_HIP(hipMemcpy(t.C, C.data(), bytes, hipMemcpyHostToDevice));
+    CIL_HIP(hipMemcpy(t.Ct, Ct.data(), bytes, hipMemcpyHostToDevice));
+    CIL_HIP(hipMemcpy(t.Cw, Cw.data(), bytes, hipMemcpyHostToDevice));
+    CIL_HIP(hipMemcpy(t.lam, lam.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    g_plain_tables[key] = t;
+    *out = t;
+    return CIL_OK;
+}
+
+// One group: solves with one grid side n, one back-end, one element type.
+struct Group {
+    int n = 0;
+    bool fused = false;
+    bool f32 = false;
+    bool polish = false;          // FP64 copies of FP32 solves
+    std::vector<int> active;      // solve indices
+    DevSolve *dsolves = nullptr;  // device array indexed by solve
+    void *state = nullptr;        // base of the element buffer
+    int *dlist = nullptr;         // device list buffer (capacity B)
+    void *work = nullptr;         // plain: 2 buffers [cap][2][n][n]
+    size_t work_cap = 0;
+    void *tables = nullptr;       // fused: spectral tables
+};
+
+int fused_supported(int n, bool f32)
+{
+    return f32 ? (n == 32 || n == 64 || n == 128) : (n == 32 || n == 64);
+}
+
+template <typename T>
+int launch_fused(const Group &g, int nl, int model, double dt, int K, StepResults R,
+                 hipStream_t st)
+{
+    const DevSolve *S = g.dsolves;
+    T *u = (T *)g.state;
+    const T *tb = (const T *)g.tables;
+    static const char *names32[3] = {"k_fused_f32_n32", "k_fused_f32_n64", "k_fused_f32_n128"};
+    static const char *names64[3] = {"k_fused_f64_n32", "k_fused_f64_n64", "k_fused_f64_n128"};
+    const int ni = g.n == 32 ? 0 : (g.n == 64 ? 1 : 2);
+    const ProfMark pm = prof_begin(std::is_same<T, float>::value ? names32[ni] : names64[ni], st);
+    switch (g.n) {
+    case 32:
+        hipLaunchKernelGGL((k_fused<T, 32>), dim3(nl), dim3(64), 0, st, S, g.dlist, u, tb, model, dt, K, R);
+        break;
+    case 64:
+        hipLaunchKernelGGL((k_fused<T, 64>), dim3(nl), dim3(128), 0, st, S, g.dlist, u, tb, model, dt, K, R);
+        break;
+    default:
+        if constexpr (std::is_same<T, float>::value) {
+            hipLaunchKernelGGL((k_fused<T, 128>), dim3(nl), dim3(256), 0, st, S, g.dlist, u, tb, model, dt, K, R);
+        } else {
+            return set_error(CIL_EUNSUPPORTED, "fused FP64 stepper supports n = 32, 64");
+        }
+        break;
+    }
+    prof_end(pm, st);
+    return check_launch("k_fused");
+}
+
+template <typename T>
+int launch_plain(Group &g, int nl, int model, double dt, int K, StepResults R, hipStream_t st)
+{
+    PlainTables tb;
+    CIL_TRY(plain_tables<T>(g.n, &tb));
+    const int n = g.n, N2 = n * n;
+    T *A = (T *)g.work;
+    T *Bw = A + g.work_cap * 2 * N2;
+    const dim3 blk(256);
+    const dim3 grid1((N2 + 255) / 256, nl), grid2((2 * N2 + 255) / 256, nl);
+    T *u = (T *)g.state;
+    const ProfMark pm = prof_begin(std::is_same<T, float>::value ? "plain_step_f32" : "plain_step_f64", st);
+    for (int k = 0; k < K; ++k) {
+        const int check = (k == K - 1);
+        hipLaunchKernelGGL(k_plain_reaction<T>, grid1, blk, 0, st, g.dsolves, g.dlist, u, A, n, model, dt);
+        hipLaunchKernelGGL(k_plain_rows_fwd<T>, grid2, blk, 0, st, g.dlist, A, Bw, (const T *)tb.Ct, n);
+        hipLaunchKernelGGL(k_plain_cols_fwd_div<T>, grid2, blk, 0, st, g.dsolves, g.dlist, Bw, A,
+                           (const T *)tb.C, tb.lam, n, dt);
+        hipLaunchKernelGGL(k_plain_cols_inv<T>, grid2, blk, 0, st, g.dlist, A, Bw, (const T *)tb.Cw, n);
+        hipLaunchKernelGGL(k_plain_rows_inv<T>, grid2, blk, 0, st, g.dsolves, g.dlist, Bw, u,
+                           (const T *)tb.Cw, n, check, R);
+    }
+    prof_end(pm, st);
+    return check_launch("plain stepper");
+}
+
+}  // namespace
+
+// Device buffers owned by one simulate call (released at its end).
+struct CallBuffers {
+    std::vector<void *> ptrs;
+    ~CallBuffers()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    int alloc(void **p, size_t bytes)
+    {
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(CIL_ENOMEM, "device allocation of %zu bytes failed", bytes);
+        }
+        ptrs.push_back(*p);
+        return CIL_OK;
+    }
+};
+
+int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs, int B, void *state,
+                  const int64_t *offs, const cil_stepping *stp, cil_solve_report *reports,
+                  hipStream_t st)
+{
+    const bool f32 = (prec == CIL_FP32);
+    const double dt = stp->dt;
+    const int64_t max_steps = stp->max_steps;
+    const double tol = stp->tol;
+    const int check = stp->check_every;
+    const int floor_ulps = stp->fp32_floor_ulps > 0 ? stp->fp32_floor_ulps : 8;
+    const bool polish = f32 && stp->polish && tol > 0.0;
+    CallBuffers cb;
+
+    std::vector<DevSolve> hs(B);
+    std::vector<int64_t> elems(B);
+    int64_t total = 0;
+    for (int b = 0; b < B; ++b) {
+        const cil_problem &pr = probs[b];
+        DevSolve d{};
+        d.n = pr.n;
+        d.off = offs ? offs[b] : total;
+        const double h = pr.L / (double)(pr.n - 1);
+        d.inv_h2 = 1.0 / (h * h);
+        d.nu[0] = pr.nu[0];
+        d.nu[1] = pr.nu[1];
+        for (int k = 0; k < 4; ++k) d.p[k] = pr.p[k];
+        d.tab = 0;
+        hs[b] = d;
+        elems[b] = 2ll * pr.n * pr.n;
+        total += elems[b];
+    }
+
+    // groups by (n); the back-end per group
+    std::map<int, std::vector<int>> byn;
+    for (int b = 0; b < B; ++b) byn[hs[b].n].push_back(b);
+    std::vector<Group> groups;
+    for (auto &kv : byn) {
+        Group g;
+        g.n = kv.first;
+        g.f32 = f32;
+        const bool fs = fused_supported(g.n, f32);
+        if (stp->path == CIL_PATH_FUSED && !fs)
+            return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", g.n,
+                             f32 ? "FP32" : "FP64");
+        g.fused = fs && stp->path != CIL_PATH_PLAIN;
+        g.active = kv.second;
+        groups.push_back(g);
+    }
+
+    // spectral tables (fused groups): one per distinct (n, h, nu)
+    for (auto &g : groups) {
+        if (!g.fused) continue;
+        std::map<std::tuple<double, double, double>, int> uniq;
+        std::vector<TabSpec> specs;
+        for (int b : g.active) {
+            auto key = std::make_tuple(hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]);
+            auto it = uniq.find(key);
+            if (it == uniq.end()) {
+                it = uniq.emplace(key, (int)specs.size()).first;
+                specs.push_back(TabSpec{hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]});
+            }
+            hs[b].tab = it->second;
+        }
+        void *dspecs;
+        CIL_TRY(cb.alloc(&dspecs, sizeof(TabSpec) * specs.size()));
+        CIL_HIP(hipMemcpyAsync(dspecs, specs.data(), sizeof(TabSpec) * specs.size(),
+                               hipMemcpyHostToDevice, st));
+        const size_t tsz = (size_t)2 * g.n * g.n * specs.size();
+        CIL_TRY(cb.alloc(&g.tables, tsz * (f32 ? 4 : 8)));
+        dim3 grid((2 * g.n * g.n + 255) / 256, (unsigned)specs.size());
+        if (f32)
+            hipLaunchKernelGGL(k_make_tables<float>, grid, dim3(256), 0, st, (const TabSpec *)dspecs,
+                               (int)specs.size(), g.n, dt, (float *)g.tables);
+        else
+            hipLaunchKernelGGL(k_make_tables<double>, grid, dim3(256), 0, st, (const TabSpec *)dspecs,
+                               (int)specs.size(), g.n, dt, (double *)g.tables);
+        CIL_TRY(check_launch("k_make_tables"));
+    }
+
+    DevSolve *dsolves;
+    CIL_TRY(cb.alloc((void **)&dsolves, sizeof(DevSolve) * B));
+    CIL_HIP(hipMemcpyAsync(dsolves, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+    for (auto &g : groups) {
+        g.dsolves = dsolves;
+        g.state = state;
+        CIL_TRY(cb.alloc((void **)&g.dlist, sizeof(int) * g.active.size()));
+        if (!g.fused) {
+            g.work_cap = g.active.size();
+            CIL_TRY(cb.alloc(&g.work, (size_t)2 * g.work_cap * 2 * g.n * g.n * (f32 ? 4 : 8)));
+        }
+    }
+
+    StepResults R;
+    CIL_TRY(cb.alloc((void **)&R.resid, sizeof(unsigned long long) * B));
+    CIL_TRY(cb.alloc((void **)&R.maxabs, sizeof(unsigned long long) * B));
+    CIL_TRY(cb.alloc((void **)&R.bad, sizeof(int) * B));
+    std::vector<unsigned long long> h_resid(B), h_maxabs(B);
+    std::vector<int> h_bad(B);
+
+    // FP64 polish groups (created lazily, one per n)
+    std::map<int, Group> pol;
+    DevSolve *dsolves64 = nullptr;
+    double *state64 = nullptr;
+    std::vector<DevSolve> hs64;
+    if (polish) {
+        hs64 = hs;
+        int64_t t = 0;
+        for (int b = 0; b < B; ++b) {
+            hs64[b].off = t;
+            t += elems[b];
+        }
+        CIL_TRY(cb.alloc((void **)&state64, sizeof(double) * std::max<int64_t>(t, 1)));
+        CIL_TRY(cb.alloc((void **)&dsolves64, sizeof(DevSolve) * B));
+        // FP64 spectral tables are made per polish group below
+    }
+
+    std::vector<int64_t> steps(B, 0), steps64(B, 0);
+    std::vector<double> fres(B, 0.0);
+    std::vector<int> status(B, CIL_SOLVE_OK);
+    std::vector<char> in_polish(B, 0);
+
+    int64_t step = 0;
+    auto any_active = [&]() {
+        for (auto &g : groups)
+            if (!g.active.empty()) return true;
+        for (auto &kv : pol)
+            if (!kv.second.active.empty()) return true;
+        return false;
+    };
+
+    while (step < max_steps && any_active()) {
+        const int64_t next = std::min<int64_t>(max_steps, (step / check + 1) * check);
+        const int K = (int)(next - step);
+        std::vector<Group *> run;
+        for (auto &g : groups)
+            if (!g.active.empty()) run.push_back(&g);
+        for (auto &kv : pol)
+            if (!kv.second.active.empty()) run.push_back(&kv.second);
+        for (Group *g : run) {
+            const int nl = (int)g->active.size();
+            CIL_HIP(hipMemcpyAsync(g->dlist, g->active.data(), sizeof(int) * nl, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_clear_results, dim3((nl + 255) / 256), dim3(256), 0, st, g->dlist, nl, R);
+            const bool gf32 = g->f32 && !g->polish;
+            if (g->fused) {
+                if (gf32) CIL_TRY(launch_fused<float>(*g, nl, (int)model, dt, K, R, st));
+                else CIL_TRY(launch_fused<double>(*g, nl, (int)model, dt, K, R, st));
+            } else {
+                if (gf32) CIL_TRY(launch_plain<float>(*g, nl, (int)model, dt, K, R, st));
+                else CIL_TRY(launch_plain<double>(*g, nl, (int)model, dt, K, R, st));
+            }
+        }
+        CIL_HIP(hipMemcpyAsync(h_resid.data(), R.resid, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipMemcpyAsync(h_maxabs.data(), R.maxabs, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipMemcpyAsync(h_bad.data(), R.bad, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipStreamSynchronize(st));
+        step = next;
+
+        std::map<int, std::vector<int>> promote;   // n -> solves moving to FP64
+        for (Group *g : run) {
+            std::vector<int> keep;
+            for (int b : g->active) {
+                double dmax, amax;
+                std::memcpy(&dmax, &h_resid[b], 8);
+                std::memcpy(&amax, &h_maxabs[b], 8);
+                const double r = dmax / dt;
+                steps[b] = step;
+                if (g->polish) steps64[b] += K;
+                if (h_bad[b]) {
+                    status[b] = CIL_SOLVE_NONFINITE;
+                    fres[b] = NAN;
+                    continue;
+                }
+                fres[b] = r;
+                if (tol > 0.0 && r < tol) continue;                       // converged
+                if (g->f32 && !g->polish && tol > 0.0) {
+                    const double floor_r = floor_ulps * std::ldexp(1.0, -24) * amax / dt;
+                    if (r < floor_r) {
+                        if (polish) promote[g->n].push_back(b);
+                        else status[b] = CIL_SOLVE_FP32_FLOOR;
+                        continue;
+                    }
+                }
+                if (step >= max_steps) {
+                    if (tol > 0.0) status[b] = CIL_SOLVE_MAXSTEPS;
+                    continue;
+                }
+                keep.push_back(b);
+            }
+            g->active.swap(keep);
+        }
+        for (auto &kv : promote) {
+            const int n = kv.first;
+            auto it = pol.find(n);
+            if (it == pol.end()) {
+                Group g;
+                g.n = n;
+                g.f32 = true;
+                g.polish = true;
+                g.fused = fused_supported(n, false) && stp->path != CIL_PATH_PLAIN;
+                g.state = state64;
+                g.dsolves = dsolves64;
+                CIL_TRY(cb.alloc((void **)&g.dlist, sizeof(int) * B));
+                if (g.fused) {
+                    // FP64 tables for this n: one per distinct (h, nu) among all solves of side n
+                    std::map<std::tuple<double, double, double>, int> uniq;
+                    std::vector<TabSpec> specs;
+                    for (int b = 0; b < B; ++b) {
+                        if (hs[b].n != n) continue;
+                        auto key = std::make_tuple(hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]);
+                        auto jt = uniq.find(key);
+                        if (jt == uniq.end()) {
+                            jt = uniq.emplace(key, (int)specs.size()).first;
+                            specs.push_back(TabSpec{hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]});
+                        }
+                        hs64[b].tab = jt->second;
+                    }
+                    void *dspecs;
+                    CIL_TRY(cb.alloc(&dspecs, sizeof(TabSpec) * specs.size()));
+                    CIL_HIP(hipMemcpyAsync(dspecs, specs.data(), sizeof(TabSpec) * specs.size(),
+                                           hipMemcpyHostToDevice, st));
+                    CIL_TRY(cb.alloc(&g.tables, sizeof(double) * 2 * n * n * specs.size()));
+                    dim3 grid((2 * n * n + 255) / 256, (unsigned)specs.size());
+                    hipLaunchKernelGGL(k_make_tables<double>, grid, dim3(256), 0, st,
+                                       (const TabSpec *)dspecs, (int)specs.size(), n, dt,
+                                       (double *)g.tables);
+                    CIL_TRY(check_launch("k_make_tables"));
+                } else {
+                    g.work_cap = B;
+                    CIL_TRY(cb.alloc(&g.work, (size_t)2 * B * 2 * n * n * sizeof(double)));
+                }
+                CIL_HIP(hipMemcpyAsync(dsolves64, hs64.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+                it = pol.emplace(n, g).first;
+            }
+            Group &pg = it->second;
+            const int nl = (int)kv.second.size();
+            CIL_HIP(hipMemcpyAsync(pg.dlist, kv.second.data(), sizeof(int) * nl, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL((k_convert_solves<float, double>), dim3(16, nl), dim3(256), 0, st,
+                               (const DevSolve *)dsolves, (const DevSolve *)dsolves64, pg.dlist,
+                               (const float *)state, state64);
+            CIL_TRY(check_launch("k_convert_solves"));
+            for (int b : kv.second) {
+                pg.active.push_back(b);
+                in_polish[b] = 1;
+            }
+            CIL_HIP(hipStreamSynchronize(st));
+        }
+    }
+
+    // polished solves: FP64 result rounded back into the caller's FP32 state
+    if (polish) {
+        std::vector<int> done;
+        for (int b = 0; b < B; ++b)
+            if (in_polish[b]) done.push_back(b);
+        if (!done.empty()) {
+            int *dl;
+            CIL_TRY(cb.alloc((void **)&dl, sizeof(int) * done.size()));
+            CIL_HIP(hipMemcpyAsync(dl, done.data(), sizeof(int) * done.size(), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL((k_convert_solves<double, float>), dim3(16, (unsigned)done.size()), dim3(256),
+                               0, st, (const DevSolve *)dsolves64, (const DevSolve *)dsolves, dl,
+                               (const double *)state64, (float *)state);
+            CIL_TRY(check_launch("k_convert_solves"));
+        }
+    }
+    CIL_HIP(hipStreamSynchronize(st));
+
+    int rc = CIL_OK;
+    for (int b = 0; b < B; ++b) {
+        if (status[b] == CIL_SOLVE_NONFINITE) rc = CIL_ENONFINITE;
+        if (reports) {
+            reports[b].steps_taken = steps[b];
+            reports[b].steps_fp64 = f32 ? steps64[b] : 0;
+            reports[b].final_resid = fres[b];
+            reports[b].status = status[b];
+            reports[b].reserved = 0;
+        }
+    }
+    if (rc == CIL_ENONFINITE) set_error(rc, "a solve produced a non-finite value");
+    return rc;
+}
+
+}  // namespace cil

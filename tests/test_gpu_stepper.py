@@ -1,0 +1,233 @@
+"""GPU parity of the IMEX stepper against the FP64 oracle (through the C ABI).
+
+Error measure for trajectories: max |gpu - oracle| / max |oracle| over the
+whole state (FHN states sit near 0, so a pointwise relative error is
+meaningless).  Bars: 1e-10 for FP64 at a fixed step count, 1e-4 for FP32 at
+<= 500 steps (pattern selection amplifies rounding differences over longer
+horizons).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import cil_synth as cs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FHN = (0, (1.0, 10.0, 1.0), (0.05, 0.00028))
+GM = (1, (0.5, 1.0), (0.00025, 0.01))
+GMS = (2, (0.5, 1.0), (1.0, 100.0))
+BZ = (3, (4.5, 6.96), (0.0016, 0.0132))
+
+
+@pytest.fixture(scope="module")
+def cil():
+    import paper_2203_14742_amd as c
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return c
+
+
+def rel_err(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def run_both(cil, oracle_mod, model, p, nu, n, L, dt, steps, ics, prec, path, tol=0.0, check=None):
+    B = ics.shape[0]
+    check = check or steps
+    probs = cil.make_problems(n, L, nu, p, count=B)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    st = torch.tensor(ics, dtype=dtype, device="cuda")
+    rep = cil.cil_simulate_patterns(model, st, probs, dt, steps, tol=tol, check_every=check, path=path)
+    torch.cuda.synchronize()
+    out, osteps, ores, ostat = oracle_mod.imex_run(model, p, nu, n, L, dt, steps, tol, check,
+                                                   state=ics.astype(np.float64), nthreads=8)
+    return st.double().cpu().numpy(), rep, out, osteps, ores, ostat
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("case,n,L,dt,steps", [(FHN, 32, 1.0, 0.01, 300), (GM, 32, 1.0, 0.05, 200),
+                                               (GMS, 64, 120.0, 0.2, 150), (BZ, 64, 1.0, 0.05, 200)])
+def test_fp64_trajectory_parity(cil, oracle_mod, path, case, n, L, dt, steps):
+    model, p, nu = case
+    base = oracle_mod.homogeneous_state(model, p)
+    print("fp64 parity model=%d n=%d path=%d" % (model, n, path), flush=True)
+    ics = cs.initial_conditions(base, n, 3, seed=20 + model, law="additive_pos")
+    g, rep, o, _, ores, _ = run_both(cil, oracle_mod, model, p, nu, n, L, dt, steps, ics, "fp64", path)
+    assert rel_err(g, o) <= 1e-10
+    assert np.all(rep["steps_taken"] == steps) and np.all(rep["status"] == 0)
+    assert np.allclose(rep["final_resid"], ores, rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("case,n,L,dt,steps", [(FHN, 32, 1.0, 0.01, 300), (GMS, 64, 120.0, 0.2, 150),
+                                               (BZ, 128, 1.0, 0.05, 100), (FHN, 128, 1.0, 0.05, 100)])
+def test_fp32_trajectory_parity(cil, oracle_mod, path, case, n, L, dt, steps):
+    model, p, nu = case
+    base = oracle_mod.homogeneous_state(model, p)
+    print("fp32 parity model=%d n=%d path=%d" % (model, n, path), flush=True)
+    ics = cs.initial_conditions(base, n, 2, seed=30 + model, law="additive_pos").astype(np.float32)
+    g, rep, o, _, _, _ = run_both(cil, oracle_mod, model, p, nu, n, L, dt, steps,
+                                  ics.astype(np.float64), "fp32", path)
+    assert rel_err(g, o) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,k,l", [(32, 3, 8), (64, 0, 5), (128, 17, 2), (20, 4, 4)])
+def test_cosine_mode_decay_closed_form(cil, prec, n, k, l):
+    """P2 on the GPU: a cosine mode decays by exactly (1 + dt nu Lambda_kl)^-s."""
+    if prec == "fp64" and n == 128:
+        path = 1
+    else:
+        path = 0
+    L, dt, steps, nu = 1.0, 0.01, 40, (0.05, 0.002)
+    mode = cs.cosine_mode(n, k, l)
+    ics = np.stack([mode, -2.0 * mode])[None]
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    st = torch.tensor(ics, dtype=dtype, device="cuda")
+    cil.cil_simulate_patterns(4, st, cil.make_problems(n, L, nu, (0.0,)), dt, steps, path=path)
+    h = L / (n - 1)
+    lam = (4 / h ** 2) * (math.sin(math.pi * k / (2 * n)) ** 2 + math.sin(math.pi * l / (2 * n)) ** 2)
+    out = st.double().cpu().numpy()[0]
+    # rounding accumulates per step: a few transforms of length n per step
+    tol = (1e-14 if prec == "fp64" else 2e-7) * steps
+    for s, sign in ((0, 1.0), (1, -2.0)):
+        amp = (1 + dt * nu[s] * lam) ** (-steps)
+        assert np.abs(out[s] - sign * amp * mode).max() <= tol * abs(sign)
+
+
+@pytest.mark.parametrize("prec,path", [("fp64", 1), ("fp64", 2), ("fp32", 2)])
+def test_homogeneous_state_stays_fixed(cil, oracle_mod, prec, path):
+    model, p, nu = GMS
+    v0, w0 = oracle_mod.homogeneous_state(model, p)
+    n = 64
+    ics = np.empty((2, 2, n, n))
+    ics[:, 0] = v0
+    ics[:, 1] = w0
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    st = torch.tensor(ics, dtype=dtype, device="cuda")
+    cil.cil_simulate_patterns(model, st, cil.make_problems(n, 120.0, nu, p, count=2), 0.2, 50, path=path)
+    out = st.double().cpu().numpy()
+    # fixed up to rounding drift (dense length-64 cosine sums on the plain path)
+    tol = 2e-12 if prec == "fp64" else 1e-6
+    assert np.abs(out[:, 0] - v0).max() <= tol * v0 and np.abs(out[:, 1] - w0).max() <= tol * w0
+
+
+@pytest.mark.parametrize("prec,path", [("fp64", 1), ("fp64", 2), ("fp32", 1), ("fp32", 2)])
+def test_resume_is_bitwise(cil, prec, path):
+    model, p, nu = FHN
+    n = 32
+    ics = cs.initial_conditions((0.0, 0.0), n, 3, seed=5, law="additive_sym")
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    probs = cil.make_problems(n, 1.0, nu, p, count=3)
+    a = torch.tensor(ics, dtype=dtype, device="cuda")
+    cil.cil_simulate_patterns(model, a, probs, 0.01, 70, check_every=70, path=path)
+    b = torch.tensor(ics, dtype=dtype, device="cuda")
+    cil.cil_simulate_patterns(model, b, probs, 0.01, 30, check_every=30, path=path)
+    cil.cil_simulate_patterns(model, b, probs, 0.01, 40, check_every=40, path=path)
+    assert torch.equal(a, b)
+
+
+def test_check_every_does_not_change_the_trajectory(cil):
+    model, p, nu = BZ
+    n = 64
+    ics = cs.initial_conditions((4.5, 6.96 / 4.5), n, 2, seed=9)
+    probs = cil.make_problems(n, 1.0, nu, p, count=2)
+    a = torch.tensor(ics, dtype=torch.float32, device="cuda")
+    cil.cil_simulate_patterns(model, a, probs, 0.05, 60, check_every=60)
+    b = torch.tensor(ics, dtype=torch.float32, device="cuda")
+    cil.cil_simulate_patterns(model, b, probs, 0.05, 60, check_every=7)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_stop_rule_matches_oracle(cil, oracle_mod, path):
+    """tol > 0: a solve stops at the first multiple of check_every whose FP64
+    residual is below tol; FP64 steps_taken equal the oracle's."""
+    model, p, nu = GMS
+    n, L, dt = 32, 60.0, 0.2
+    base = oracle_mod.homogeneous_state(model, p)
+    ics = cs.initial_conditions(base, n, 4, seed=41, law="multiplicative")
+    tol, check = 1e-7, 10
+    g, rep, o, osteps, ores, ostat = run_both(cil, oracle_mod, model, p, nu, n, L, dt, 5000, ics, "fp64", path,
+                                              tol=tol, check=check)
+    assert np.all(ostat == 0) and np.all(rep["status"] == 0)
+    # steps agree unless the oracle residual sits within rounding of tol at a check
+    assert np.array_equal(rep["steps_taken"], osteps)
+    assert np.all(rep["final_resid"] < tol)
+    assert rel_err(g, o) <= 1e-9
+
+
+def test_fp32_polish_reaches_fp64_tolerance(cil, oracle_mod):
+    """FP32 stepping stalls at its floor; the polish phase continues in FP64 on
+    the GPU until the 1e-8 residual is met; the returned pattern is a
+    stationary solution of the stencil system to FP32 rounding."""
+    model, p, nu = GMS
+    n, L, dt = 64, 120.0, 0.2
+    base = oracle_mod.homogeneous_state(model, p)
+    ics = cs.initial_conditions(base, n, 4, seed=3, law="multiplicative")
+    st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+    rep = cil.cil_simulate_patterns(model, st, cil.make_problems(n, L, nu, p, count=4), dt, 20000, tol=1e-8,
+                                    check_every=25)
+    assert np.all(rep["status"] == 0), rep
+    assert np.all(rep["final_resid"] < 1e-8)
+    assert np.all(rep["steps_fp64"] > 0) and np.all(rep["steps_fp64"] < rep["steps_taken"])
+    out = st.double().cpu().numpy()
+    for b in range(4):
+        rhs = oracle_mod.mol_rhs(model, p, nu, n, L, out[b])
+        assert np.abs(rhs).max() < 1e-4                     # fp32 rounding of a stationary state
+    # without polish: FP32 floor status
+    st2 = torch.tensor(ics, dtype=torch.float32, device="cuda")
+    rep2 = cil.cil_simulate_patterns(model, st2, cil.make_problems(n, L, nu, p, count=4), dt, 20000, tol=1e-8,
+                                     check_every=25, polish=0)
+    assert np.all(rep2["status"] == cil.CIL_SOLVE_FP32_FLOOR)
+
+
+def test_uneven_batch_matches_oracle(cil, oracle_mod):
+    """Solves of different grid sides and parameters in one call."""
+    model, p0, nu0 = BZ
+    ns = [32, 64, 17, 128, 32]
+    params = cs.relative_draws(p0, len(ns), 0.05, seed=4)
+    nus = cs.relative_draws(nu0, len(ns), 0.05, seed=5)
+    ics = []
+    for b, n in enumerate(ns):
+        base = oracle_mod.homogeneous_state(model, params[b])
+        ics.append(cs.initial_conditions(base, n, 1, seed=50 + b)[0])
+    flat = np.concatenate([x.reshape(-1) for x in ics])
+    probs = cil.make_problems(ns, 1.0, nus, params)
+    st = torch.tensor(flat, dtype=torch.float64, device="cuda")
+    rep = cil.cil_simulate_patterns(model, st, probs, 0.05, 120, check_every=40)
+    outs, osteps, _, _ = oracle_mod.imex_run(model, params, nus, ns, 1.0, 0.05, 120, 0.0, 40, state=ics)
+    g = st.cpu().numpy()
+    off = 0
+    for b, n in enumerate(ns):
+        gb = g[off: off + 2 * n * n].reshape(2, n, n)
+        off += 2 * n * n
+        assert rel_err(gb, outs[b]) <= 1e-10, (b, n)
+    assert np.all(rep["steps_taken"] == 120)
+
+
+def test_nonfinite_solve_is_reported(cil):
+    model, p, nu = GMS
+    n = 32
+    ics = cs.initial_conditions((1.5, 2.25), n, 3, seed=1, law="multiplicative")
+    ics[1, 1, 5, 5] = np.nan
+    st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+    rep = cil.cil_simulate_patterns(model, st, cil.make_problems(n, 60.0, nu, p, count=3), 0.2, 20,
+                                    check_every=10, raise_on_nonfinite=False)
+    assert list(rep["status"]) == [0, cil.CIL_SOLVE_NONFINITE, 0]
+    assert rep["steps_taken"][1] == 10 and np.isnan(rep["final_resid"][1])
+    with pytest.raises(cil.CilError) as e:
+        st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+        cil.cil_simulate_patterns(model, st, cil.make_problems(n, 60.0, nu, p, count=3), 0.2, 20, check_every=10)
+    assert e.value.code == cil.CIL_ENONFINITE
+
+
+def test_fused_unsupported_size_is_an_error(cil):
+    st = torch.zeros((1, 2, 20, 20), dtype=torch.float64, device="cuda")
+    with pytest.raises(cil.CilError) as e:
+        cil.cil_simulate_patterns(0, st, cil.make_problems(20, 1.0, (0.1, 0.1), (1, 1, 1)), 0.01, 5, path=2)
+    assert e.value.code == cil.CIL_EUNSUPPORTED
