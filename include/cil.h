@@ -181,6 +181,14 @@ int cil_canonical_d2(const void *setA, int64_t nA, const void *setB, int64_t nB,
                      cil_precision prec, const int64_t *ia, const int64_t *jb, int64_t npairs,
                      double *d2, void *hip_stream);
 
+/* The fast-pass approximation of every squared distance and its rigorous
+ * error bound: |d2[i*nB+j] - D(A_i, B_j)| <= eps[i*nB+j].  FP64 sets: direct
+ * FP64 sums; FP32 sets: split-bf16x3 Gram on the matrix cores.  These are the
+ * values the counting calls classify before re-checking pairs near a radius.
+ * d2, eps device double[nA][nB].  For diagnostics and tests. */
+int cil_approx_d2(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                  cil_precision prec, double *d2, double *eps, void *hip_stream);
+
 /* Radii ladder from a squared-distance range (Sec. 2.1, Sec. 3.2):
  * R_0 = sqrt(d2max), R_M = sqrt(d2min); law 0: R_m = R_0 b^-m with
  * b = (R_0/R_M)^(1/M); law 1: R_m = R_0 - m (R_0 - R_M)/M; m = 1..M.

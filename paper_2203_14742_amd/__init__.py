@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
         L.cil_distance_range.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, vp, vp, vp]
         L.cil_canonical_d2.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, vp, i64, vp, vp]
         L.cil_radii.argtypes = [dbl, dbl, i32, i32, vp]
+        L.cil_approx_d2.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, vp, vp]
+        L.cil_approx_d2.restype = ctypes.c_int
         L.cil_last_distance_stats.argtypes = [vp, vp, vp]
         L.cil_bootstrap_features.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp]
         L.cil_gaussian_loglik.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
@@ -240,6 +242,17 @@ def cil_canonical_d2(A, B, ia, jb):
     _check(lib().cil_canonical_d2(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1], _prec(A2),
                                   _dev(ia, "ia"), _dev(jb, "jb"), ia.numel(), _dev(out, "d2"), _stream(A2)))
     return out
+
+
+def cil_approx_d2(A, B):
+    """(fast-pass squared distances, their error bounds) as [nA, nB] float64 device tensors."""
+    import torch
+    A2, B2 = _sets(A, B)
+    d2 = torch.empty((A2.shape[0], B2.shape[0]), dtype=torch.float64, device=A2.device)
+    eps = torch.empty_like(d2)
+    _check(lib().cil_approx_d2(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1], _prec(A2),
+                               _dev(d2, "d2"), _dev(eps, "eps"), _stream(A2)))
+    return d2, eps
 
 
 def cil_radii(d2min: float, d2max: float, M: int, law: int = 0):

@@ -27,6 +27,8 @@ int distance_range_impl(const T *, long long, const T *, long long, long long, i
 template <typename T>
 int canonical_pairs_impl(const T *, long long, const T *, long long, long long, const long long *,
                          const long long *, long long, double *, hipStream_t);
+template <typename T>
+int approx_d2_impl(const T *, long long, const T *, long long, long long, double *, double *, hipStream_t);
 int bootstrap_impl(const uint8_t *, long long, long long, int, const int *, int, const int *, int, int,
                    long long *, double *, hipStream_t);
 int loglik_impl(const double *, int, int, int, const double *, double *, double *, int *, int *,
@@ -386,6 +388,20 @@ int cil_canonical_d2(const void *setA, int64_t nA, const void *setB, int64_t nB,
                                             (const long long *)ia, (const long long *)jb, npairs, d2, st);
     return canonical_pairs_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, (const long long *)ia,
                                        (const long long *)jb, npairs, d2, st);
+}
+
+int cil_approx_d2(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                  double *d2, double *eps, void *hip_stream)
+{
+    API_BEGIN();
+    CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
+    if (nA * nB == 0) return CIL_OK;
+    if (!d2 || !eps) return set_error(CIL_EINVAL, "null output");
+    CIL_TRY(check_device());
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == CIL_FP64)
+        return approx_d2_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim, d2, eps, st);
+    return approx_d2_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, d2, eps, st);
 }
 
 int cil_radii(double d2min, double d2max, int32_t M, int32_t law, double *radii)

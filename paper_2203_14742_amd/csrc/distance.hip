@@ -6,13 +6,16 @@
 //   D   = RN64(sum_k d_k^2)   -- the exact sum, rounded once.
 // Counting rule: a pair lies under radius R_m when D < fl(R_m * R_m).
 //
-// Fast pass (this file, k_dist_tile): D~ = sum_k d_k^2 in FP64, one pair per
-// accumulator, summed sequentially with FMA.  All terms are non-negative, so
-// |D~ - sum| <= gamma_d * D~ with gamma_d = d u / (1 - d u), u = 2^-53; with
-// the final rounding and a margin, |D~ - D| <= eps_rel * D~, eps_rel =
-// (d + 4) 2^-53 * 1.01.  A pair whose D~ is within that band of any
-// threshold is recomputed canonically (k_canonical), all others are binned
-// from D~ directly: every count is exact.
+// Pipeline for every pair statistic:
+//   1. fast pass -> FP64 partials P[split][i][j] over K ranges:
+//      FP64 sets: direct differences, P = sum d_k^2 over the range (k_dist_partial);
+//      FP32 sets: split-bf16x3 Gram on the matrix cores (gram.hip).
+//   2. k_classify sums the partials in a fixed order into D~ and its rigorous
+//      bound eps (direct: all terms are non-negative, so any summation order
+//      is within gamma_{d+S} D~ of the exact sum, and eps = (d + S + 4)
+//      2^-53 1.01 D~; Gram: the bound derived in gram.hip), then bins the pair
+//      or, when |D~ - fl(R_m^2)| <= eps for some m, puts it on a re-check list.
+//   3. k_canonical recomputes the listed pairs canonically; every count is exact.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,59 +32,51 @@
 
 namespace cil {
 
-constexpr int TILE = 64;       // pairs per tile side
+// gram.hip
+struct GramWork {
+    __bf16 *Ah, *Al, *Bh, *Bl;
+    double *na, *nb;
+    float *c;
+    long long dimP;
+};
+int gram_prepare(const float *, long long, const float *, long long, long long, GramWork *, hipStream_t);
+long long gram_splits(long long, long long, long long);
+int gram_partials(const GramWork &, long long, long long, long long, long long, double *, hipStream_t);
+
+constexpr int TILE = 64;       // pairs per tile side (direct pass)
 constexpr int KC = 16;         // k-chunk staged in LDS
 constexpr int MAX_M = 255;
-
-struct BinOut {
-    const double *thr;          // device [M]: fl(R_m^2), strictly decreasing
-    int M;
-    double eps_rel;             // band half-width relative to max(D~, thr)
-    unsigned long long *hist;   // device [M+1]: pairs per bin value (binned pairs only)
-    uint8_t *bins;              // device [nA][nB] or null
-    int2 *recheck;              // device list of pairs to recompute
-    unsigned long long *nrecheck;
-    long long recheck_cap;
-    double *dmat;               // device [nA][nB] of D~ or null (range mode)
-    int exclude_diag;
-    unsigned long long *dmin_bits, *dmax_bits;   // range mode (non-negative doubles)
-};
 
 __device__ __forceinline__ double ld(const double *p) { return *p; }
 __device__ __forceinline__ double ld(const float *p) { return (double)*p; }
 
-// One 64 x 64 tile of pairs per block of 256 threads; thread (ty, tx) owns
-// rows ty + 16 i and columns tx + 16 j, i, j < 4.
-template <typename T, bool RANGE>
-__global__ __launch_bounds__(256) void k_dist_tile(const T *A, long long nA, const T *B, long long nB,
-                                                   long long dim, BinOut o)
+// ------------------------------------------------------------ direct pass
+// One 64 x 64 tile of pairs and one K range per block of 256 threads; thread
+// (ty, tx) owns rows ty + 16 i and columns tx + 16 j, i, j < 4.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dist_partial(const T *A, long long nA, const T *B, long long nB,
+                                                      long long dim, long long ksplit, double *P)
 {
     __shared__ double sA[TILE][KC + 1];
     __shared__ double sB[TILE][KC + 1];
-    __shared__ unsigned int hist[MAX_M + 1];
-    __shared__ double sthr[MAX_M];
-
     const int tid = threadIdx.x;
     const int tx = tid % 16, ty = tid / 16;
     const long long i0 = (long long)blockIdx.y * TILE, j0 = (long long)blockIdx.x * TILE;
-    if (!RANGE) {
-        for (int m = tid; m <= o.M; m += 256) hist[m] = 0;
-        for (int m = tid; m < o.M; m += 256) sthr[m] = o.thr[m];
-    }
+    const long long kb = (long long)blockIdx.z * ksplit;
+    const long long ke = kb + ksplit < dim ? kb + ksplit : dim;
     double acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-
-    for (long long k0 = 0; k0 < dim; k0 += KC) {
+    for (long long k0 = kb; k0 < ke; k0 += KC) {
         __syncthreads();
         for (int e = tid; e < TILE * KC; e += 256) {
             const int r = e / KC, kk = e % KC;
             const long long k = k0 + kk;
             const long long ia = i0 + r, jb = j0 + r;
-            sA[r][kk] = (ia < nA && k < dim) ? ld(A + ia * dim + k) : 0.0;
-            sB[r][kk] = (jb < nB && k < dim) ? ld(B + jb * dim + k) : 0.0;
+            sA[r][kk] = (ia < nA && k < ke) ? ld(A + ia * dim + k) : 0.0;
+            sB[r][kk] = (jb < nB && k < ke) ? ld(B + jb * dim + k) : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -100,53 +95,121 @@ __global__ __launch_bounds__(256) void k_dist_tile(const T *A, long long nA, con
                 }
         }
     }
-    __syncthreads();
-
-    if (RANGE) {
-        double mn = INFINITY, mx = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const long long ia = i0 + ty + 16 * i, jb = j0 + tx + 16 * j;
-                if (ia >= nA || jb >= nB) continue;
-                if (o.exclude_diag && ia == jb) continue;
-                const double D = acc[i][j];
-                o.dmat[ia * nB + jb] = D;
-                mn = fmin(mn, D);
-                mx = fmax(mx, D);
-            }
-        if (mn < INFINITY) atomicMin(o.dmin_bits, (unsigned long long)__double_as_longlong(mn));
-        atomicMax(o.dmax_bits, (unsigned long long)__double_as_longlong(mx));
-        return;
-    }
-
+    double *Ps = P + (long long)blockIdx.z * nA * nB;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const long long ia = i0 + ty + 16 * i, jb = j0 + tx + 16 * j;
-            if (ia >= nA || jb >= nB) continue;
-            const double D = acc[i][j];
+            if (ia < nA && jb < nB) Ps[ia * nB + jb] = acc[i][j];
+        }
+}
+
+// ---------------------------------------------------------------- classify
+enum { MODE_BINS = 0, MODE_RANGE1 = 1, MODE_RANGE2 = 2, MODE_DUMP = 3 };
+
+struct ClassifyArgs {
+    const double *P;            // partials [S][nA][nB]
+    int S;
+    int gram;                   // 0: direct partials of D, 1: Gram partials
+    const double *na, *nb;      // Gram: |a^|^2, |b^|^2
+    double eps_rel;             // direct
+    double eG;                  // Gram: eG / (|a'||b'|)
+    double e1;                  // Gram: split error per element
+    int mode;
+    int exclude_diag;
+    const double *thr;          // bins: [M]
+    int M;
+    unsigned long long *hist;   // bins: [M+1]
+    uint8_t *bins;              // bins: [nA][nB] or null
+    int2 *list;                 // re-check / candidate list
+    unsigned long long *nlist;
+    long long cap;
+    unsigned long long *minmax; // range: [min(D~+eps) bits, max(D~-eps) bits]
+    double *dump_d, *dump_eps;  // dump
+};
+
+__device__ __forceinline__ void approx_pair(const ClassifyArgs &c, long long i, long long j, long long nA,
+                                            long long nB, double &D, double &eps)
+{
+    double s = 0.0;
+    for (int k = 0; k < c.S; ++k) s += c.P[(long long)k * nA * nB + i * nB + j];
+    if (!c.gram) {
+        D = s;
+        eps = c.eps_rel * s;
+        return;
+    }
+    const double na = c.na[i], nb = c.nb[j];
+    D = na + nb - 2.0 * s;
+    const double ra = sqrt(na), rb = sqrt(nb);
+    const double Sg = ra + rb;
+    const double eG = c.eG * ra * rb;
+    const double Dp = D > 0.0 ? D : 0.0;
+    const double u = 0x1p-53;
+    const double bound = 2.0 * eG + 2.0 * c.e1 * Sg * (sqrt(Dp + 2.0 * eG) + c.e1 * Sg) + c.e1 * c.e1 * Sg * Sg +
+                         8.0 * u * (na + nb + Dp) + u * Dp;
+    eps = 2.0 * bound;
+}
+
+__global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, long long nB)
+{
+    __shared__ unsigned int hist[MAX_M + 1];
+    __shared__ double sthr[MAX_M];
+    const int tid = threadIdx.x;
+    if (c.mode == MODE_BINS) {
+        for (int m = tid; m <= c.M; m += 256) hist[m] = 0;
+        for (int m = tid; m < c.M; m += 256) sthr[m] = c.thr[m];
+        __syncthreads();
+    }
+    const long long e = (long long)blockIdx.x * 256 + tid;
+    const bool live = e < nA * nB;
+    const long long i = live ? e / nB : 0, j = live ? e % nB : 0;
+    const bool skip = !live || (c.exclude_diag && i == j);
+    double D = 0.0, eps = 0.0;
+    if (!skip) approx_pair(c, i, j, nA, nB, D, eps);
+    const bool finite = isfinite(D) && isfinite(eps);
+    if (c.mode == MODE_BINS) {
+        if (!skip) {
             int bin = 0;
-            bool amb = false;
-            for (int m = 0; m < o.M; ++m) {
+            bool amb = !finite;
+            for (int m = 0; m < c.M; ++m) {
                 const double t = sthr[m];
-                if (fabs(D - t) <= o.eps_rel * fmax(D, t)) amb = true;
+                if (fabs(D - t) <= eps) amb = true;
                 bin += (D < t);
             }
-            if (!isfinite(D)) amb = true;
             if (amb) {
-                const unsigned long long slot = atomicAdd(o.nrecheck, 1ull);
-                if ((long long)slot < o.recheck_cap) o.recheck[slot] = make_int2((int)ia, (int)jb);
+                const unsigned long long slot = atomicAdd(c.nlist, 1ull);
+                if ((long long)slot < c.cap) c.list[slot] = make_int2((int)i, (int)j);
             } else {
                 atomicAdd(&hist[bin], 1u);
-                if (o.bins) o.bins[ia * nB + jb] = (uint8_t)bin;
+                if (c.bins) c.bins[i * nB + j] = (uint8_t)bin;
             }
         }
-    __syncthreads();
-    for (int m = tid; m <= o.M; m += 256)
-        if (hist[m]) atomicAdd(&o.hist[m], (unsigned long long)hist[m]);
+        __syncthreads();
+        for (int m = tid; m <= c.M; m += 256)
+            if (hist[m]) atomicAdd(&c.hist[m], (unsigned long long)hist[m]);
+    } else if (c.mode == MODE_RANGE1) {
+        if (!skip) {
+            if (!finite) {
+                atomicOr(c.nlist, 1ull << 63);   // flag: non-finite distance
+            } else {
+                atomicMin(&c.minmax[0], (unsigned long long)__double_as_longlong(D + eps));
+                atomicMax(&c.minmax[1], (unsigned long long)__double_as_longlong(fmax(D - eps, 0.0)));
+            }
+        }
+    } else if (c.mode == MODE_RANGE2) {
+        if (!skip) {
+            const double mnub = __longlong_as_double((long long)c.minmax[0]);
+            const double mxlb = __longlong_as_double((long long)c.minmax[1]);
+            if (D - eps <= mnub || D + eps >= mxlb) {
+                const unsigned long long slot = atomicAdd(c.nlist, 1ull);
+                if ((long long)slot < c.cap) c.list[slot] = make_int2((int)i, (int)j);
+            }
+        }
+    } else if (live) {
+        c.dump_d[e] = D;
+        c.dump_eps[e] = eps;
+    }
 }
 
 // ---------------------------------------------------------------- canonical
@@ -278,8 +341,10 @@ __global__ __launch_bounds__(256) void k_canonical(const T *A, const T *B, long 
         two_sum(hi, lo, R, e);
         const double delta = (double)(dim + 64) * 0x1p-100;   // relative error bound
         int ex;
-        (void)frexp(R, &ex);                                 // R in [2^(ex-1), 2^ex)
-        const double half = ldexp(1.0, ex - 1 - 54);         // smallest half-spacing near R
+        const double frac = frexp(R, &ex);                   // R = frac 2^ex, frac in [0.5, 1)
+        // rounding boundaries of R: R +- half an ulp (ulp = 2^(ex-53)), except
+        // below a power of two, where the spacing halves
+        const double half = (e < 0.0 && frac == 0.5) ? ldexp(1.0, ex - 55) : ldexp(1.0, ex - 54);
         const bool certain = isfinite(R) && (fabs(e) + delta * R < half || R == 0.0);
         D = R;
         if (!certain || o.force_exact) {
@@ -296,24 +361,6 @@ __global__ __launch_bounds__(256) void k_canonical(const T *A, const T *B, long 
     }
 }
 
-// ---------------------------------------------------------------- range fix
-// Candidates for the canonical extremes: pairs whose D~ lies within the band
-// of the fast-pass minimum or maximum.
-__global__ void k_range_candidates(const double *dmat, long long nA, long long nB, double lo_thr,
-                                   double hi_thr, int exclude_diag, int2 *out,
-                                   unsigned long long *count, long long cap)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nA * nB) return;
-    const long long i = e / nB, j = e % nB;
-    if (exclude_diag && i == j) return;
-    const double D = dmat[e];
-    if (D <= lo_thr || D >= hi_thr || !isfinite(D)) {
-        const unsigned long long s = atomicAdd(count, 1ull);
-        if ((long long)s < cap) out[s] = make_int2((int)i, (int)j);
-    }
-}
-
 // ======================================================================
 // Host side.
 
@@ -324,32 +371,27 @@ int g_force_exact = 0;
 struct DistScratch {
     double *thr = nullptr;
     unsigned long long *hist = nullptr;
-    unsigned long long *nrecheck = nullptr;
+    unsigned long long *nlist = nullptr;
     unsigned long long *nexact = nullptr;
     unsigned long long *minmax = nullptr;
-    int2 *recheck = nullptr;
+    int2 *list = nullptr;
     long long cap = 0;
 };
 
-int scratch(long long npairs_cap, DistScratch *s)
+int scratch(long long cap, DistScratch *s)
 {
     void *p;
     CIL_TRY(ws_get(WS_DIST_MISC, 4096 + sizeof(double) * 512, &p));
     char *c = (char *)p;
     s->thr = (double *)c;                                   // 256 doubles
     s->hist = (unsigned long long *)(c + 2048);             // 256 counters
-    s->nrecheck = (unsigned long long *)(c + 4096);
-    s->nexact = s->nrecheck + 1;
-    s->minmax = s->nrecheck + 2;
-    CIL_TRY(ws_get(WS_DIST_RECHECK, sizeof(int2) * (size_t)std::max<long long>(npairs_cap, 1), &p));
-    s->recheck = (int2 *)p;
-    s->cap = npairs_cap;
+    s->nlist = (unsigned long long *)(c + 4096);
+    s->nexact = s->nlist + 1;
+    s->minmax = s->nlist + 2;
+    CIL_TRY(ws_get(WS_DIST_RECHECK, sizeof(int2) * (size_t)std::max<long long>(cap, 1), &p));
+    s->list = (int2 *)p;
+    s->cap = cap;
     return CIL_OK;
-}
-
-dim3 tile_grid(long long nA, long long nB)
-{
-    return dim3((unsigned)((nB + TILE - 1) / TILE), (unsigned)((nA + TILE - 1) / TILE));
 }
 
 template <typename T>
@@ -361,6 +403,67 @@ int run_canonical(const T *A, const T *B, long long dim, CanonOut &co, long long
     hipLaunchKernelGGL(k_canonical<T>, dim3((unsigned)blocks), dim3(256), 0, st, A, B, dim, co);
     prof_end(pm, st);
     return check_launch("k_canonical");
+}
+
+struct Approx {
+    ClassifyArgs c{};
+};
+
+// FP64 sets: direct differences, split over K so the grid fills the chip.
+int approx_pass(const double *A, long long nA, const double *B, long long nB, long long dim, Approx *ap,
+                hipStream_t st)
+{
+    const long long tiles = ((nA + TILE - 1) / TILE) * ((nB + TILE - 1) / TILE);
+    long long S = 1;
+    while (tiles * S < 1024 && dim / (2 * S) >= 256) S *= 2;
+    const long long ks = std::max<long long>(KC, (dim / S + KC - 1) / KC * KC);
+    S = std::max<long long>(1, (dim + ks - 1) / ks);
+    void *p;
+    CIL_TRY(ws_get(WS_DIST_SAMPLE, sizeof(double) * (size_t)std::max<long long>(S * nA * nB, 1), &p));
+    ap->c.P = (const double *)p;
+    ap->c.S = (int)S;
+    ap->c.gram = 0;
+    ap->c.eps_rel = (double)(dim + S + 4) * 0x1p-53 * 1.01;
+    if (nA * nB > 0) {
+        dim3 grid((unsigned)((nB + TILE - 1) / TILE), (unsigned)((nA + TILE - 1) / TILE), (unsigned)S);
+        const ProfMark pm = prof_begin("k_dist_partial", st);
+        hipLaunchKernelGGL(k_dist_partial<double>, grid, dim3(256), 0, st, A, nA, B, nB, dim, ks, (double *)p);
+        prof_end(pm, st);
+        CIL_TRY(check_launch("k_dist_partial"));
+    }
+    return CIL_OK;
+}
+
+// FP32 sets: split-bf16x3 Gram on the matrix cores.
+int approx_pass(const float *A, long long nA, const float *B, long long nB, long long dim, Approx *ap,
+                hipStream_t st)
+{
+    GramWork g;
+    CIL_TRY(gram_prepare(A, nA, B, nB, dim, &g, st));
+    long long S = gram_splits(nA, nB, g.dimP);
+    const long long ks = std::max<long long>(64, (g.dimP / S + 63) / 64 * 64);
+    S = std::max<long long>(1, (g.dimP + ks - 1) / ks);
+    void *p;
+    CIL_TRY(ws_get(WS_DIST_SAMPLE, sizeof(double) * (size_t)std::max<long long>(S * nA * nB, 1), &p));
+    ap->c.P = (const double *)p;
+    ap->c.S = (int)S;
+    ap->c.gram = 1;
+    ap->c.na = g.na;
+    ap->c.nb = g.nb;
+    ap->c.eG = 3.0 * 256.0 * 0x1p-24 + 0x1p-18 + 0x1p-40;
+    ap->c.e1 = 0x1p-24 + 0x1p-18;
+    if (nA * nB > 0) CIL_TRY(gram_partials(g, nA, nB, S, ks, (double *)p, st));
+    return CIL_OK;
+}
+
+int classify(ClassifyArgs &c, long long nA, long long nB, hipStream_t st)
+{
+    const long long n = nA * nB;
+    if (n <= 0) return CIL_OK;
+    const ProfMark pm = prof_begin("k_classify", st);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, nA, nB);
+    prof_end(pm, st);
+    return check_launch("k_classify");
 }
 }  // namespace
 
@@ -376,9 +479,8 @@ int last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact)
 
 // Bins / counts for all pairs.  hist_host[M+1] gets the per-bin pair counts.
 template <typename T>
-int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim,
-                   const double *radii, int M, uint8_t *bins, std::vector<unsigned long long> &hist_host,
-                   hipStream_t st)
+int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim, const double *radii, int M,
+                   uint8_t *bins, std::vector<unsigned long long> &hist_host, hipStream_t st)
 {
     const long long npairs = nA * nB;
     DistScratch s;
@@ -387,30 +489,26 @@ int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long
     for (int m = 0; m < M; ++m) thr[m] = radii[m] * radii[m];
     CIL_HIP(hipMemcpyAsync(s.thr, thr.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
     CIL_TRY(fill_zero(s.hist, sizeof(unsigned long long) * (M + 1), st));
-    CIL_TRY(fill_zero(s.nrecheck, sizeof(unsigned long long) * 2, st));
-
-    BinOut o{};
-    o.thr = s.thr;
-    o.M = M;
-    o.eps_rel = (double)(dim + 4) * 0x1p-53 * 1.01;
-    o.hist = s.hist;
-    o.bins = bins;
-    o.recheck = s.recheck;
-    o.nrecheck = s.nrecheck;
-    o.recheck_cap = s.cap;
-    if (npairs > 0) {
-        const ProfMark pm = prof_begin("k_dist_tile", st);
-        hipLaunchKernelGGL((k_dist_tile<T, false>), tile_grid(nA, nB), dim3(256), 0, st, A, nA, B, nB, dim, o);
-        prof_end(pm, st);
-        CIL_TRY(check_launch("k_dist_tile"));
-    }
+    CIL_TRY(fill_zero(s.nlist, sizeof(unsigned long long) * 2, st));
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    ClassifyArgs &c = ap.c;
+    c.mode = MODE_BINS;
+    c.thr = s.thr;
+    c.M = M;
+    c.hist = s.hist;
+    c.bins = bins;
+    c.list = s.list;
+    c.nlist = s.nlist;
+    c.cap = s.cap;
+    CIL_TRY(classify(c, nA, nB, st));
     unsigned long long nre = 0;
-    CIL_HIP(hipMemcpyAsync(&nre, s.nrecheck, sizeof(nre), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(&nre, s.nlist, sizeof(nre), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     if ((long long)nre > s.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
     CanonOut co{};
-    co.pairs = s.recheck;
-    co.npairs_dev = s.nrecheck;
+    co.pairs = s.list;
+    co.npairs_dev = s.nlist;
     co.cap = s.cap;
     co.thr = s.thr;
     co.M = M;
@@ -422,8 +520,7 @@ int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long
     CIL_TRY(run_canonical(A, B, dim, co, (long long)nre, st));
     hist_host.assign(M + 1, 0);
     unsigned long long nex = 0;
-    CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1),
-                           hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipMemcpyAsync(&nex, s.nexact, sizeof(nex), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     t_pairs = npairs;
@@ -432,59 +529,48 @@ int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long
     return CIL_OK;
 }
 
-template int pair_bins_impl<double>(const double *, long long, const double *, long long, long long,
-                                    const double *, int, uint8_t *, std::vector<unsigned long long> &,
-                                    hipStream_t);
-template int pair_bins_impl<float>(const float *, long long, const float *, long long, long long,
-                                   const double *, int, uint8_t *, std::vector<unsigned long long> &,
-                                   hipStream_t);
+template int pair_bins_impl<double>(const double *, long long, const double *, long long, long long, const double *,
+                                    int, uint8_t *, std::vector<unsigned long long> &, hipStream_t);
+template int pair_bins_impl<float>(const float *, long long, const float *, long long, long long, const double *, int,
+                                   uint8_t *, std::vector<unsigned long long> &, hipStream_t);
 
+// Canonical extremes: pass 1 bounds them by min(D~ + eps) and max(D~ - eps);
+// pass 2 lists every pair whose interval reaches those bounds; the listed
+// pairs are recomputed canonically and the extremes taken over them.
 template <typename T>
-int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int excl,
-                        double *dmin, double *dmax, hipStream_t st)
+int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int excl, double *dmin,
+                        double *dmax, hipStream_t st)
 {
     const long long npairs = nA * nB;
     DistScratch s;
     CIL_TRY(scratch(npairs, &s));
-    void *p;
-    CIL_TRY(ws_get(WS_DIST_SAMPLE, sizeof(double) * (size_t)std::max<long long>(npairs, 1), &p));
-    double *dmat = (double *)p;
-    unsigned long long init[2] = {(unsigned long long)0x7ff0000000000000ull, 0ull};   // +inf, 0
-    CIL_HIP(hipMemcpyAsync(s.minmax, init, sizeof(init), hipMemcpyHostToDevice, st));
-    CIL_TRY(fill_zero(s.nrecheck, sizeof(unsigned long long) * 2, st));
-    BinOut o{};
-    o.dmat = dmat;
-    o.exclude_diag = excl;
-    o.dmin_bits = s.minmax;
-    o.dmax_bits = s.minmax + 1;
-    const ProfMark pm = prof_begin("k_dist_tile_range", st);
-    hipLaunchKernelGGL((k_dist_tile<T, true>), tile_grid(nA, nB), dim3(256), 0, st, A, nA, B, nB, dim, o);
-    prof_end(pm, st);
-    CIL_TRY(check_launch("k_dist_tile range"));
-    unsigned long long mm[2];
-    CIL_HIP(hipMemcpyAsync(mm, s.minmax, sizeof(mm), hipMemcpyDeviceToHost, st));
+    unsigned long long init[4] = {0ull, 0ull, (unsigned long long)0x7ff0000000000000ull, 0ull};  // nlist, nexact, +inf, 0
+    CIL_HIP(hipMemcpyAsync(s.nlist, init, sizeof(init), hipMemcpyHostToDevice, st));
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    ClassifyArgs &c = ap.c;
+    c.exclude_diag = excl;
+    c.minmax = s.minmax;
+    c.list = s.list;
+    c.nlist = s.nlist;
+    c.cap = s.cap;
+    c.mode = MODE_RANGE1;
+    CIL_TRY(classify(c, nA, nB, st));
+    unsigned long long flag = 0;
+    CIL_HIP(hipMemcpyAsync(&flag, s.nlist, sizeof(flag), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
-    double fmin_, fmax_;
-    memcpy(&fmin_, &mm[0], 8);
-    memcpy(&fmax_, &mm[1], 8);
-    if (!std::isfinite(fmin_) || !std::isfinite(fmax_))
-        return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
-    const double eps = (double)(dim + 4) * 0x1p-53 * 1.01;
-    const double lo_thr = fmin_ * (1.0 + 2.0 * eps) + 1e-300;
-    const double hi_thr = fmax_ * (1.0 - 2.0 * eps);
-    const long long nthr = 256;
-    hipLaunchKernelGGL(k_range_candidates, dim3((unsigned)((npairs + nthr - 1) / nthr)), dim3(nthr), 0, st,
-                       (const double *)dmat, nA, nB, lo_thr, hi_thr, excl, s.recheck, s.nrecheck, s.cap);
-    CIL_TRY(check_launch("k_range_candidates"));
+    if (flag) return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
+    c.mode = MODE_RANGE2;
+    CIL_TRY(classify(c, nA, nB, st));
     unsigned long long nc = 0;
-    CIL_HIP(hipMemcpyAsync(&nc, s.nrecheck, sizeof(nc), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(&nc, s.nlist, sizeof(nc), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     if ((long long)nc > s.cap) return set_error(CIL_EDEVICE, "range candidate overflow");
     double *cand;
     CIL_TRY(ws_get(WS_DIST_NORMS, sizeof(double) * std::max<unsigned long long>(nc, 1), (void **)&cand));
     CanonOut co{};
-    co.pairs = s.recheck;
-    co.npairs_dev = s.nrecheck;
+    co.pairs = s.list;
+    co.npairs_dev = s.nlist;
     co.cap = s.cap;
     co.d2 = cand;
     co.nexact = s.nexact;
@@ -492,6 +578,8 @@ int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long
     CIL_TRY(run_canonical(A, B, dim, co, (long long)nc, st));
     std::vector<double> hc(nc);
     if (nc) CIL_HIP(hipMemcpyAsync(hc.data(), cand, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
+    unsigned long long nex = 0;
+    CIL_HIP(hipMemcpyAsync(&nex, s.nexact, sizeof(nex), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     double lo = INFINITY, hi = 0.0;
     for (double v : hc) {
@@ -502,13 +590,34 @@ int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long
     *dmax = hi;
     t_pairs = npairs;
     t_rechecked = (long long)nc;
+    t_exact = (long long)nex;
     return CIL_OK;
 }
 
-template int distance_range_impl<double>(const double *, long long, const double *, long long, long long,
-                                         int, double *, double *, hipStream_t);
-template int distance_range_impl<float>(const float *, long long, const float *, long long, long long, int,
-                                        double *, double *, hipStream_t);
+template int distance_range_impl<double>(const double *, long long, const double *, long long, long long, int,
+                                         double *, double *, hipStream_t);
+template int distance_range_impl<float>(const float *, long long, const float *, long long, long long, int, double *,
+                                        double *, hipStream_t);
+
+// The fast-pass approximation and its bound for every pair (diagnostics).
+template <typename T>
+int approx_d2_impl(const T *A, long long nA, const T *B, long long nB, long long dim, double *d2, double *eps,
+                   hipStream_t st)
+{
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    ap.c.mode = MODE_DUMP;
+    ap.c.dump_d = d2;
+    ap.c.dump_eps = eps;
+    CIL_TRY(classify(ap.c, nA, nB, st));
+    t_pairs = nA * nB;
+    return CIL_OK;
+}
+
+template int approx_d2_impl<double>(const double *, long long, const double *, long long, long long, double *,
+                                    double *, hipStream_t);
+template int approx_d2_impl<float>(const float *, long long, const float *, long long, long long, double *, double *,
+                                   hipStream_t);
 
 template <typename T>
 int canonical_pairs_impl(const T *A, long long nA, const T *B, long long nB, long long dim, const long long *ia,
@@ -516,21 +625,21 @@ int canonical_pairs_impl(const T *A, long long nA, const T *B, long long nB, lon
 {
     DistScratch s;
     CIL_TRY(scratch(1, &s));
-    // nrecheck slot doubles as the bad-index flag here; nexact counts fallbacks
-    CIL_TRY(fill_zero(s.nrecheck, sizeof(unsigned long long) * 2, st));
+    // the list counter slot doubles as the bad-index flag here; nexact counts fallbacks
+    CIL_TRY(fill_zero(s.nlist, sizeof(unsigned long long) * 2, st));
     CanonOut co{};
     co.ia = ia;
     co.jb = jb;
     co.npairs = np;
     co.nA = nA;
     co.nB = nB;
-    co.bad = (int *)s.nrecheck;
+    co.bad = (int *)s.nlist;
     co.d2 = d2;
     co.nexact = s.nexact;
     co.force_exact = g_force_exact;
     CIL_TRY(run_canonical(A, B, dim, co, np, st));
     unsigned long long flags[2];
-    CIL_HIP(hipMemcpyAsync(flags, s.nrecheck, sizeof(flags), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(flags, s.nlist, sizeof(flags), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     t_pairs = np;
     t_rechecked = np;

@@ -1,0 +1,251 @@
+// Split-bf16x3 Gram on the gfx950 matrix cores, for FP32 pattern sets.
+//
+// Squared distances through the Gram: D(a, b) = |a|^2 + |b|^2 - 2 <a, b>.
+// Both sets are first shifted by one common vector c (a sampled column mean,
+// which does not change any distance) and each shifted value x' = fl32(x - c)
+// is split into two bf16 numbers x' ~ hi + lo (hi = bf16(x'), lo =
+// bf16(x' - hi)).  The Gram of the split vectors is taken as three bf16
+// products hi.hi + hi.lo + lo.hi on v_mfma_f32_32x32x16_bf16 (products exact,
+// FP32 accumulation), promoted to an FP64 accumulator every KC = 256
+// elements.  |a^|^2 is summed in FP64 from (hi + lo).
+//
+// Error bound (per pair, relative to S = |a'| + |b'| and |a'| |b'|):
+//   Gram:     |G~ - <a^, b^>| <= eG = (3 KC 2^-24 + 2^-18 + 2^-40) |a'||b'|
+//             (FP32 roundings of the accumulation; the dropped lo.lo term)
+//   split:    a^ = (a - c) + e_a with |e_a,k| <= e1 |a'_k|, e1 = 2^-24 + 2^-18
+//   distance: |D~ - D| <= 2 eG + 2 e1 S (sqrt(D~+ + 2 eG) + e1 S) + e1^2 S^2
+//             + 8 u64 (|a^|^2 + |b^|^2 + D~+) + u64 D
+// and the band used is twice that.  Pairs within the band of a threshold are
+// recomputed canonically (distance.hip), so counts stay exact.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "cil_internal.hpp"
+
+namespace cil {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int GT = 128;          // tile side (pairs) per workgroup
+constexpr int GK = 64;           // k per LDS stage
+constexpr int GPAD = 8;          // row padding (elements) of LDS tiles
+constexpr int GKC = 256;         // FP32 -> FP64 promotion interval (elements)
+
+// ------------------------------------------------------------------ shift
+// c_k = mean over up to 64 sampled rows of A and B (FP64 sum, rounded to FP32)
+__global__ void k_shift_vector(const float *A, long long nA, const float *B, long long nB, long long dim,
+                               float *c)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= dim) return;
+    const long long sa = std::min<long long>(nA, 32), sb = std::min<long long>(nB, 32);
+    double s = 0.0;
+    for (long long r = 0; r < sa; ++r) s += A[(r * nA / sa) * dim + k];
+    for (long long r = 0; r < sb; ++r) s += B[(r * nB / sb) * dim + k];
+    const long long cnt = sa + sb;
+    c[k] = cnt ? (float)(s / (double)cnt) : 0.0f;
+}
+
+// ------------------------------------------------------------------ split
+// One workgroup per row: hi/lo into [n][dimP] (zero padded), |x^|^2 in FP64.
+__global__ __launch_bounds__(256) void k_split_rows(const float *X, long long dim, long long dimP, const float *c,
+                                                    __bf16 *hi, __bf16 *lo, double *norm2)
+{
+    __shared__ double red[4];
+    const long long r = blockIdx.x;
+    const float *x = X + r * dim;
+    __bf16 *h = hi + r * dimP;
+    __bf16 *l = lo + r * dimP;
+    double s = 0.0;
+    for (long long k = threadIdx.x; k < dimP; k += blockDim.x) {
+        __bf16 bh = (__bf16)0.0f, bl = (__bf16)0.0f;
+        if (k < dim) {
+            const float xs = x[k] - c[k];
+            bh = (__bf16)xs;
+            bl = (__bf16)(xs - (float)bh);
+            const double v = (double)(float)bh + (double)(float)bl;
+            s = fma(v, v, s);
+        }
+        h[k] = bh;
+        l[k] = bl;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) norm2[r] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ------------------------------------------------------------------ Gram
+// Grid (tiles over B, tiles over A, K splits).  Four wavefronts, each a 64 x 64
+// block of the 128 x 128 tile as 2 x 2 MFMA 32 x 32 tiles.  Output: FP64
+// partial Gram P[split][i][j].
+//
+// v_mfma_f32_32x32x16_bf16 lane layout: lane l supplies row l%32 of the A
+// block and row l%32 of the B block (a column of B^T), elements
+// k = 8 (l/32) .. 8 (l/32) + 7 of the 16-wide k step; accumulator element r of
+// lane l is C[8 (r/4) + 4 (l/32) + r%4][l%32].
+__global__ __launch_bounds__(256) void k_gram_bf16x3(const __bf16 *Ah, const __bf16 *Al, long long nA,
+                                                     const __bf16 *Bh, const __bf16 *Bl, long long nB,
+                                                     long long dimP, long long ksplit, double *P)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sAh[GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) __bf16 sAl[GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) __bf16 sBh[GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) __bf16 sBl[GT][GK + GPAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    const long long i0 = (long long)blockIdx.y * GT, j0 = (long long)blockIdx.x * GT;
+    const long long kb = (long long)blockIdx.z * ksplit;
+    const long long ke = std::min<long long>(dimP, kb + ksplit);
+
+    floatx16 acc[2][2];
+    double acc64[2][2][16];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[a][b][r] = 0.0f;
+                acc64[a][b][r] = 0.0;
+            }
+        }
+
+    int since_flush = 0;
+    for (long long k0 = kb; k0 < ke; k0 += GK) {
+        __syncthreads();
+        // stage 128 rows x 64 k of each split array: 16-byte chunks, 8 per row
+        for (int e = tid; e < GT * (GK / 8); e += 256) {
+            const int row = e / (GK / 8), ch = e % (GK / 8);
+            const long long ia = i0 + row, jb = j0 + row;
+            const long long off = k0 + 8 * ch;
+            bf16x8 z;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) z[t] = (__bf16)0.0f;
+            const bool ka = off < ke;
+            *(bf16x8 *)&sAh[row][8 * ch] = (ia < nA && ka) ? *(const bf16x8 *)(Ah + ia * dimP + off) : z;
+            *(bf16x8 *)&sAl[row][8 * ch] = (ia < nA && ka) ? *(const bf16x8 *)(Al + ia * dimP + off) : z;
+            *(bf16x8 *)&sBh[row][8 * ch] = (jb < nB && ka) ? *(const bf16x8 *)(Bh + jb * dimP + off) : z;
+            *(bf16x8 *)&sBl[row][8 * ch] = (jb < nB && ka) ? *(const bf16x8 *)(Bl + jb * dimP + off) : z;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 16) {
+            const int kofs = kk + 8 * (lane >> 5);
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ra = wr * 64 + t * 32 + (lane & 31);
+                const int rb = wc * 64 + t * 32 + (lane & 31);
+                ah[t] = *(const bf16x8 *)&sAh[ra][kofs];
+                al[t] = *(const bf16x8 *)&sAl[ra][kofs];
+                bh[t] = *(const bf16x8 *)&sBh[rb][kofs];
+                bl[t] = *(const bf16x8 *)&sBl[rb][kofs];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        since_flush += GK;
+        if (since_flush >= GKC) {
+            since_flush = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        acc64[a][b][r] += (double)acc[a][b][r];
+                        acc[a][b][r] = 0.0f;
+                    }
+        }
+    }
+    double *Ps = P + (long long)blockIdx.z * nA * nB;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const long long i = i0 + wr * 64 + a * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                const long long j = j0 + wc * 64 + b * 32 + (lane & 31);
+                if (i < nA && j < nB) Ps[i * nB + j] = acc64[a][b][r] + (double)acc[a][b][r];
+            }
+}
+
+// ---------------------------------------------------------------- host
+struct GramWork {
+    __bf16 *Ah, *Al, *Bh, *Bl;
+    double *na, *nb;
+    float *c;
+    long long dimP;
+};
+
+int gram_prepare(const float *A, long long nA, const float *B, long long nB, long long dim, GramWork *g,
+                 hipStream_t st)
+{
+    const long long dimP = std::max<long long>(GK, (dim + GK - 1) / GK * GK);
+    void *p;
+    const size_t sa = sizeof(__bf16) * (size_t)std::max<long long>(nA, 1) * dimP;
+    const size_t sb = sizeof(__bf16) * (size_t)std::max<long long>(nB, 1) * dimP;
+    CIL_TRY(ws_get(WS_DIST_SPLIT_A, 2 * sa, &p));
+    g->Ah = (__bf16 *)p;
+    g->Al = (__bf16 *)((char *)p + sa);
+    CIL_TRY(ws_get(WS_DIST_SPLIT_B, 2 * sb, &p));
+    g->Bh = (__bf16 *)p;
+    g->Bl = (__bf16 *)((char *)p + sb);
+    CIL_TRY(ws_get(WS_DIST_COUNTS, sizeof(double) * (size_t)(nA + nB + 2) + sizeof(float) * (size_t)dimP + 64, &p));
+    g->na = (double *)p;
+    g->nb = g->na + nA + 1;
+    g->c = (float *)(g->nb + nB + 1);
+    g->dimP = dimP;
+    if (dim > 0) {
+        hipLaunchKernelGGL(k_shift_vector, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, st, A, nA, B, nB, dim,
+                           g->c);
+        CIL_TRY(check_launch("k_shift_vector"));
+    }
+    const ProfMark pm = prof_begin("k_split_rows", st);
+    if (nA > 0)
+        hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nA), dim3(256), 0, st, A, dim, dimP, (const float *)g->c,
+                           g->Ah, g->Al, g->na);
+    if (nB > 0)
+        hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nB), dim3(256), 0, st, B, dim, dimP, (const float *)g->c,
+                           g->Bh, g->Bl, g->nb);
+    prof_end(pm, st);
+    return check_launch("k_split_rows");
+}
+
+// number of K splits so that the grid holds enough workgroups
+long long gram_splits(long long nA, long long nB, long long dimP)
+{
+    const long long tiles = ((nA + GT - 1) / GT) * ((nB + GT - 1) / GT);
+    long long s = 1;
+    while (tiles * s < 1024 && (dimP / (s * 2)) >= GKC) s *= 2;
+    return s;
+}
+
+// splits x ks must cover dimP; ks a multiple of GK
+int gram_partials(const GramWork &g, long long nA, long long nB, long long splits, long long ks, double *P,
+                  hipStream_t st)
+{
+    if (ks % GK != 0 || splits * ks < g.dimP) return set_error(CIL_EINVAL, "bad Gram split");
+    dim3 grid((unsigned)((nB + GT - 1) / GT), (unsigned)((nA + GT - 1) / GT), (unsigned)splits);
+    const ProfMark pm = prof_begin("k_gram_bf16x3", st);
+    hipLaunchKernelGGL(k_gram_bf16x3, grid, dim3(256), 0, st, (const __bf16 *)g.Ah, (const __bf16 *)g.Al, nA,
+                       (const __bf16 *)g.Bh, (const __bf16 *)g.Bl, nB, g.dimP, ks, P);
+    prof_end(pm, st);
+    return check_launch("k_gram_bf16x3");
+}
+
+}  // namespace cil

@@ -58,6 +58,61 @@ def test_exact_summation_path_bit_exact(cil, oracle_mod):
     assert np.array_equal(got, oracle_mod.pair_d2(A, B).reshape(-1))
 
 
+def adversarial_sets(case, nA, nB, d, seed):
+    g = np.random.default_rng(seed)
+    if case == "random":
+        A = g.standard_normal((nA, d))
+        B = g.standard_normal((nB, d))
+    elif case == "offset":                       # large common offset, small spread
+        A = 40.0 + 0.01 * g.standard_normal((nA, d))
+        B = 40.0 + 0.01 * g.standard_normal((nB, d))
+    elif case == "near_equal":                   # B rows are tiny perturbations of A rows
+        A = g.standard_normal((nA, d))
+        B = A[g.integers(0, nA, nB)] + 1e-5 * g.standard_normal((nB, d))
+    elif case == "dynamic_range":                # entries spanning many binades
+        A = g.standard_normal((nA, d)) * 10.0 ** g.integers(-6, 4, size=(nA, d))
+        B = g.standard_normal((nB, d)) * 10.0 ** g.integers(-6, 4, size=(nB, d))
+    elif case == "bf16_boundary":                # values halfway between bf16 neighbours
+        base = 2.0 ** g.integers(-3, 3, size=(nA + nB, d))
+        mant = (g.integers(128, 256, size=(nA + nB, d)) + 0.5) / 128.0
+        X = base * mant * np.where(g.random((nA + nB, d)) < 0.5, -1, 1)
+        A, B = X[:nA], X[nA:]
+    elif case == "stripes":                      # Turing-like stand-in patterns
+        X = cs.stripe_patterns(nA + nB, int(np.sqrt(d // 2)), seed=seed).reshape(nA + nB, -1)
+        A, B = X[:nA], X[nA:]
+    return A.astype(np.float32), B.astype(np.float32)
+
+
+@pytest.mark.parametrize("case", ["random", "offset", "near_equal", "dynamic_range", "bf16_boundary", "stripes"])
+@pytest.mark.parametrize("d", [200, 2048, 8192])
+def test_fast_pass_bound_holds(cil, oracle_mod, case, d):
+    """P10: the split-bf16x3 Gram value is within its stated bound of the
+    canonical distance for every pair, on random and adversarial inputs; the
+    counts after the re-check equal the canonical counts."""
+    nA, nB = 40, 37
+    if case == "stripes":
+        d = {200: 2 * 10 * 10, 2048: 2048, 8192: 8192}[d]
+    A, B = adversarial_sets(case, nA, nB, d, seed=d)
+    d2, eps = cil.cil_approx_d2(dev(A), dev(B))
+    D = oracle_mod.pair_d2(A, B)
+    d2, eps = d2.cpu().numpy(), eps.cpu().numpy()
+    assert np.all(np.abs(d2 - D) <= eps), float((np.abs(d2 - D) / np.maximum(eps, 1e-300)).max())
+    rel = float(np.median(eps / np.maximum(D, 1e-300)))
+    print("%s d=%d: median bound/D %.2e, max err/bound %.3f" % (case, d, rel,
+          float((np.abs(d2 - D) / np.maximum(eps, 1e-300)).max())))
+    radii = oracle_mod.radii_ladder(D.min() if D.min() > 0 else D.max() / 100, D.max(), 13)
+    c, _ = cil.cil_features(dev(A), dev(B), radii)
+    assert np.array_equal(c, oracle_mod.counts_from_d2(D, radii))
+
+
+def test_fast_pass_bound_fp64(cil, oracle_mod):
+    A, B = adversarial_sets("dynamic_range", 30, 33, 777, seed=1)
+    A, B = A.astype(np.float64), B.astype(np.float64)
+    d2, eps = cil.cil_approx_d2(dev(A), dev(B))
+    D = oracle_mod.pair_d2(A, B)
+    assert np.all(np.abs(d2.cpu().numpy() - D) <= eps.cpu().numpy())
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nA,nB,d,M", [(1, 1, 8, 3), (67, 131, 50, 13), (64, 64, 2048, 16), (130, 70, 333, 32),
                                        (20, 30, 100, 100)])
