@@ -81,9 +81,12 @@ typedef struct {
 } cil_problem;
 
 typedef enum {
-    CIL_PATH_AUTO = 0,   /* fused LDS-resident stepper where supported, else plain */
-    CIL_PATH_PLAIN = 1,  /* one kernel per stage, host-driven step loop           */
-    CIL_PATH_FUSED = 2   /* fused stepper; CIL_EUNSUPPORTED where not available    */
+    CIL_PATH_AUTO = 0,        /* fused LDS-resident stepper where supported, else plain */
+    CIL_PATH_PLAIN = 1,       /* one kernel per stage, host-driven step loop           */
+    CIL_PATH_FUSED = 2,       /* fused stepper (default variant); CIL_EUNSUPPORTED
+                                 where not available (n not in {32, 64, 128}; FP64 n = 128) */
+    CIL_PATH_FUSED_LINE = 3,  /* fused, one lane transforms a whole grid line        */
+    CIL_PATH_FUSED_QUAD = 4   /* fused, a quad of lanes transforms a grid line       */
 } cil_path;
 
 /* Time stepping: IMEX Euler with step dt.  tol <= 0: exactly max_steps steps.

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libcil.so")
 CIL_OK, CIL_EINVAL, CIL_EUNSUPPORTED, CIL_ENOMEM, CIL_EDEVICE, CIL_ENOTSPD, CIL_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 CIL_FHN, CIL_GM, CIL_GM_SOURCE, CIL_BRUSSELATOR, CIL_HEAT = 0, 1, 2, 3, 4
 CIL_FP64, CIL_FP32 = 0, 1
-CIL_PATH_AUTO, CIL_PATH_PLAIN, CIL_PATH_FUSED = 0, 1, 2
+CIL_PATH_AUTO, CIL_PATH_PLAIN, CIL_PATH_FUSED, CIL_PATH_FUSED_LINE, CIL_PATH_FUSED_QUAD = 0, 1, 2, 3, 4
 CIL_SOLVE_OK, CIL_SOLVE_NONFINITE, CIL_SOLVE_MAXSTEPS, CIL_SOLVE_FP32_FLOOR = 0, 1, 2, 3
 CIL_OPT_FORCE_EXACT_SUM = 1
 

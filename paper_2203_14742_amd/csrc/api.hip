@@ -292,7 +292,7 @@ int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem
     if (!(stepping->dt > 0.0) || !std::isfinite(stepping->dt)) return set_error(CIL_EINVAL, "dt must be > 0");
     if (stepping->max_steps < 0) return set_error(CIL_EINVAL, "max_steps < 0");
     if (stepping->check_every < 1) return set_error(CIL_EINVAL, "check_every < 1");
-    if (stepping->path < CIL_PATH_AUTO || stepping->path > CIL_PATH_FUSED)
+    if (stepping->path < CIL_PATH_AUTO || stepping->path > CIL_PATH_FUSED_QUAD)
         return set_error(CIL_EINVAL, "unknown path");
     for (int b = 0; b < B; ++b) {
         const cil_problem &p = probs[b];

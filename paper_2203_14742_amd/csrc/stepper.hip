@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "cil_internal.hpp"
+#include "dct_quad.hpp"
 #include "dct_reg.hpp"
 
 namespace cil {
@@ -346,6 +347,110 @@ __global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *l
     }
 }
 
+// Quad variant: one workgroup of 8N threads per solve; quad t / 4 handles
+// species (t / 4) / N, line (t / 4) % N, with the line transforms of
+// dct_quad.hpp.  Per step: gather the explicit reaction at the quad's row
+// positions, row DCT, column DCT + divide + inverse, row inverse; each line
+// is updated in place by its own quad (within one wavefront).
+template <typename T, int N>
+__global__ __launch_bounds__(8 * N) void k_fused_q(const DevSolve *S, const int *list, T *state, const T *tables,
+                                                   int model, double dt, int K, StepResults R)
+{
+    using Q = QuadLine<T, N>;
+    constexpr int P = Q::P;
+    constexpr int LD = N + 1, SP = N * LD, THREADS = 8 * N, WAVES = THREADS / 64;
+    __shared__ T sm[2 * SP];
+    __shared__ double red[2 * WAVES];
+
+    const int b = list[blockIdx.x];
+    const DevSolve s = S[b];
+    T *u = state + s.off;
+    const int tid = threadIdx.x;
+    const int quad = tid >> 2, q = tid & 3;
+    const int sp = quad / N, ln = quad % N;
+    typename Q::Lane L;
+    Q::init(L, q);
+    const T *tabc = tables + (size_t)s.tab * 2 * N * N + (size_t)sp * N * N + ln;
+    T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
+    const T tdt = T(dt);
+    T *ms = sm + sp * SP;
+
+    for (int e = tid; e < 2 * N * N; e += THREADS) {
+        const int c = e / (N * N), rem = e % (N * N);
+        sm[c * SP + (rem / N) * LD + rem % N] = u[e];
+    }
+    __syncthreads();
+
+    for (int step = 0; step < K; ++step) {
+        if (step == K - 1) {          // keep u^{K-1} in HBM for the residual
+            for (int e = tid; e < 2 * N * N; e += THREADS) {
+                const int c = e / (N * N), rem = e % (N * N);
+                u[e] = sm[c * SP + (rem / N) * LD + rem % N];
+            }
+        }
+        // explicit reaction at this lane's row positions (both species read, own species kept)
+        T zr[P], zi[P];
+        dispatch_model(model, [&](auto MD) {
+            static_for<0, P>([&](auto Mi) {
+                constexpr int m1 = Mi;
+                constexpr int pb = bitrev(m1, Q::LOGP);
+                const int j = 2 * (4 * m1 + q);
+                const int a0 = ln * LD + Q::vsrc(j), a1 = ln * LD + Q::vsrc(j + 1);
+                T f, g;
+                const T v0 = sm[a0], w0 = sm[SP + a0];
+                kinetics<MD>(p, v0, w0, f, g);
+                zr[pb] = sp ? w0 + tdt * g : v0 + tdt * f;
+                const T v1 = sm[a1], w1 = sm[SP + a1];
+                kinetics<MD>(p, v1, w1, f, g);
+                zi[pb] = sp ? w1 + tdt * g : v1 + tdt * f;
+            });
+        });
+        __syncthreads();
+        Q::forward_from(L, zr, zi, [&](int k, T v) { ms[ln * LD + k] = v; });
+        __syncthreads();
+        Q::forward(L, [&](int i) { return ms[i * LD + ln]; }, [&](int k, T v) { ms[k * LD + ln] = v * tabc[k * N]; });
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        Q::inverse(L, [&](int k) { return ms[k * LD + ln]; }, [&](int i, T v) { ms[i * LD + ln] = v; });
+        __syncthreads();
+        Q::inverse(L, [&](int k) { return ms[ln * LD + k]; }, [&](int j, T v) { ms[ln * LD + j] = v; });
+        __syncthreads();
+    }
+
+    double d = 0.0, a = 0.0;
+    int bad = 0;
+    for (int e = tid; e < 2 * N * N; e += THREADS) {
+        const int c = e / (N * N), rem = e % (N * N);
+        const T nv = sm[c * SP + (rem / N) * LD + rem % N];
+        const double dv = fabs((double)nv - (double)u[e]);
+        const double av = fabs((double)nv);
+        if (!isfinite((double)nv)) bad = 1;
+        d = fmax(d, isnan(dv) ? 0.0 : dv);
+        a = fmax(a, isnan(av) ? 0.0 : av);
+        u[e] = nv;
+    }
+    d = wave_max(d);
+    a = wave_max(a);
+    bad = wave_or(bad);
+    const int wv = tid / 64;
+    if ((tid & 63) == 0) {
+        red[wv] = d;
+        red[WAVES + wv] = a;
+        if (bad) R.bad[b] = 1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double dm = 0.0, am = 0.0;
+        for (int w = 0; w < WAVES; ++w) {
+            dm = fmax(dm, red[w]);
+            am = fmax(am, red[WAVES + w]);
+        }
+        R.resid[b] = (unsigned long long)__double_as_longlong(dm);
+        R.maxabs[b] = (unsigned long long)__double_as_longlong(am);
+    }
+}
+
 // Spectral tables for the fused back-end:
 // tab[s][k][l] = 1 / (4 N^2 (1 + dt nu_s (lam_k + lam_l) / h^2)), in FP64 then T.
 struct TabSpec {
@@ -429,6 +534,7 @@ int plain_tables(int n, PlainTables *out)
 struct Group {
     int n = 0;
     bool fused = false;
+    bool quad = true;             // fused: quad-lane line transforms (else one lane per line)
     bool f32 = false;
     bool polish = false;          // FP64 copies of FP32 solves
     std::vector<int> active;      // solve indices
@@ -452,9 +558,32 @@ int launch_fused(const Group &g, int nl, int model, double dt, int K, StepResult
     const DevSolve *S = g.dsolves;
     T *u = (T *)g.state;
     const T *tb = (const T *)g.tables;
+    const int ni = g.n == 32 ? 0 : (g.n == 64 ? 1 : 2);
+    if (g.quad) {
+        static const char *q32[3] = {"k_fused_q_f32_n32", "k_fused_q_f32_n64", "k_fused_q_f32_n128"};
+        static const char *q64[3] = {"k_fused_q_f64_n32", "k_fused_q_f64_n64", "k_fused_q_f64_n128"};
+        const ProfMark pm = prof_begin(std::is_same<T, float>::value ? q32[ni] : q64[ni], st);
+        switch (g.n) {
+        case 32:
+            hipLaunchKernelGGL((k_fused_q<T, 32>), dim3(nl), dim3(256), 0, st, S, g.dlist, u, tb, model, dt, K, R);
+            break;
+        case 64:
+            hipLaunchKernelGGL((k_fused_q<T, 64>), dim3(nl), dim3(512), 0, st, S, g.dlist, u, tb, model, dt, K, R);
+            break;
+        default:
+            if constexpr (std::is_same<T, float>::value) {
+                hipLaunchKernelGGL((k_fused_q<T, 128>), dim3(nl), dim3(1024), 0, st, S, g.dlist, u, tb, model, dt, K,
+                                   R);
+            } else {
+                return set_error(CIL_EUNSUPPORTED, "fused FP64 stepper supports n = 32, 64");
+            }
+            break;
+        }
+        prof_end(pm, st);
+        return check_launch("k_fused_q");
+    }
     static const char *names32[3] = {"k_fused_f32_n32", "k_fused_f32_n64", "k_fused_f32_n128"};
     static const char *names64[3] = {"k_fused_f64_n32", "k_fused_f64_n64", "k_fused_f64_n128"};
-    const int ni = g.n == 32 ? 0 : (g.n == 64 ? 1 : 2);
     const ProfMark pm = prof_begin(std::is_same<T, float>::value ? names32[ni] : names64[ni], st);
     switch (g.n) {
     case 32:
@@ -563,10 +692,11 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         g.n = kv.first;
         g.f32 = f32;
         const bool fs = fused_supported(g.n, f32);
-        if (stp->path == CIL_PATH_FUSED && !fs)
+        if (stp->path >= CIL_PATH_FUSED && !fs)
             return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", g.n,
                              f32 ? "FP32" : "FP64");
         g.fused = fs && stp->path != CIL_PATH_PLAIN;
+        g.quad = stp->path != CIL_PATH_FUSED_LINE;
         g.active = kv.second;
         groups.push_back(g);
     }
@@ -721,6 +851,7 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
                 g.f32 = true;
                 g.polish = true;
                 g.fused = fused_supported(n, false) && stp->path != CIL_PATH_PLAIN;
+                g.quad = stp->path != CIL_PATH_FUSED_LINE;
                 g.state = state64;
                 g.dsolves = dsolves64;
                 CIL_TRY(cb.alloc((void **)&g.dlist, sizeof(int) * B));

@@ -48,7 +48,7 @@ def run_both(cil, oracle_mod, model, p, nu, n, L, dt, steps, ics, prec, path, to
     return st.double().cpu().numpy(), rep, out, osteps, ores, ostat
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 3, 4])
 @pytest.mark.parametrize("case,n,L,dt,steps", [(FHN, 32, 1.0, 0.01, 300), (GM, 32, 1.0, 0.05, 200),
                                                (GMS, 64, 120.0, 0.2, 150), (BZ, 64, 1.0, 0.05, 200)])
 def test_fp64_trajectory_parity(cil, oracle_mod, path, case, n, L, dt, steps):
@@ -62,7 +62,7 @@ def test_fp64_trajectory_parity(cil, oracle_mod, path, case, n, L, dt, steps):
     assert np.allclose(rep["final_resid"], ores, rtol=1e-6, atol=1e-14)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 3, 4])
 @pytest.mark.parametrize("case,n,L,dt,steps", [(FHN, 32, 1.0, 0.01, 300), (GMS, 64, 120.0, 0.2, 150),
                                                (BZ, 128, 1.0, 0.05, 100), (FHN, 128, 1.0, 0.05, 100)])
 def test_fp32_trajectory_parity(cil, oracle_mod, path, case, n, L, dt, steps):
@@ -99,7 +99,7 @@ def test_cosine_mode_decay_closed_form(cil, prec, n, k, l):
         assert np.abs(out[s] - sign * amp * mode).max() <= tol * abs(sign)
 
 
-@pytest.mark.parametrize("prec,path", [("fp64", 1), ("fp64", 2), ("fp32", 2)])
+@pytest.mark.parametrize("prec,path", [("fp64", 1), ("fp64", 3), ("fp64", 4), ("fp32", 3), ("fp32", 4)])
 def test_homogeneous_state_stays_fixed(cil, oracle_mod, prec, path):
     model, p, nu = GMS
     v0, w0 = oracle_mod.homogeneous_state(model, p)
@@ -116,7 +116,8 @@ def test_homogeneous_state_stays_fixed(cil, oracle_mod, prec, path):
     assert np.abs(out[:, 0] - v0).max() <= tol * v0 and np.abs(out[:, 1] - w0).max() <= tol * w0
 
 
-@pytest.mark.parametrize("prec,path", [("fp64", 1), ("fp64", 2), ("fp32", 1), ("fp32", 2)])
+@pytest.mark.parametrize("prec,path", [("fp64", 1), ("fp64", 3), ("fp64", 4), ("fp32", 1), ("fp32", 3),
+                                       ("fp32", 4)])
 def test_resume_is_bitwise(cil, prec, path):
     model, p, nu = FHN
     n = 32
@@ -143,7 +144,7 @@ def test_check_every_does_not_change_the_trajectory(cil):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 3, 4])
 def test_stop_rule_matches_oracle(cil, oracle_mod, path):
     """tol > 0: a solve stops at the first multiple of check_every whose FP64
     residual is below tol; FP64 steps_taken equal the oracle's."""
