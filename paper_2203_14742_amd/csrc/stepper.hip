@@ -13,12 +13,14 @@
 //   plain  one kernel per stage (reaction, row DCT, column DCT + divide,
 //          column inverse, row inverse + residual), dense cosine matrices,
 //          state streamed through HBM, host-driven step loop; any n >= 2.
-//   fused  one workgroup per solve, the whole n x n x 2 state resident in
-//          LDS for K steps per launch, every line transformed in registers
-//          by the FFT-based DCT of dct_reg.hpp; n in {32, 64, 128} (FP32),
-//          {32, 64} (FP64).
+//   fused  one persistent workgroup per solve, the whole n x n x 2 state
+//          resident in LDS from the first step to the last; every line
+//          transformed in registers by one lane (dct_reg.hpp) or a quad of
+//          lanes (dct_quad.hpp); the workgroup evaluates its own stop rule
+//          and retires; n in {32, 64, 128} (FP32), {32, 64} (FP64).
 // Both evaluate the stationarity residual max |u^s - u^{s-1}| / dt in FP64
-// at the last step of each launch, per solve.
+// every check_every steps (and at max_steps), per solve.  FP32 solves whose
+// residual falls below the FP32 floor continue in FP64 (phase 2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -224,27 +226,105 @@ __global__ void k_plain_rows_inv(const DevSolve *S, const int *list, const T *in
 }
 
 // ======================================================================
-// Fused back-end: one workgroup of 2N threads per solve; thread t handles
-// species t / N and line t % N.  LDS holds u[2][N][N+1] (padded rows).
+// Fused back-end: one workgroup per solve, both species resident in LDS as
+// u[2][N][N+1] (padded rows).  The workgroup runs its solve by itself: at
+// every evaluation step (a multiple of check_every, or max_steps) it keeps
+// the previous state in HBM, takes the step, computes the FP64 residual
+// max |u^s - u^{s-1}| / dt, max |u| and a non-finite flag over both species,
+// and retires when the stop rule fires.  No host round trip per step.
 
-template <typename T, int N>
-struct FusedCfg {
-    static constexpr int LD = N + 1;
-    static constexpr int SP = N * LD;
-    static constexpr int THREADS = 2 * N;
-    static constexpr size_t LDS_BYTES = sizeof(T) * 2 * SP;
+struct PersistArgs {
+    long long max_steps;
+    double tol;
+    int check;
+    double floor_coef;          // FP32 stepping: floor_ulps 2^-24 / dt, so the floor is floor_coef max|u|; 0 = off
+    long long *steps;           // per solve: steps taken (in: start, out: end)
+    double *resid;              // per solve: residual of the last evaluated step
+    int *status;                // per solve: cil_solve_status
 };
 
-template <typename T, int N>
-__global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *list, T *state,
-                                                 const T *tables, int model, double dt, int K,
-                                                 StepResults R)
+template <int N>
+__device__ __forceinline__ int lds_addr(int e)
 {
-    using Cfg = FusedCfg<T, N>;
-    using D = DctLine<T, N>;
-    __shared__ T sm[2 * Cfg::SP];
-    __shared__ double red[2 * Cfg::THREADS / 64 + 2];
+    const int c = e / (N * N), rem = e % (N * N);
+    return c * (N * (N + 1)) + (rem / N) * (N + 1) + rem % N;
+}
 
+// Load the solve, step it with body() (one IMEX step on the LDS state,
+// ending with a barrier) until the stop rule fires, store it.
+template <typename T, int N, int THREADS, typename Body>
+__device__ __forceinline__ void run_solve(T *sm, T *u, int b, double dt, const PersistArgs &pa, Body &&body)
+{
+    constexpr int WAVES = THREADS / 64;
+    __shared__ double red[2 * WAVES];
+    __shared__ int s_bad;
+    __shared__ int s_stop;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 2 * N * N; e += THREADS) sm[lds_addr<N>(e)] = u[e];
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    long long step = pa.steps[b];
+    while (step < pa.max_steps) {
+        const long long next = step + 1;
+        const bool eval = (next % pa.check == 0) || (next == pa.max_steps);
+        if (eval)
+            for (int e = tid; e < 2 * N * N; e += THREADS) u[e] = sm[lds_addr<N>(e)];
+        body();
+        step = next;
+        if (eval) {
+            double d = 0.0, a = 0.0;
+            int bad = 0;
+            for (int e = tid; e < 2 * N * N; e += THREADS) {
+                const T nv = sm[lds_addr<N>(e)];
+                const double dv = fabs((double)nv - (double)u[e]);
+                const double av = fabs((double)nv);
+                if (!isfinite((double)nv)) bad = 1;
+                d = fmax(d, isnan(dv) ? 0.0 : dv);
+                a = fmax(a, isnan(av) ? 0.0 : av);
+            }
+            d = wave_max(d);
+            a = wave_max(a);
+            bad = wave_or(bad);
+            const int wv = tid / 64;
+            if ((tid & 63) == 0) {
+                red[wv] = d;
+                red[WAVES + wv] = a;
+                if (bad) s_bad = 1;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double dm = 0.0, am = 0.0;
+                for (int w = 0; w < WAVES; ++w) {
+                    dm = fmax(dm, red[w]);
+                    am = fmax(am, red[WAVES + w]);
+                }
+                const double r = dm / dt;
+                int st = -1;
+                if (s_bad) st = CIL_SOLVE_NONFINITE;
+                else if (pa.tol > 0.0 && r < pa.tol) st = CIL_SOLVE_OK;
+                else if (pa.tol > 0.0 && pa.floor_coef > 0.0 && r < pa.floor_coef * am) st = CIL_SOLVE_FP32_FLOOR;
+                else if (next == pa.max_steps) st = pa.tol > 0.0 ? CIL_SOLVE_MAXSTEPS : CIL_SOLVE_OK;
+                pa.resid[b] = s_bad ? (double)NAN : r;
+                if (st >= 0) pa.status[b] = st;
+                s_stop = st >= 0;
+            }
+            __syncthreads();
+            if (s_stop) break;
+        }
+    }
+    for (int e = tid; e < 2 * N * N; e += THREADS) u[e] = sm[lds_addr<N>(e)];
+    if (tid == 0) pa.steps[b] = step;
+}
+
+// Line variant: 2N threads, thread t handles species t / N, line t % N,
+// whole line in its registers (dct_reg.hpp).
+template <typename T, int N>
+__global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *list, T *state, const T *tables,
+                                                 int model, double dt, PersistArgs pa)
+{
+    using D = DctLine<T, N>;
+    constexpr int LD = N + 1, SP = N * LD, THREADS = 2 * N;
+    __shared__ T sm[2 * SP];
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
     T *u = state + s.off;
@@ -253,115 +333,66 @@ __global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *l
     const int sp = tid / N, ln = tid % N;
     T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
     const T tdt = T(dt);
-
-    for (int q = tid; q < 2 * N * N; q += Cfg::THREADS) {
-        const int c = q / (N * N), rem = q % (N * N);
-        sm[c * Cfg::SP + (rem / N) * Cfg::LD + rem % N] = u[q];
-    }
-    __syncthreads();
-
-    for (int step = 0; step < K; ++step) {
-        if (step == K - 1) {          // keep u^{K-1} in HBM for the residual
-            for (int q = tid; q < 2 * N * N; q += Cfg::THREADS) {
-                const int c = q / (N * N), rem = q % (N * N);
-                u[q] = sm[c * Cfg::SP + (rem / N) * Cfg::LD + rem % N];
-            }
-        }
-        // explicit reaction, pointwise, both species from the old values
-        dispatch_model(model, [&](auto MD) {
-            for (int q = tid; q < N * N; q += Cfg::THREADS) {
-                const int a = (q / N) * Cfg::LD + q % N;
-                const T v = sm[a], w = sm[Cfg::SP + a];
+    T *ms = sm + sp * SP;
+    run_solve<T, N, THREADS>(sm, u, b, dt, pa, [&]() {
+        dispatch_model(model, [&](auto MD) {        // explicit reaction, pointwise
+            for (int q = tid; q < N * N; q += THREADS) {
+                const int a = (q / N) * LD + q % N;
+                const T v = sm[a], w = sm[SP + a];
                 T f, g;
                 kinetics<MD>(p, v, w, f, g);
                 sm[a] = v + tdt * f;
-                sm[Cfg::SP + a] = w + tdt * g;
+                sm[SP + a] = w + tdt * g;
             }
         });
         __syncthreads();
-        T *ms = sm + sp * Cfg::SP;
         {   // forward DCT along rows
             T x[N], X[N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) x[j] = ms[ln * Cfg::LD + j];
+            for (int j = 0; j < N; ++j) x[j] = ms[ln * LD + j];
             D::forward(x, X);
 #pragma unroll
-            for (int j = 0; j < N; ++j) ms[ln * Cfg::LD + j] = X[j];
+            for (int j = 0; j < N; ++j) ms[ln * LD + j] = X[j];
         }
         __syncthreads();
-        {   // forward DCT along columns, spectral divide, inverse along columns
+        {   // forward along columns, spectral divide, inverse along columns
             T x[N], X[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) x[i] = ms[i * Cfg::LD + ln];
+            for (int i = 0; i < N; ++i) x[i] = ms[i * LD + ln];
             D::forward(x, X);
             const T *tb = tab + (size_t)sp * N * N + ln;
 #pragma unroll
             for (int k = 0; k < N; ++k) X[k] *= tb[k * N];
             D::inverse(X, x);
 #pragma unroll
-            for (int i = 0; i < N; ++i) ms[i * Cfg::LD + ln] = x[i];
+            for (int i = 0; i < N; ++i) ms[i * LD + ln] = x[i];
         }
         __syncthreads();
-        {   // inverse DCT along rows
+        {   // inverse along rows
             T x[N], X[N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) X[j] = ms[ln * Cfg::LD + j];
+            for (int j = 0; j < N; ++j) X[j] = ms[ln * LD + j];
             D::inverse(X, x);
 #pragma unroll
-            for (int j = 0; j < N; ++j) ms[ln * Cfg::LD + j] = x[j];
+            for (int j = 0; j < N; ++j) ms[ln * LD + j] = x[j];
         }
         __syncthreads();
-    }
-
-    // write back, residual against u^{K-1} (FP64), max |u|, non-finite flag
-    double d = 0.0, a = 0.0;
-    int bad = 0;
-    for (int q = tid; q < 2 * N * N; q += Cfg::THREADS) {
-        const int c = q / (N * N), rem = q % (N * N);
-        const T nv = sm[c * Cfg::SP + (rem / N) * Cfg::LD + rem % N];
-        const double dv = fabs((double)nv - (double)u[q]);
-        const double av = fabs((double)nv);
-        if (!isfinite((double)nv)) bad = 1;
-        d = fmax(d, isnan(dv) ? 0.0 : dv);
-        a = fmax(a, isnan(av) ? 0.0 : av);
-        u[q] = nv;
-    }
-    d = wave_max(d);
-    a = wave_max(a);
-    bad = wave_or(bad);
-    const int wv = tid / 64;
-    if ((tid & 63) == 0) {
-        red[wv] = d;
-        red[Cfg::THREADS / 64 + wv] = a;
-        if (bad) R.bad[b] = 1;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double dm = 0.0, am = 0.0;
-        for (int w = 0; w < Cfg::THREADS / 64; ++w) {
-            dm = fmax(dm, red[w]);
-            am = fmax(am, red[Cfg::THREADS / 64 + w]);
-        }
-        R.resid[b] = (unsigned long long)__double_as_longlong(dm);
-        R.maxabs[b] = (unsigned long long)__double_as_longlong(am);
-    }
+    });
 }
 
-// Quad variant: one workgroup of 8N threads per solve; quad t / 4 handles
-// species (t / 4) / N, line (t / 4) % N, with the line transforms of
-// dct_quad.hpp.  Per step: gather the explicit reaction at the quad's row
-// positions, row DCT, column DCT + divide + inverse, row inverse; each line
-// is updated in place by its own quad (within one wavefront).
+// Quad variant: 8N threads; quad t / 4 handles species (t / 4) / N, line
+// (t / 4) % N with the line transforms of dct_quad.hpp.  Per step: gather
+// the explicit reaction at the quad's row positions, row DCT, column DCT +
+// divide + inverse, row inverse; each line is updated in place by its own
+// quad (within one wavefront).
 template <typename T, int N>
 __global__ __launch_bounds__(8 * N) void k_fused_q(const DevSolve *S, const int *list, T *state, const T *tables,
-                                                   int model, double dt, int K, StepResults R)
+                                                   int model, double dt, PersistArgs pa)
 {
     using Q = QuadLine<T, N>;
     constexpr int P = Q::P;
-    constexpr int LD = N + 1, SP = N * LD, THREADS = 8 * N, WAVES = THREADS / 64;
+    constexpr int LD = N + 1, SP = N * LD, THREADS = 8 * N;
     __shared__ T sm[2 * SP];
-    __shared__ double red[2 * WAVES];
-
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
     T *u = state + s.off;
@@ -374,21 +405,7 @@ __global__ __launch_bounds__(8 * N) void k_fused_q(const DevSolve *S, const int 
     T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
     const T tdt = T(dt);
     T *ms = sm + sp * SP;
-
-    for (int e = tid; e < 2 * N * N; e += THREADS) {
-        const int c = e / (N * N), rem = e % (N * N);
-        sm[c * SP + (rem / N) * LD + rem % N] = u[e];
-    }
-    __syncthreads();
-
-    for (int step = 0; step < K; ++step) {
-        if (step == K - 1) {          // keep u^{K-1} in HBM for the residual
-            for (int e = tid; e < 2 * N * N; e += THREADS) {
-                const int c = e / (N * N), rem = e % (N * N);
-                u[e] = sm[c * SP + (rem / N) * LD + rem % N];
-            }
-        }
-        // explicit reaction at this lane's row positions (both species read, own species kept)
+    run_solve<T, N, THREADS>(sm, u, b, dt, pa, [&]() {
         T zr[P], zi[P];
         dispatch_model(model, [&](auto MD) {
             static_for<0, P>([&](auto Mi) {
@@ -416,39 +433,7 @@ __global__ __launch_bounds__(8 * N) void k_fused_q(const DevSolve *S, const int 
         __syncthreads();
         Q::inverse(L, [&](int k) { return ms[ln * LD + k]; }, [&](int j, T v) { ms[ln * LD + j] = v; });
         __syncthreads();
-    }
-
-    double d = 0.0, a = 0.0;
-    int bad = 0;
-    for (int e = tid; e < 2 * N * N; e += THREADS) {
-        const int c = e / (N * N), rem = e % (N * N);
-        const T nv = sm[c * SP + (rem / N) * LD + rem % N];
-        const double dv = fabs((double)nv - (double)u[e]);
-        const double av = fabs((double)nv);
-        if (!isfinite((double)nv)) bad = 1;
-        d = fmax(d, isnan(dv) ? 0.0 : dv);
-        a = fmax(a, isnan(av) ? 0.0 : av);
-        u[e] = nv;
-    }
-    d = wave_max(d);
-    a = wave_max(a);
-    bad = wave_or(bad);
-    const int wv = tid / 64;
-    if ((tid & 63) == 0) {
-        red[wv] = d;
-        red[WAVES + wv] = a;
-        if (bad) R.bad[b] = 1;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double dm = 0.0, am = 0.0;
-        for (int w = 0; w < WAVES; ++w) {
-            dm = fmax(dm, red[w]);
-            am = fmax(am, red[WAVES + w]);
-        }
-        R.resid[b] = (unsigned long long)__double_as_longlong(dm);
-        R.maxabs[b] = (unsigned long long)__double_as_longlong(am);
-    }
+    });
 }
 
 // Spectral tables for the fused back-end:
@@ -530,82 +515,55 @@ int plain_tables(int n, PlainTables *out)
     return CIL_OK;
 }
 
-// One group: solves with one grid side n, one back-end, one element type.
-struct Group {
-    int n = 0;
-    bool fused = false;
-    bool quad = true;             // fused: quad-lane line transforms (else one lane per line)
-    bool f32 = false;
-    bool polish = false;          // FP64 copies of FP32 solves
-    std::vector<int> active;      // solve indices
-    DevSolve *dsolves = nullptr;  // device array indexed by solve
-    void *state = nullptr;        // base of the element buffer
-    int *dlist = nullptr;         // device list buffer (capacity B)
-    void *work = nullptr;         // plain: 2 buffers [cap][2][n][n]
-    size_t work_cap = 0;
-    void *tables = nullptr;       // fused: spectral tables
-};
-
 int fused_supported(int n, bool f32)
 {
     return f32 ? (n == 32 || n == 64 || n == 128) : (n == 32 || n == 64);
 }
 
 template <typename T>
-int launch_fused(const Group &g, int nl, int model, double dt, int K, StepResults R,
-                 hipStream_t st)
+int launch_persistent(int n, bool quad, int nl, const DevSolve *S, const int *list, T *state, const T *tables,
+                      int model, double dt, const PersistArgs &pa, hipStream_t st)
 {
-    const DevSolve *S = g.dsolves;
-    T *u = (T *)g.state;
-    const T *tb = (const T *)g.tables;
-    const int ni = g.n == 32 ? 0 : (g.n == 64 ? 1 : 2);
-    if (g.quad) {
-        static const char *q32[3] = {"k_fused_q_f32_n32", "k_fused_q_f32_n64", "k_fused_q_f32_n128"};
-        static const char *q64[3] = {"k_fused_q_f64_n32", "k_fused_q_f64_n64", "k_fused_q_f64_n128"};
-        const ProfMark pm = prof_begin(std::is_same<T, float>::value ? q32[ni] : q64[ni], st);
-        switch (g.n) {
-        case 32:
-            hipLaunchKernelGGL((k_fused_q<T, 32>), dim3(nl), dim3(256), 0, st, S, g.dlist, u, tb, model, dt, K, R);
-            break;
-        case 64:
-            hipLaunchKernelGGL((k_fused_q<T, 64>), dim3(nl), dim3(512), 0, st, S, g.dlist, u, tb, model, dt, K, R);
-            break;
-        default:
-            if constexpr (std::is_same<T, float>::value) {
-                hipLaunchKernelGGL((k_fused_q<T, 128>), dim3(nl), dim3(1024), 0, st, S, g.dlist, u, tb, model, dt, K,
-                                   R);
-            } else {
-                return set_error(CIL_EUNSUPPORTED, "fused FP64 stepper supports n = 32, 64");
-            }
-            break;
-        }
-        prof_end(pm, st);
-        return check_launch("k_fused_q");
-    }
-    static const char *names32[3] = {"k_fused_f32_n32", "k_fused_f32_n64", "k_fused_f32_n128"};
-    static const char *names64[3] = {"k_fused_f64_n32", "k_fused_f64_n64", "k_fused_f64_n128"};
-    const ProfMark pm = prof_begin(std::is_same<T, float>::value ? names32[ni] : names64[ni], st);
-    switch (g.n) {
-    case 32:
-        hipLaunchKernelGGL((k_fused<T, 32>), dim3(nl), dim3(64), 0, st, S, g.dlist, u, tb, model, dt, K, R);
-        break;
-    case 64:
-        hipLaunchKernelGGL((k_fused<T, 64>), dim3(nl), dim3(128), 0, st, S, g.dlist, u, tb, model, dt, K, R);
-        break;
-    default:
-        if constexpr (std::is_same<T, float>::value) {
-            hipLaunchKernelGGL((k_fused<T, 128>), dim3(nl), dim3(256), 0, st, S, g.dlist, u, tb, model, dt, K, R);
-        } else {
-            return set_error(CIL_EUNSUPPORTED, "fused FP64 stepper supports n = 32, 64");
-        }
-        break;
+    const bool f32 = std::is_same<T, float>::value;
+    const int ni = n == 32 ? 0 : (n == 64 ? 1 : 2);
+    static const char *nq32[3] = {"k_fused_q_f32_n32", "k_fused_q_f32_n64", "k_fused_q_f32_n128"};
+    static const char *nq64[3] = {"k_fused_q_f64_n32", "k_fused_q_f64_n64", "k_fused_q_f64_n128"};
+    static const char *nl32[3] = {"k_fused_f32_n32", "k_fused_f32_n64", "k_fused_f32_n128"};
+    static const char *nl64[3] = {"k_fused_f64_n32", "k_fused_f64_n64", "k_fused_f64_n128"};
+    const char *name = quad ? (f32 ? nq32[ni] : nq64[ni]) : (f32 ? nl32[ni] : nl64[ni]);
+    if (!f32 && n == 128) return set_error(CIL_EUNSUPPORTED, "fused FP64 stepper supports n = 32, 64");
+    const ProfMark pm = prof_begin(name, st);
+    if (quad) {
+        if (n == 32)
+            hipLaunchKernelGGL((k_fused_q<T, 32>), dim3(nl), dim3(256), 0, st, S, list, state, tables, model, dt, pa);
+        else if (n == 64)
+            hipLaunchKernelGGL((k_fused_q<T, 64>), dim3(nl), dim3(512), 0, st, S, list, state, tables, model, dt, pa);
+        else if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL((k_fused_q<T, 128>), dim3(nl), dim3(1024), 0, st, S, list, state, tables, model, dt, pa);
+    } else {
+        if (n == 32)
+            hipLaunchKernelGGL((k_fused<T, 32>), dim3(nl), dim3(64), 0, st, S, list, state, tables, model, dt, pa);
+        else if (n == 64)
+            hipLaunchKernelGGL((k_fused<T, 64>), dim3(nl), dim3(128), 0, st, S, list, state, tables, model, dt, pa);
+        else if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL((k_fused<T, 128>), dim3(nl), dim3(256), 0, st, S, list, state, tables, model, dt, pa);
     }
     prof_end(pm, st);
-    return check_launch("k_fused");
+    return check_launch(name);
 }
 
+// One plain group: solves with one grid side n, advanced in lockstep.
+struct PlainGroup {
+    int n = 0;
+    std::vector<int> active;
+    int *dlist = nullptr;
+    void *work = nullptr;         // 2 buffers [cap][2][n][n]
+    size_t work_cap = 0;
+};
+
 template <typename T>
-int launch_plain(Group &g, int nl, int model, double dt, int K, StepResults R, hipStream_t st)
+int launch_plain(PlainGroup &g, const DevSolve *S, T *u, int nl, int model, double dt, int K, StepResults R,
+                 hipStream_t st)
 {
     PlainTables tb;
     CIL_TRY(plain_tables<T>(g.n, &tb));
@@ -614,17 +572,15 @@ int launch_plain(Group &g, int nl, int model, double dt, int K, StepResults R, h
     T *Bw = A + g.work_cap * 2 * N2;
     const dim3 blk(256);
     const dim3 grid1((N2 + 255) / 256, nl), grid2((2 * N2 + 255) / 256, nl);
-    T *u = (T *)g.state;
     const ProfMark pm = prof_begin(std::is_same<T, float>::value ? "plain_step_f32" : "plain_step_f64", st);
     for (int k = 0; k < K; ++k) {
         const int check = (k == K - 1);
-        hipLaunchKernelGGL(k_plain_reaction<T>, grid1, blk, 0, st, g.dsolves, g.dlist, u, A, n, model, dt);
+        hipLaunchKernelGGL(k_plain_reaction<T>, grid1, blk, 0, st, S, g.dlist, u, A, n, model, dt);
         hipLaunchKernelGGL(k_plain_rows_fwd<T>, grid2, blk, 0, st, g.dlist, A, Bw, (const T *)tb.Ct, n);
-        hipLaunchKernelGGL(k_plain_cols_fwd_div<T>, grid2, blk, 0, st, g.dsolves, g.dlist, Bw, A,
-                           (const T *)tb.C, tb.lam, n, dt);
+        hipLaunchKernelGGL(k_plain_cols_fwd_div<T>, grid2, blk, 0, st, S, g.dlist, Bw, A, (const T *)tb.C, tb.lam, n,
+                           dt);
         hipLaunchKernelGGL(k_plain_cols_inv<T>, grid2, blk, 0, st, g.dlist, A, Bw, (const T *)tb.Cw, n);
-        hipLaunchKernelGGL(k_plain_rows_inv<T>, grid2, blk, 0, st, g.dsolves, g.dlist, Bw, u,
-                           (const T *)tb.Cw, n, check, R);
+        hipLaunchKernelGGL(k_plain_rows_inv<T>, grid2, blk, 0, st, S, g.dlist, Bw, u, (const T *)tb.Cw, n, check, R);
     }
     prof_end(pm, st);
     return check_launch("plain stepper");
@@ -651,18 +607,189 @@ struct CallBuffers {
     }
 };
 
+namespace {
+
+struct SimCtx {
+    int model;
+    double dt, tol;
+    int64_t max_steps;
+    int check;
+    double floor_coef32;          // FP32 floor per unit max|u| (0 if no floor test)
+    hipStream_t st;
+    CallBuffers *cb;
+    std::vector<int64_t> steps;   // per solve (host)
+    std::vector<double> fres;
+    std::vector<int> status;
+};
+
+// Spectral tables for the solves in `ids` (side n): one per distinct (h, nu);
+// sets hs[b].tab.  Returns the device table buffer.
+template <typename T>
+int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSolve> &hs, void **tables)
+{
+    std::map<std::tuple<double, double, double>, int> uniq;
+    std::vector<TabSpec> specs;
+    for (int b : ids) {
+        auto key = std::make_tuple(hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]);
+        auto it = uniq.find(key);
+        if (it == uniq.end()) {
+            it = uniq.emplace(key, (int)specs.size()).first;
+            specs.push_back(TabSpec{hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]});
+        }
+        hs[b].tab = it->second;
+    }
+    void *dspecs;
+    CIL_TRY(c.cb->alloc(&dspecs, sizeof(TabSpec) * specs.size()));
+    CIL_HIP(hipMemcpyAsync(dspecs, specs.data(), sizeof(TabSpec) * specs.size(), hipMemcpyHostToDevice, c.st));
+    CIL_TRY(c.cb->alloc(tables, sizeof(T) * (size_t)2 * n * n * specs.size()));
+    dim3 grid((2 * n * n + 255) / 256, (unsigned)specs.size());
+    hipLaunchKernelGGL(k_make_tables<T>, grid, dim3(256), 0, c.st, (const TabSpec *)dspecs, (int)specs.size(), n, c.dt,
+                       (T *)*tables);
+    return check_launch("k_make_tables");
+}
+
+// Fused solves, all sides in one go: every workgroup runs its solve from
+// steps[b] until its stop rule fires.  `dsteps/dres/dstat` are per-solve
+// device arrays; the host copies are refreshed after the launches.
+template <typename T>
+int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<DevSolve> &hs, DevSolve *dS, T *state,
+              bool quad, double floor_coef, long long *dsteps, double *dres, int *dstat)
+{
+    if (byn.empty()) return CIL_OK;
+    std::vector<void *> tabs;
+    for (auto &kv : byn) {
+        void *t;
+        CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &t));
+        tabs.push_back(t);
+    }
+    const int B = (int)hs.size();
+    CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
+    std::vector<long long> hsteps(c.steps.begin(), c.steps.end());
+    CIL_HIP(hipMemcpyAsync(dsteps, hsteps.data(), sizeof(long long) * B, hipMemcpyHostToDevice, c.st));
+    PersistArgs pa{(long long)c.max_steps, c.tol, c.check, floor_coef, dsteps, dres, dstat};
+    size_t gi = 0;
+    for (auto &kv : byn) {
+        int *dl;
+        CIL_TRY(c.cb->alloc((void **)&dl, sizeof(int) * kv.second.size()));
+        CIL_HIP(hipMemcpyAsync(dl, kv.second.data(), sizeof(int) * kv.second.size(), hipMemcpyHostToDevice, c.st));
+        CIL_TRY(launch_persistent<T>(kv.first, quad, (int)kv.second.size(), dS, dl, state, (const T *)tabs[gi++],
+                                     c.model, c.dt, pa, c.st));
+    }
+    std::vector<double> hres(B);
+    std::vector<int> hstat(B);
+    CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipStreamSynchronize(c.st));
+    for (auto &kv : byn)
+        for (int b : kv.second) {
+            c.steps[b] = hsteps[b];
+            c.fres[b] = hres[b];
+            c.status[b] = hstat[b];
+        }
+    return CIL_OK;
+}
+
+// Plain solves: host-driven lockstep loop from a common step `start`; a
+// launch per stage per step, the residual read back every check_every steps.
+template <typename T>
+int run_plain(SimCtx &c, std::vector<PlainGroup> &groups, const DevSolve *dS, T *state, int64_t start,
+              double floor_coef, StepResults R, int B)
+{
+    std::vector<unsigned long long> h_resid(B), h_maxabs(B);
+    std::vector<int> h_bad(B);
+    int64_t step = start;
+    auto any_active = [&]() {
+        for (auto &g : groups)
+            if (!g.active.empty()) return true;
+        return false;
+    };
+    while (step < c.max_steps && any_active()) {
+        const int64_t next = std::min<int64_t>(c.max_steps, (step / c.check + 1) * c.check);
+        const int K = (int)(next - step);
+        for (auto &g : groups) {
+            if (g.active.empty()) continue;
+            const int nl = (int)g.active.size();
+            CIL_HIP(hipMemcpyAsync(g.dlist, g.active.data(), sizeof(int) * nl, hipMemcpyHostToDevice, c.st));
+            hipLaunchKernelGGL(k_clear_results, dim3((nl + 255) / 256), dim3(256), 0, c.st, g.dlist, nl, R);
+            CIL_TRY(launch_plain<T>(g, dS, state, nl, c.model, c.dt, K, R, c.st));
+        }
+        CIL_HIP(hipMemcpyAsync(h_resid.data(), R.resid, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, c.st));
+        CIL_HIP(hipMemcpyAsync(h_maxabs.data(), R.maxabs, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, c.st));
+        CIL_HIP(hipMemcpyAsync(h_bad.data(), R.bad, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
+        CIL_HIP(hipStreamSynchronize(c.st));
+        step = next;
+        for (auto &g : groups) {
+            std::vector<int> keep;
+            for (int b : g.active) {
+                double dmax, amax;
+                std::memcpy(&dmax, &h_resid[b], 8);
+                std::memcpy(&amax, &h_maxabs[b], 8);
+                const double r = dmax / c.dt;
+                c.steps[b] = step;
+                if (h_bad[b]) {
+                    c.status[b] = CIL_SOLVE_NONFINITE;
+                    c.fres[b] = NAN;
+                    continue;
+                }
+                c.fres[b] = r;
+                if (c.tol > 0.0 && r < c.tol) {
+                    c.status[b] = CIL_SOLVE_OK;
+                    continue;
+                }
+                if (c.tol > 0.0 && floor_coef > 0.0 && r < floor_coef * amax) {
+                    c.status[b] = CIL_SOLVE_FP32_FLOOR;
+                    continue;
+                }
+                if (step >= c.max_steps) {
+                    c.status[b] = c.tol > 0.0 ? CIL_SOLVE_MAXSTEPS : CIL_SOLVE_OK;
+                    continue;
+                }
+                keep.push_back(b);
+            }
+            g.active.swap(keep);
+        }
+    }
+    return CIL_OK;
+}
+
+template <typename T>
+int make_plain_groups(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<PlainGroup> &out)
+{
+    for (auto &kv : byn) {
+        PlainGroup g;
+        g.n = kv.first;
+        g.active = kv.second;
+        g.work_cap = kv.second.size();
+        CIL_TRY(c.cb->alloc((void **)&g.dlist, sizeof(int) * g.work_cap));
+        CIL_TRY(c.cb->alloc(&g.work, sizeof(T) * (size_t)2 * g.work_cap * 2 * g.n * g.n));
+        out.push_back(g);
+    }
+    return CIL_OK;
+}
+
+}  // namespace
+
 int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs, int B, void *state,
-                  const int64_t *offs, const cil_stepping *stp, cil_solve_report *reports,
-                  hipStream_t st)
+                  const int64_t *offs, const cil_stepping *stp, cil_solve_report *reports, hipStream_t st)
 {
     const bool f32 = (prec == CIL_FP32);
-    const double dt = stp->dt;
-    const int64_t max_steps = stp->max_steps;
-    const double tol = stp->tol;
-    const int check = stp->check_every;
     const int floor_ulps = stp->fp32_floor_ulps > 0 ? stp->fp32_floor_ulps : 8;
-    const bool polish = f32 && stp->polish && tol > 0.0;
     CallBuffers cb;
+    SimCtx c;
+    c.model = (int)model;
+    c.dt = stp->dt;
+    c.tol = stp->tol;
+    c.max_steps = stp->max_steps;
+    c.check = stp->check_every;
+    c.floor_coef32 = (f32 && stp->tol > 0.0) ? floor_ulps * std::ldexp(1.0, -24) / stp->dt : 0.0;
+    c.st = st;
+    c.cb = &cb;
+    c.steps.assign(B, 0);
+    c.fres.assign(B, 0.0);
+    c.status.assign(B, CIL_SOLVE_OK);
+    const bool polish = f32 && stp->polish && stp->tol > 0.0;
+    const bool quad = stp->path != CIL_PATH_FUSED_LINE;
 
     std::vector<DevSolve> hs(B);
     std::vector<int64_t> elems(B);
@@ -677,255 +804,106 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         d.nu[0] = pr.nu[0];
         d.nu[1] = pr.nu[1];
         for (int k = 0; k < 4; ++k) d.p[k] = pr.p[k];
-        d.tab = 0;
         hs[b] = d;
         elems[b] = 2ll * pr.n * pr.n;
         total += elems[b];
     }
 
-    // groups by (n); the back-end per group
-    std::map<int, std::vector<int>> byn;
-    for (int b = 0; b < B; ++b) byn[hs[b].n].push_back(b);
-    std::vector<Group> groups;
-    for (auto &kv : byn) {
-        Group g;
-        g.n = kv.first;
-        g.f32 = f32;
-        const bool fs = fused_supported(g.n, f32);
+    // phase 1: fused sides run persistently, the rest in the plain lockstep loop
+    std::map<int, std::vector<int>> fused_byn, plain_byn;
+    for (int b = 0; b < B; ++b) {
+        const int n = hs[b].n;
+        const bool fs = fused_supported(n, f32);
         if (stp->path >= CIL_PATH_FUSED && !fs)
-            return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", g.n,
-                             f32 ? "FP32" : "FP64");
-        g.fused = fs && stp->path != CIL_PATH_PLAIN;
-        g.quad = stp->path != CIL_PATH_FUSED_LINE;
-        g.active = kv.second;
-        groups.push_back(g);
+            return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", n, f32 ? "FP32" : "FP64");
+        if (fs && stp->path != CIL_PATH_PLAIN) fused_byn[n].push_back(b);
+        else plain_byn[n].push_back(b);
     }
-
-    // spectral tables (fused groups): one per distinct (n, h, nu)
-    for (auto &g : groups) {
-        if (!g.fused) continue;
-        std::map<std::tuple<double, double, double>, int> uniq;
-        std::vector<TabSpec> specs;
-        for (int b : g.active) {
-            auto key = std::make_tuple(hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]);
-            auto it = uniq.find(key);
-            if (it == uniq.end()) {
-                it = uniq.emplace(key, (int)specs.size()).first;
-                specs.push_back(TabSpec{hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]});
-            }
-            hs[b].tab = it->second;
-        }
-        void *dspecs;
-        CIL_TRY(cb.alloc(&dspecs, sizeof(TabSpec) * specs.size()));
-        CIL_HIP(hipMemcpyAsync(dspecs, specs.data(), sizeof(TabSpec) * specs.size(),
-                               hipMemcpyHostToDevice, st));
-        const size_t tsz = (size_t)2 * g.n * g.n * specs.size();
-        CIL_TRY(cb.alloc(&g.tables, tsz * (f32 ? 4 : 8)));
-        dim3 grid((2 * g.n * g.n + 255) / 256, (unsigned)specs.size());
-        if (f32)
-            hipLaunchKernelGGL(k_make_tables<float>, grid, dim3(256), 0, st, (const TabSpec *)dspecs,
-                               (int)specs.size(), g.n, dt, (float *)g.tables);
-        else
-            hipLaunchKernelGGL(k_make_tables<double>, grid, dim3(256), 0, st, (const TabSpec *)dspecs,
-                               (int)specs.size(), g.n, dt, (double *)g.tables);
-        CIL_TRY(check_launch("k_make_tables"));
-    }
-
-    DevSolve *dsolves;
-    CIL_TRY(cb.alloc((void **)&dsolves, sizeof(DevSolve) * B));
-    CIL_HIP(hipMemcpyAsync(dsolves, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
-    for (auto &g : groups) {
-        g.dsolves = dsolves;
-        g.state = state;
-        CIL_TRY(cb.alloc((void **)&g.dlist, sizeof(int) * g.active.size()));
-        if (!g.fused) {
-            g.work_cap = g.active.size();
-            CIL_TRY(cb.alloc(&g.work, (size_t)2 * g.work_cap * 2 * g.n * g.n * (f32 ? 4 : 8)));
-        }
-    }
-
+    DevSolve *dS;
+    long long *dsteps;
+    double *dres;
+    int *dstat;
+    CIL_TRY(cb.alloc((void **)&dS, sizeof(DevSolve) * B));
+    CIL_TRY(cb.alloc((void **)&dsteps, sizeof(long long) * B));
+    CIL_TRY(cb.alloc((void **)&dres, sizeof(double) * B));
+    CIL_TRY(cb.alloc((void **)&dstat, sizeof(int) * B));
+    CIL_TRY(fill_zero(dstat, sizeof(int) * B, st));
     StepResults R;
     CIL_TRY(cb.alloc((void **)&R.resid, sizeof(unsigned long long) * B));
     CIL_TRY(cb.alloc((void **)&R.maxabs, sizeof(unsigned long long) * B));
     CIL_TRY(cb.alloc((void **)&R.bad, sizeof(int) * B));
-    std::vector<unsigned long long> h_resid(B), h_maxabs(B);
-    std::vector<int> h_bad(B);
 
-    // FP64 polish groups (created lazily, one per n)
-    std::map<int, Group> pol;
-    DevSolve *dsolves64 = nullptr;
-    double *state64 = nullptr;
-    std::vector<DevSolve> hs64;
-    if (polish) {
-        hs64 = hs;
+    if (f32) CIL_TRY(run_fused<float>(c, fused_byn, hs, dS, (float *)state, quad, c.floor_coef32, dsteps, dres, dstat));
+    else CIL_TRY(run_fused<double>(c, fused_byn, hs, dS, (double *)state, quad, 0.0, dsteps, dres, dstat));
+    if (!plain_byn.empty()) {
+        CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+        std::vector<PlainGroup> pg;
+        if (f32) {
+            CIL_TRY(make_plain_groups<float>(c, plain_byn, pg));
+            CIL_TRY(run_plain<float>(c, pg, dS, (float *)state, 0, c.floor_coef32, R, B));
+        } else {
+            CIL_TRY(make_plain_groups<double>(c, plain_byn, pg));
+            CIL_TRY(run_plain<double>(c, pg, dS, (double *)state, 0, 0.0, R, B));
+        }
+    }
+
+    // phase 2: FP32 solves stopped at the FP32 floor continue in FP64
+    std::vector<int64_t> steps64(B, 0);
+    std::vector<int> promoted;
+    for (int b = 0; b < B; ++b)
+        if (polish && c.status[b] == CIL_SOLVE_FP32_FLOOR) promoted.push_back(b);
+    if (!promoted.empty()) {
+        std::vector<DevSolve> hs64 = hs;
         int64_t t = 0;
         for (int b = 0; b < B; ++b) {
             hs64[b].off = t;
             t += elems[b];
         }
+        double *state64;
+        DevSolve *dS64;
+        int *dprom;
         CIL_TRY(cb.alloc((void **)&state64, sizeof(double) * std::max<int64_t>(t, 1)));
-        CIL_TRY(cb.alloc((void **)&dsolves64, sizeof(DevSolve) * B));
-        // FP64 spectral tables are made per polish group below
-    }
-
-    std::vector<int64_t> steps(B, 0), steps64(B, 0);
-    std::vector<double> fres(B, 0.0);
-    std::vector<int> status(B, CIL_SOLVE_OK);
-    std::vector<char> in_polish(B, 0);
-
-    int64_t step = 0;
-    auto any_active = [&]() {
-        for (auto &g : groups)
-            if (!g.active.empty()) return true;
-        for (auto &kv : pol)
-            if (!kv.second.active.empty()) return true;
-        return false;
-    };
-
-    while (step < max_steps && any_active()) {
-        const int64_t next = std::min<int64_t>(max_steps, (step / check + 1) * check);
-        const int K = (int)(next - step);
-        std::vector<Group *> run;
-        for (auto &g : groups)
-            if (!g.active.empty()) run.push_back(&g);
-        for (auto &kv : pol)
-            if (!kv.second.active.empty()) run.push_back(&kv.second);
-        for (Group *g : run) {
-            const int nl = (int)g->active.size();
-            CIL_HIP(hipMemcpyAsync(g->dlist, g->active.data(), sizeof(int) * nl, hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(k_clear_results, dim3((nl + 255) / 256), dim3(256), 0, st, g->dlist, nl, R);
-            const bool gf32 = g->f32 && !g->polish;
-            if (g->fused) {
-                if (gf32) CIL_TRY(launch_fused<float>(*g, nl, (int)model, dt, K, R, st));
-                else CIL_TRY(launch_fused<double>(*g, nl, (int)model, dt, K, R, st));
-            } else {
-                if (gf32) CIL_TRY(launch_plain<float>(*g, nl, (int)model, dt, K, R, st));
-                else CIL_TRY(launch_plain<double>(*g, nl, (int)model, dt, K, R, st));
-            }
+        CIL_TRY(cb.alloc((void **)&dS64, sizeof(DevSolve) * B));
+        CIL_TRY(cb.alloc((void **)&dprom, sizeof(int) * promoted.size()));
+        CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+        CIL_HIP(hipMemcpyAsync(dS64, hs64.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+        CIL_HIP(hipMemcpyAsync(dprom, promoted.data(), sizeof(int) * promoted.size(), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL((k_convert_solves<float, double>), dim3(16, (unsigned)promoted.size()), dim3(256), 0, st,
+                           (const DevSolve *)dS, (const DevSolve *)dS64, dprom, (const float *)state, state64);
+        CIL_TRY(check_launch("k_convert_solves"));
+        std::vector<int64_t> before(B);
+        for (int b = 0; b < B; ++b) before[b] = c.steps[b];
+        std::map<int, std::vector<int>> fz;                            // n -> solves (fused FP64)
+        std::map<std::pair<int, int64_t>, std::vector<int>> pz;        // (n, start) -> solves (plain FP64)
+        for (int b : promoted) {
+            c.status[b] = CIL_SOLVE_OK;
+            if (fused_supported(hs[b].n, false) && stp->path != CIL_PATH_PLAIN) fz[hs[b].n].push_back(b);
+            else pz[std::make_pair(hs[b].n, c.steps[b])].push_back(b);
         }
-        CIL_HIP(hipMemcpyAsync(h_resid.data(), R.resid, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, st));
-        CIL_HIP(hipMemcpyAsync(h_maxabs.data(), R.maxabs, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, st));
-        CIL_HIP(hipMemcpyAsync(h_bad.data(), R.bad, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-        CIL_HIP(hipStreamSynchronize(st));
-        step = next;
-
-        std::map<int, std::vector<int>> promote;   // n -> solves moving to FP64
-        for (Group *g : run) {
-            std::vector<int> keep;
-            for (int b : g->active) {
-                double dmax, amax;
-                std::memcpy(&dmax, &h_resid[b], 8);
-                std::memcpy(&amax, &h_maxabs[b], 8);
-                const double r = dmax / dt;
-                steps[b] = step;
-                if (g->polish) steps64[b] += K;
-                if (h_bad[b]) {
-                    status[b] = CIL_SOLVE_NONFINITE;
-                    fres[b] = NAN;
-                    continue;
-                }
-                fres[b] = r;
-                if (tol > 0.0 && r < tol) continue;                       // converged
-                if (g->f32 && !g->polish && tol > 0.0) {
-                    const double floor_r = floor_ulps * std::ldexp(1.0, -24) * amax / dt;
-                    if (r < floor_r) {
-                        if (polish) promote[g->n].push_back(b);
-                        else status[b] = CIL_SOLVE_FP32_FLOOR;
-                        continue;
-                    }
-                }
-                if (step >= max_steps) {
-                    if (tol > 0.0) status[b] = CIL_SOLVE_MAXSTEPS;
-                    continue;
-                }
-                keep.push_back(b);
-            }
-            g->active.swap(keep);
+        CIL_TRY(run_fused<double>(c, fz, hs64, dS64, state64, quad, 0.0, dsteps, dres, dstat));
+        if (!pz.empty()) CIL_HIP(hipMemcpyAsync(dS64, hs64.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+        for (auto &kv : pz) {
+            std::map<int, std::vector<int>> one;
+            one[kv.first.first] = kv.second;
+            std::vector<PlainGroup> pg;
+            CIL_TRY(make_plain_groups<double>(c, one, pg));
+            CIL_TRY(run_plain<double>(c, pg, dS64, state64, kv.first.second, 0.0, R, B));
         }
-        for (auto &kv : promote) {
-            const int n = kv.first;
-            auto it = pol.find(n);
-            if (it == pol.end()) {
-                Group g;
-                g.n = n;
-                g.f32 = true;
-                g.polish = true;
-                g.fused = fused_supported(n, false) && stp->path != CIL_PATH_PLAIN;
-                g.quad = stp->path != CIL_PATH_FUSED_LINE;
-                g.state = state64;
-                g.dsolves = dsolves64;
-                CIL_TRY(cb.alloc((void **)&g.dlist, sizeof(int) * B));
-                if (g.fused) {
-                    // FP64 tables for this n: one per distinct (h, nu) among all solves of side n
-                    std::map<std::tuple<double, double, double>, int> uniq;
-                    std::vector<TabSpec> specs;
-                    for (int b = 0; b < B; ++b) {
-                        if (hs[b].n != n) continue;
-                        auto key = std::make_tuple(hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]);
-                        auto jt = uniq.find(key);
-                        if (jt == uniq.end()) {
-                            jt = uniq.emplace(key, (int)specs.size()).first;
-                            specs.push_back(TabSpec{hs[b].inv_h2, hs[b].nu[0], hs[b].nu[1]});
-                        }
-                        hs64[b].tab = jt->second;
-                    }
-                    void *dspecs;
-                    CIL_TRY(cb.alloc(&dspecs, sizeof(TabSpec) * specs.size()));
-                    CIL_HIP(hipMemcpyAsync(dspecs, specs.data(), sizeof(TabSpec) * specs.size(),
-                                           hipMemcpyHostToDevice, st));
-                    CIL_TRY(cb.alloc(&g.tables, sizeof(double) * 2 * n * n * specs.size()));
-                    dim3 grid((2 * n * n + 255) / 256, (unsigned)specs.size());
-                    hipLaunchKernelGGL(k_make_tables<double>, grid, dim3(256), 0, st,
-                                       (const TabSpec *)dspecs, (int)specs.size(), n, dt,
-                                       (double *)g.tables);
-                    CIL_TRY(check_launch("k_make_tables"));
-                } else {
-                    g.work_cap = B;
-                    CIL_TRY(cb.alloc(&g.work, (size_t)2 * B * 2 * n * n * sizeof(double)));
-                }
-                CIL_HIP(hipMemcpyAsync(dsolves64, hs64.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
-                it = pol.emplace(n, g).first;
-            }
-            Group &pg = it->second;
-            const int nl = (int)kv.second.size();
-            CIL_HIP(hipMemcpyAsync(pg.dlist, kv.second.data(), sizeof(int) * nl, hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL((k_convert_solves<float, double>), dim3(16, nl), dim3(256), 0, st,
-                               (const DevSolve *)dsolves, (const DevSolve *)dsolves64, pg.dlist,
-                               (const float *)state, state64);
-            CIL_TRY(check_launch("k_convert_solves"));
-            for (int b : kv.second) {
-                pg.active.push_back(b);
-                in_polish[b] = 1;
-            }
-            CIL_HIP(hipStreamSynchronize(st));
-        }
-    }
-
-    // polished solves: FP64 result rounded back into the caller's FP32 state
-    if (polish) {
-        std::vector<int> done;
-        for (int b = 0; b < B; ++b)
-            if (in_polish[b]) done.push_back(b);
-        if (!done.empty()) {
-            int *dl;
-            CIL_TRY(cb.alloc((void **)&dl, sizeof(int) * done.size()));
-            CIL_HIP(hipMemcpyAsync(dl, done.data(), sizeof(int) * done.size(), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL((k_convert_solves<double, float>), dim3(16, (unsigned)done.size()), dim3(256),
-                               0, st, (const DevSolve *)dsolves64, (const DevSolve *)dsolves, dl,
-                               (const double *)state64, (float *)state);
-            CIL_TRY(check_launch("k_convert_solves"));
-        }
+        for (int b : promoted) steps64[b] = c.steps[b] - before[b];
+        hipLaunchKernelGGL((k_convert_solves<double, float>), dim3(16, (unsigned)promoted.size()), dim3(256), 0, st,
+                           (const DevSolve *)dS64, (const DevSolve *)dS, dprom, (const double *)state64, (float *)state);
+        CIL_TRY(check_launch("k_convert_solves"));
     }
     CIL_HIP(hipStreamSynchronize(st));
 
     int rc = CIL_OK;
     for (int b = 0; b < B; ++b) {
-        if (status[b] == CIL_SOLVE_NONFINITE) rc = CIL_ENONFINITE;
+        if (c.status[b] == CIL_SOLVE_NONFINITE) rc = CIL_ENONFINITE;
         if (reports) {
-            reports[b].steps_taken = steps[b];
+            reports[b].steps_taken = c.steps[b];
             reports[b].steps_fp64 = f32 ? steps64[b] : 0;
-            reports[b].final_resid = fres[b];
-            reports[b].status = status[b];
+            reports[b].final_resid = c.fres[b];
+            reports[b].status = c.status[b];
             reports[b].reserved = 0;
         }
     }
