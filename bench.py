@@ -3,18 +3,21 @@
 One step = one pass of the whole hot path over one batch of synthetic input:
   500 Gierer-Meinhardt (source form) solves on 64x64 grids from randomised
   initial states (+-1% multiplicative noise) to stationarity (FP64 residual
-  < 1e-8; FP32 stepping with FP64 polish), then the CIL statistic of the two
-  250-pattern halves: canonical distance range, 13 power-law radii fitted to
-  it, per-pair radius bins (62 500 pairs, d = 8192), 200 bootstrap resamples
+  < 1e-8), stepped by the persistent fused kernel in FP64, then the CIL
+  statistic of the two 250-pattern halves stored as FP32: canonical distance
+  range, 13 power-law radii fitted to it, per-pair radius bins (62 500 pairs,
+  d = 8192, split-bf16x3 Gram + canonical re-check), 200 bootstrap resamples
   (Alg. 2bst halves), FP64 mean/covariance/Cholesky and the Gaussian
   log-likelihood of the full-halves vector.
 Initial states are resident on the device before the timed region.
 
 Prints one JSON line.  `value` is stationary patterns/s of the whole step.
-Also reported: CIL pairs/s, the plain FP64 GPU path (one kernel per stage,
-host-driven loop, FP64 distances) timed the same way, the dominant kernel's
-roofline (its durations taken with HIP events on its own stream inside the
-timed region), and the FP64 CPU oracle timed on a bounded sample.
+Also reported: CIL pairs/s, the same step with FP32 stepping (+ FP64 polish),
+the plain FP64 GPU path (one kernel per stage, host-driven loop, FP64
+distances) timed the same way, the dominant kernel's roofline (durations
+from HIP events the library records on the kernel's own stream inside the
+timed region), the Gram's MFMA rate, and the FP64 CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -30,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "gm_source64_stationary"
 VALU_FP32_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+VALU_FP64_PEAK_TFLOPS = 78.6    # MI355X published FP64 vector peak
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
 
 
 def line_dct_flops(N: int, inverse: bool) -> int:
@@ -67,7 +72,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-sample-solves", type=int, default=32)
+    ap.add_argument("--no-fp32-stepping", action="store_true")
+    ap.add_argument("--cpu-sample-solves", type=int, default=96)
     return ap.parse_args()
 
 
@@ -101,29 +107,35 @@ def main():
     idxA = torch.from_numpy(ia).to(dev)
     idxB = torch.from_numpy(ib).to(dev)
     bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
+    pat32 = torch.empty((B, d), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def one_step(state, ics, path):
+    def one_step(state, ics, path, stat_fp32):
+        """Whole hot path; stat_fp32: statistic on FP32 patterns (split-bf16x3 Gram)."""
         state.copy_(ics)
         rep = cil.cil_simulate_patterns(w["model"], state, probs, w["dt"], w["max_steps"], tol=w["tol"],
                                         check_every=w["check_every"], path=path, polish=1)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        A = state[:half].reshape(half, d)
-        Bs = state[half:].reshape(half, d)
+        if stat_fp32 and state.dtype != torch.float32:
+            pat32.copy_(state.reshape(B, d))          # patterns stored as FP32
+            pats = pat32
+        else:
+            pats = state.reshape(B, d)
+        A, Bs = pats[:half], pats[half:]
         lo, hi = cil.cil_distance_range(A, Bs)
         radii = cil.cil_radii(lo, hi, M)
         _, counts = cil.cil_pair_bins(A, Bs, radii, bins=bins)
         _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
         y_obs = torch.tensor(counts / float(half * half), dtype=torch.float64, device=dev)
-        f, ll, me, st = cil.cil_gaussian_loglik(Y, y_obs)
+        out = cil.cil_gaussian_loglik(Y, y_obs)
         ev1.record(stream)
-        return rep, counts, ev0, ev1, (f, ll, me, st)
+        return rep, counts, ev0, ev1, out
 
-    def timed(state, ics, path, steps, warmup, profile=False):
+    def timed(state, ics, path, stat_fp32, steps, warmup, profile=False):
         for _ in range(warmup):
-            one_step(state, ics, path)
+            one_step(state, ics, path, stat_fp32)
         torch.cuda.synchronize()
         if profile:
             cil.cil_profile(True)
@@ -131,7 +143,7 @@ def main():
         cil_ms = 0.0
         reps = []
         for _ in range(steps):
-            rep, counts, e0, e1, out = one_step(state, ics, path)
+            rep, counts, e0, e1, out = one_step(state, ics, path, stat_fp32)
             reps.append(rep)
             torch.cuda.synchronize()
             cil_ms += e0.elapsed_time(e1)
@@ -144,8 +156,9 @@ def main():
             cil.cil_profile(False)
         return el, cil_ms / 1e3, reps, counts, out, prof
 
-    state32 = torch.empty_like(ics32)
-    el, cil_s, reps, counts, out, prof = timed(state32, ics32, cil.CIL_PATH_AUTO, args.steps, args.warmup,
+    # batched path: persistent fused FP64 stepping, statistic on FP32 patterns
+    state64 = torch.empty_like(ics64)
+    el, cil_s, reps, counts, out, prof = timed(state64, ics64, cil.CIL_PATH_AUTO, True, args.steps, args.warmup,
                                                profile=True)
     K = args.steps
     ms_per_step = 1e3 * el / K
@@ -153,37 +166,50 @@ def main():
     pairs = half * half
     pairs_per_s = pairs * K / cil_s if cil_s > 0 else None
     rep = reps[-1]
-    steps_total = int(rep["steps_taken"].sum())
-    steps_fp64 = int(rep["steps_fp64"].sum())
     status_ok = bool(np.all(rep["status"] == 0))
+    solve_steps = sum(int(r["steps_taken"].sum()) for r in reps)
 
-    # dominant kernel: the fused FP32 stepper (most of the step's time)
-    kname = "k_fused_f32_n64"
-    cnt, tot_ms = prof.get(kname, (0, 0.0))
-    roof = None
-    if cnt:
-        # solve-steps run by the FP32 stepper over the timed region
-        solve_steps_fp32 = sum(int((r["steps_taken"] - r["steps_fp64"]).sum()) for r in reps)
-        flops = solve_steps_fp32 * fused_step_flops(n, REACTION_FLOPS[w["model"]])
-        avg_ms = tot_ms / cnt
-        flops_per_launch = flops / cnt
-        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
-                "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "launches": cnt, "avg_launch_ms": round(avg_ms, 4),
-                "flops_per_solve_step": fused_step_flops(n, REACTION_FLOPS[w["model"]])}
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())}
+    kname = max(prof, key=lambda k: prof[k][1]) if prof else None
+    roof = None
+    if kname and kname.startswith("k_fused"):
+        cnt, tot_ms = prof[kname]
+        f64 = "_f64_" in kname
+        flops = solve_steps * fused_step_flops(n, REACTION_FLOPS[w["model"]])
+        avg_ms = tot_ms / cnt
+        achieved = flops / cnt / (avg_ms * 1e-3) / 1e12
+        peak = VALU_FP64_PEAK_TFLOPS if f64 else VALU_FP32_PEAK_TFLOPS
+        roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "launches": cnt,
+                "avg_launch_ms": round(avg_ms, 4), "flops_per_solve_step": fused_step_flops(n, REACTION_FLOPS[w["model"]]),
+                "solve_steps": solve_steps}
+    gram = None
+    if "k_gram_bf16x3" in prof:
+        cnt, tot_ms = prof["k_gram_bf16x3"]
+        executed = 6.0 * d * pairs * K               # three bf16 products per element pair
+        gram = {"kernel": "k_gram_bf16x3", "bound": "mfma", "achieved": round(executed / (tot_ms * 1e-3) / 1e12, 3),
+                "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(executed / (tot_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
+                "avg_launch_ms": round(tot_ms / cnt, 4)}
+
+    fp32_stepping = None
+    if not args.no_fp32_stepping:
+        state32 = torch.empty_like(ics32)
+        e32, c32, r32, _, _, _ = timed(state32, ics32, cil.CIL_PATH_AUTO, True, 1, 1)
+        fp32_stepping = {"patterns_per_s": round(B / e32, 3), "ms_per_step": round(1e3 * e32, 2),
+                         "max_steps": int(r32[-1]["steps_taken"].max()),
+                         "fp64_polish_steps": int(r32[-1]["steps_fp64"].sum()),
+                         "all_converged": bool(np.all(r32[-1]["status"] == 0))}
 
     plain = None
     if not args.no_plain:
-        state64 = torch.empty_like(ics64)
-        pel, pcil_s, preps, pcounts, _, _ = timed(state64, ics64, cil.CIL_PATH_PLAIN, 1, 0)
+        statep = torch.empty_like(ics64)
+        pel, pcil_s, preps, pcounts, _, _ = timed(statep, ics64, cil.CIL_PATH_PLAIN, False, 1, 0)
         plain = {"patterns_per_s": round(B / pel, 3), "pairs_per_s": round(pairs / pcil_s, 1),
                  "ms_per_step": round(1e3 * pel, 2),
                  "speedup_patterns": round(patterns_per_s / (B / pel), 2),
                  "speedup_pairs": round(pairs_per_s / (pairs / pcil_s), 2) if pairs_per_s else None,
-                 "mean_steps": float(preps[-1]["steps_taken"].mean())}
+                 "max_steps": int(preps[-1]["steps_taken"].max())}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -193,13 +219,17 @@ def main():
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
         "value": round(patterns_per_s, 3), "unit": "patterns/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOAD, "model": "gierer_meinhardt_source", "solves": B, "grid": n,
                    "dt": w["dt"], "tol": w["tol"], "radii": M, "bootstrap": n_boot,
-                   "pairs_per_step": pairs, "parallelism": "none (1 GPU)"},
+                   "pairs_per_step": pairs, "stepping": "fp64 fused persistent (quad-lane DCT)",
+                   "statistic": "fp32 patterns, split-bf16x3 MFMA Gram + canonical re-check",
+                   "parallelism": "none (1 GPU)"},
         "pairs_per_s": round(pairs_per_s, 1) if pairs_per_s else None,
-        "solve_steps": steps_total, "solve_steps_fp64_polish": steps_fp64, "all_converged": status_ok,
-        "roofline": roof, "kernels": kernels, "plain_fp64": plain, "cpu_baseline": cpu,
+        "solve_steps": solve_steps // K, "max_solve_steps": int(rep["steps_taken"].max()),
+        "all_converged": status_ok,
+        "roofline": roof, "roofline_gram": gram, "kernels": kernels, "fp32_stepping": fp32_stepping,
+        "plain_fp64": plain, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -221,9 +251,9 @@ def cpu_baseline(w, ics_host, base, n_solves, half, d):
                                               w["max_steps"], w["tol"], w["check_every"], state=ics,
                                               nthreads=threads)
     t_sim = time.perf_counter() - t0
-    k = n_solves // 2
-    A = out[:k].reshape(k, -1)
-    Bm = out[k:2 * k].reshape(k, -1)
+    k = min(64, n_solves // 2)
+    A = out[:k].reshape(k, -1).astype(np.float32)
+    Bm = out[k:2 * k].reshape(k, -1).astype(np.float32)
     t1 = time.perf_counter()
     D = oracle.pair_d2(A, Bm, nthreads=threads)
     t_pairs = time.perf_counter() - t1

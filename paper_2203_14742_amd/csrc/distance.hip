@@ -214,11 +214,15 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
 
 // ---------------------------------------------------------------- canonical
 // Double-double accumulation of the exact squares, one wavefront per pair,
-// then a certified rounding: with the accumulated value S = hi + lo and its
+// then a certified rounding.  The accumulation records whether any of its
+// roundings lost bits: if none did, hi + lo is the exact sum and the
+// hardware's RN(hi + lo) is the correctly rounded value, ties included (the
+// common case for FP32 sets, whose squares are exact).  Otherwise, with the
 // relative error bound delta, RN(sum) = RN(hi + lo) whenever the interval
-// [S - delta S, S + delta S] holds no rounding boundary.  Otherwise (or when
-// forced) lane 0 recomputes the sum exactly in a non-overlapping expansion
-// (Shewchuk's exact summation) and rounds it once, half to even.
+// [S - delta S, S + delta S] holds no rounding boundary.  If neither holds
+// (or when forced) the wavefront recomputes the sum exactly: each lane builds
+// a non-overlapping expansion of its terms (Shewchuk's exact summation),
+// lane 0 merges the 64 expansions and rounds once, half to even.
 
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
 {
@@ -226,44 +230,42 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     const double bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
-__device__ __forceinline__ void dd_add(double &hi, double &lo, double bh, double bl)
+
+// (hi, lo) += (bh, bl); inexact |= some rounding lost bits
+__device__ __forceinline__ void dd_add_t(double &hi, double &lo, double bh, double bl, int &inexact)
 {
-    double s, e;
+    double s, e, t, et, u, eu;
     two_sum(hi, bh, s, e);
-    e += lo + bl;
-    hi = s + e;
-    lo = e - (hi - s);
+    two_sum(lo, bl, t, et);
+    two_sum(e, t, u, eu);
+    inexact |= (et != 0.0) | (eu != 0.0);
+    hi = s + u;
+    lo = u - (hi - s);
 }
 
-template <typename T>
-__device__ double exact_d2_serial(const T *a, const T *b, long long dim)
+constexpr int EXP_CAP = 64;     // a non-overlapping expansion of doubles has < 40 parts
+
+__device__ __forceinline__ void exp_add(double (&part)[EXP_CAP], int &np, double x)
 {
-    double part[96];
-    int np = 0;
-    auto add = [&](double x) {
-        int k = 0;
-        for (int i = 0; i < np; ++i) {
-            double y = part[i];
-            if (fabs(x) < fabs(y)) {
-                const double t = x;
-                x = y;
-                y = t;
-            }
-            const double hi = x + y;
-            const double lo = y - (hi - x);
-            if (lo != 0.0) part[k++] = lo;
-            x = hi;
+    int k = 0;
+    for (int i = 0; i < np; ++i) {
+        double y = part[i];
+        if (fabs(x) < fabs(y)) {
+            const double t = x;
+            x = y;
+            y = t;
         }
-        part[k++] = x;
-        np = k;
-    };
-    for (long long k = 0; k < dim; ++k) {
-        const double d = ld(a + k) - ld(b + k);
-        const double p = d * d;
-        const double e = fma(d, d, -p);
-        add(p);
-        if (e != 0.0) add(e);
+        const double hi = x + y;
+        const double lo = y - (hi - x);
+        if (lo != 0.0) part[k++] = lo;
+        x = hi;
     }
+    part[k++] = x;
+    np = k;
+}
+
+__device__ __forceinline__ double exp_round(const double (&part)[EXP_CAP], int np)
+{
     if (np == 0) return 0.0;
     int m = np;
     double hi = part[--m], lo = 0.0;
@@ -278,6 +280,32 @@ __device__ double exact_d2_serial(const T *a, const T *b, long long dim)
         if (y == x - hi) hi = x;
     }
     return hi;
+}
+
+// Exact sum over the wavefront (all 64 lanes call it); result valid in lane 0.
+template <typename T>
+__device__ double exact_d2_wave(const T *a, const T *b, long long dim, int lane)
+{
+    double part[EXP_CAP];
+    int np = 0;
+    for (long long k = lane; k < dim; k += 64) {
+        const double d = ld(a + k) - ld(b + k);
+        const double p = d * d;
+        const double e = fma(d, d, -p);
+        exp_add(part, np, p);
+        if (e != 0.0) exp_add(part, np, e);
+    }
+    int maxm = np;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxm = max(maxm, __shfl_xor(maxm, o, 64));
+    for (int src = 1; src < 64; ++src) {
+        for (int c = 0; c < maxm; ++c) {
+            const double mine = c < np ? part[c] : 0.0;
+            const double v = __shfl(mine, src, 64);
+            if (lane == 0 && v != 0.0) exp_add(part, np, v);
+        }
+    }
+    return lane == 0 ? exp_round(part, np) : 0.0;
 }
 
 struct CanonOut {
@@ -325,32 +353,34 @@ __global__ __launch_bounds__(256) void k_canonical(const T *A, const T *B, long 
     const T *a = A + i * dim;
     const T *b = B + j * dim;
     double hi = 0.0, lo = 0.0;
+    int inexact = 0;
     for (long long k = lane; k < dim; k += 64) {
         const double d = ld(a + k) - ld(b + k);
         const double p = d * d;
-        dd_add(hi, lo, p, fma(d, d, -p));
+        dd_add_t(hi, lo, p, fma(d, d, -p), inexact);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const double oh = __shfl_xor(hi, off, 64), ol = __shfl_xor(lo, off, 64);
-        dd_add(hi, lo, oh, ol);
+        dd_add_t(hi, lo, oh, ol, inexact);
+        inexact |= __shfl_xor(inexact, off, 64);
     }
-    double D;
+    double R, e;
+    two_sum(hi, lo, R, e);
+    const double delta = (double)(dim + 64) * 0x1p-100;   // relative error bound
+    int ex;
+    const double frac = frexp(R, &ex);                   // R = frac 2^ex, frac in [0.5, 1)
+    // rounding boundaries of R: R +- half an ulp (ulp = 2^(ex-53)), except
+    // below a power of two, where the spacing halves
+    const double half = (e < 0.0 && frac == 0.5) ? ldexp(1.0, ex - 55) : ldexp(1.0, ex - 54);
+    int certain = isfinite(R) && (!inexact || fabs(e) + delta * R < half || R == 0.0);
+    certain = __shfl(certain, 0, 64);                    // lane 0 decides for the wavefront
+    double D = R;
+    if (!certain || o.force_exact) {
+        D = exact_d2_wave(a, b, dim, lane);
+        if (lane == 0) atomicAdd(o.nexact, 1ull);
+    }
     if (lane == 0) {
-        double R, e;
-        two_sum(hi, lo, R, e);
-        const double delta = (double)(dim + 64) * 0x1p-100;   // relative error bound
-        int ex;
-        const double frac = frexp(R, &ex);                   // R = frac 2^ex, frac in [0.5, 1)
-        // rounding boundaries of R: R +- half an ulp (ulp = 2^(ex-53)), except
-        // below a power of two, where the spacing halves
-        const double half = (e < 0.0 && frac == 0.5) ? ldexp(1.0, ex - 55) : ldexp(1.0, ex - 54);
-        const bool certain = isfinite(R) && (fabs(e) + delta * R < half || R == 0.0);
-        D = R;
-        if (!certain || o.force_exact) {
-            D = exact_d2_serial(a, b, dim);
-            atomicAdd(o.nexact, 1ull);
-        }
         if (o.d2) o.d2[w] = D;
         if (o.hist) {
             int bin = 0;

@@ -44,6 +44,20 @@ def test_canonical_distance_bit_exact(cil, oracle_mod, dtype, d):
     assert np.array_equal(got, want)
 
 
+def test_fp32_ties_need_no_exact_fallback(cil, oracle_mod):
+    """FP32 sets have exact squares, so the exact sum has few bits and often
+    sits exactly half-way between two doubles.  The double-double sum is then
+    exact and certified as such: bit-exact results, no slow exact fallback."""
+    g = np.random.default_rng(21)
+    A = (20.0 * g.random((40, 8192))).astype(np.float32)
+    B = (20.0 * g.random((50, 8192))).astype(np.float32)
+    ia = np.repeat(np.arange(40), 50)
+    jb = np.tile(np.arange(50), 40)
+    got = cil.cil_canonical_d2(dev(A), dev(B), torch.from_numpy(ia), torch.from_numpy(jb)).cpu().numpy()
+    assert np.array_equal(got, oracle_mod.pair_d2(A, B).reshape(-1))
+    assert cil.cil_last_distance_stats()["exact_fallbacks"] == 0
+
+
 def test_exact_summation_path_bit_exact(cil, oracle_mod):
     """The rarely needed exact (expansion) summation, forced on every pair."""
     A, B = sets(5, 6, 3001, seed=1, dtype=np.float64, scale=1e3, offset=-2.0)
