@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32-stepping", action="store_true")
     ap.add_argument("--cpu-sample-solves", type=int, default=96)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
+                         "that scales HBM byte counters)")
     return ap.parse_args()
 
 
@@ -109,6 +112,14 @@ def main():
     bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
     pat32 = torch.empty((B, d), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def one_step(state, ics, path, stat_fp32):
         """Whole hot path; stat_fp32: statistic on FP32 patterns (split-bf16x3 Gram)."""
@@ -244,7 +255,7 @@ def cpu_baseline(w, ics_host, base, n_solves, half, d):
     import oracle
 
     oracle.build()
-    threads = os.cpu_count() or 1
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
     ics = ics_host[:n_solves].copy()
     t0 = time.perf_counter()
     out, steps, res, status = oracle.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"],

@@ -1,0 +1,86 @@
+"""Full-size parity of the benchmarked step (the launch configuration bench.py
+times): 500 Gierer-Meinhardt (source form) solves on 64x64 grids to FP64
+residual < 1e-8, then the CIL statistic of the two 250-pattern halves stored
+as FP32 (d = 8192, 13 radii, 200 bootstrap resamples) and the likelihood.
+
+Sampled solves are re-run by the oracle (steps taken identical, patterns
+within 1e-8 of the oracle's); the statistic is checked in full: the oracle
+computes all 62 500 canonical distances, and range, radii, bins, counts,
+bootstrap counts (bit-exact) and the likelihood (1e-10) must agree.
+"""
+import numpy as np
+import pytest
+
+import cil_synth as cs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cil():
+    import paper_2203_14742_amd as c
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return c
+
+
+@pytest.fixture(scope="module")
+def stepped(cil):
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics = cs.initial_conditions(base, w["n"], w["count"], seed=w["seeds"][0], law=w["ic_law"])
+    st = torch.tensor(ics, dtype=torch.float64, device="cuda")
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=w["count"])
+    print("full-size GM-source run", flush=True)
+    rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                    check_every=w["check_every"], path=cil.CIL_PATH_AUTO)
+    return w, ics, st, rep
+
+
+def test_full_workload_stationary_patterns(cil, oracle_mod, stepped):
+    w, ics, st, rep = stepped
+    assert np.all(rep["status"] == 0) and np.all(rep["final_resid"] < w["tol"])
+    s = rep["steps_taken"]
+    sample = sorted({int(np.argmax(s)), int(np.argmin(s)), 0, 123, 249, 250, 377, 499})
+    out, osteps, ores, ostat = oracle_mod.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"],
+                                                   w["max_steps"], w["tol"], w["check_every"],
+                                                   state=ics[sample].copy(), nthreads=8)
+    assert np.all(ostat == 0)
+    assert np.array_equal(s[sample], osteps)
+    g = st.cpu().numpy()[sample]
+    err = np.abs(g - out).max() / np.abs(out).max()
+    print("sampled stationary patterns: rel err %.3e, steps %s" % (err, list(osteps)))
+    assert err <= 1e-8
+
+
+def test_full_workload_statistic(cil, oracle_mod, stepped):
+    w, ics, st, rep = stepped
+    B, half, d, M = w["count"], w["count"] // 2, 2 * w["n"] ** 2, w["M"]
+    P = st.reshape(B, d).float().contiguous()
+    A, Bs = P[:half], P[half:]
+    An, Bn = A.cpu().numpy(), Bs.cpu().numpy()
+    D = oracle_mod.pair_d2(An, Bn, nthreads=8)
+    lo, hi = cil.cil_distance_range(A, Bs)
+    assert (lo, hi) == (D.min(), D.max())
+    radii = cil.cil_radii(lo, hi, M)
+    assert np.array_equal(radii, oracle_mod.radii_ladder(D.min(), D.max(), M))
+    bins, counts = cil.cil_pair_bins(A, Bs, radii)
+    assert np.array_equal(bins.cpu().numpy(), oracle_mod.bins_from_d2(D, radii))
+    assert np.array_equal(counts, oracle_mod.counts_from_d2(D, radii))
+    ia, ib = cs.resample_halves(half, half, half, half, w["n_boot"], seed=6)
+    Yc, Y = cil.cil_bootstrap_features(bins, torch.from_numpy(ia), torch.from_numpy(ib), M)
+    want_c, want_y = oracle_mod.bootstrap_vectors(D, ia, ib, radii, nthreads=8)
+    assert np.array_equal(Yc.cpu().numpy(), want_c)
+    assert np.array_equal(Y.cpu().numpy(), want_y)
+    y_obs = counts / float(half * half)
+    f, ll, me, stt = cil.cil_gaussian_loglik(Y, torch.tensor(y_obs, dtype=torch.float64, device="cuda"))
+    r = oracle_mod.gaussian_cost(want_y, y_obs)
+    assert int(me.cpu()[0]) == r["m_eff"]
+    if r["ok"]:
+        assert int(stt.cpu()[0]) == 0
+        assert float(f.cpu()[0]) == pytest.approx(r["f"], rel=1e-10)
+        assert float(ll.cpu()[0]) == pytest.approx(r["loglik"], rel=1e-10)
+    else:
+        assert int(stt.cpu()[0]) == cil.CIL_ENOTSPD
+    print("full statistic: counts", counts.tolist(), "m_eff", r["m_eff"], "f", r.get("f"))
