@@ -227,10 +227,16 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
                         const double *y_obs, double *f, double *loglik, int32_t *m_eff,
                         int32_t *status, void *hip_stream);
 
-/* Library options.  CIL_OPT_FORCE_EXACT_SUM (value 0/1): every canonical
- * distance is taken by the exact (slow) summation instead of the certified
- * double-double one; for testing that path.  Host only. */
-enum { CIL_OPT_FORCE_EXACT_SUM = 1 };
+/* Library options (host only; they apply to later calls).
+ * CIL_OPT_FORCE_EXACT_SUM (value 0/1): every canonical distance is taken by
+ *   the exact (slow) summation instead of the certified double-double one;
+ *   for testing that path.
+ * CIL_OPT_QUAD_SHAPE (value -1..2): code shape of the fused quad-lane stepper,
+ *   -1 = chosen by precision and grid side (default); 0 = both species of a
+ *   grid line in one lane, 4n threads per solve; 1 = one species per lane, 8n
+ *   threads, register target 128; 2 = the same with register target 256.
+ *   Every shape computes the same step; timing and register use differ. */
+enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

@@ -35,6 +35,7 @@ int loglik_impl(const double *, int, int, int, const double *, double *, double 
                 hipStream_t);
 int last_distance_stats(int64_t *, int64_t *, int64_t *);
 void set_force_exact(int);
+int set_quad_shape(int64_t);
 
 // ------------------------------------------------------------------ errors
 namespace {
@@ -458,6 +459,7 @@ int cil_set_option(int32_t option, int64_t value)
         set_force_exact((int)value);
         return CIL_OK;
     }
+    if (option == CIL_OPT_QUAD_SHAPE) return set_quad_shape(value);
     return set_error(CIL_EINVAL, "unknown option %d", option);
 }
 

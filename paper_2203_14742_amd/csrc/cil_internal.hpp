@@ -111,6 +111,33 @@ constexpr double ce_cospi(long p, long q)
 
 constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
 
+// ------------------------------------------------------- buffer accesses
+// Raw buffer loads/stores: the base lives in a uniform resource (SGPRs), so a
+// lane address is one 32-bit byte offset plus compile-time offsets, instead
+// of a 64-bit VGPR pair per distinct address.  Accesses past `bytes` read 0
+// and are dropped on store.  Resource word 3 = 0x00020000 (gfx9 family).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                              voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
 // ------------------------------------------------------------ static_for
 template <int I, int N, typename F>
 __host__ __device__ __forceinline__ void static_for(F &&f)

@@ -14,24 +14,28 @@
 // lane of the one-lane transform, which gives a solve four times the waves.
 //
 // Scaling (folded into the spectral divisor): forward = 2 DCT2,
-// inverse = N DCT2^{-1}.  Input and output live in LDS, addressed by the
-// caller's functors; a line is updated in place by its own quad.
+// inverse = N DCT2^{-1}.  Input and output are the lanes' registers: line
+// values in the order the four-step split fixes (the caller moves them to and
+// from LDS or HBM), spectral values as the pairs (X_k, X_{N-k}) a lane's own
+// split step yields, so a forward transform, a pointwise spectral operation
+// and an inverse chain without any data leaving the quad.
 #pragma once
 
 #include "cil_internal.hpp"
 
 namespace cil {
 
-// quad_perm controls: lane q reads lane q ^ 1, q ^ 2, q ^ 3 of its quad
-constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_XOR3 = 0x1B;
+// DPP controls.  quad_perm: lane q reads lane q ^ 1, q ^ 2, q ^ 3 of its quad;
+// row_half_mirror: lane i reads lane 7 - i of its group of eight.
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_XOR3 = 0x1B, DPP_HALF_MIRROR = 0x141;
 
 template <int CTRL>
-__device__ __forceinline__ float quad_swap(float v)
+__device__ __forceinline__ float dpp_mov(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 template <int CTRL>
-__device__ __forceinline__ double quad_swap(double v)
+__device__ __forceinline__ double dpp_mov(double v)
 {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
@@ -53,28 +57,46 @@ struct QuadLine {
         T be_r, be_i;         // exp(-i pi P k2 / (2N))
     };
 
+    // The lane constants, selected from compile-time values (exact to the
+    // last bit of T, no run-time trigonometry).
     __device__ static void init(Lane &L, int q)
     {
         L.q = q;
         L.k2 = (q >> 1) + 2 * (q & 1);
-#pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) {
-            double s, c;
-            sincospi(-2.0 * q * k1 / (double)M, &s, &c);
-            L.tw_r[k1] = (T)c;
-            L.tw_i[k1] = (T)s;
-        }
-        double s, c;
-        sincospi(-2.0 * P * L.k2 / (double)N, &s, &c);
-        L.al_r = (T)c;
-        L.al_i = (T)s;
-        sincospi(-(double)P * L.k2 / (2.0 * N), &s, &c);
-        L.be_r = (T)c;
-        L.be_i = (T)s;
+        static_for<0, P>([&](auto Ki) {
+            constexpr int k1 = Ki;
+            // W_M^(q k1) for q = 0..3
+            constexpr T r1 = (T)ce_cospi(2 * k1, M), i1 = (T)(-ce_sinpi(2 * k1, M));
+            constexpr T r2 = (T)ce_cospi(4 * k1, M), i2 = (T)(-ce_sinpi(4 * k1, M));
+            constexpr T r3 = (T)ce_cospi(6 * k1, M), i3 = (T)(-ce_sinpi(6 * k1, M));
+            L.tw_r[k1] = q == 0 ? T(1) : (q == 1 ? r1 : (q == 2 ? r2 : r3));
+            L.tw_i[k1] = q == 0 ? T(0) : (q == 1 ? i1 : (q == 2 ? i2 : i3));
+        });
+        // alpha = exp(-2 pi i P k2 / N), beta = exp(-i pi P k2 / 2N) for k2 = 0..3
+        const int k2 = L.k2;
+        constexpr T a1r = (T)ce_cospi(2 * P, N), a1i = (T)(-ce_sinpi(2 * P, N));
+        constexpr T a2r = (T)ce_cospi(4 * P, N), a2i = (T)(-ce_sinpi(4 * P, N));
+        constexpr T a3r = (T)ce_cospi(6 * P, N), a3i = (T)(-ce_sinpi(6 * P, N));
+        constexpr T b1r = (T)ce_cospi(P, 2 * N), b1i = (T)(-ce_sinpi(P, 2 * N));
+        constexpr T b2r = (T)ce_cospi(2 * P, 2 * N), b2i = (T)(-ce_sinpi(2 * P, 2 * N));
+        constexpr T b3r = (T)ce_cospi(3 * P, 2 * N), b3i = (T)(-ce_sinpi(3 * P, 2 * N));
+        L.al_r = k2 == 0 ? T(1) : (k2 == 1 ? a1r : (k2 == 2 ? a2r : a3r));
+        L.al_i = k2 == 0 ? T(0) : (k2 == 1 ? a1i : (k2 == 2 ? a2i : a3i));
+        L.be_r = k2 == 0 ? T(1) : (k2 == 1 ? b1r : (k2 == 2 ? b2r : b3r));
+        L.be_i = k2 == 0 ? T(0) : (k2 == 1 ? b1i : (k2 == 2 ? b2i : b3i));
     }
 
     // index of the input element that lands at position j of the reordering
     __device__ static int vsrc(int j) { return j < M ? 2 * j : 2 * (N - 1 - j) + 1; }
+
+    // Line position of lane q's value h (0: real part, 1: imaginary part) of
+    // pair m1, i.e. vsrc(2 (4 m1 + q) + h), split so that the lane-dependent
+    // part is one base per half: pairs m1 < P/2 lie at 4q + 16 m1 + 2h, the
+    // others at (2N - 1 - 4q) - 16 m1 - 2h.
+    template <int m1, int h>
+    __device__ static constexpr int pos_off() { return m1 < P / 2 ? 16 * m1 + 2 * h : -(16 * m1 + 2 * h); }
+    template <int m1>
+    __device__ static int pos_base(int q) { return m1 < P / 2 ? 4 * q : 2 * N - 1 - 4 * q; }
 
     template <int SIGN>
     __device__ __forceinline__ static void fftP(T (&re)[P], T (&im)[P])
@@ -119,10 +141,10 @@ struct QuadLine {
         const bool rot = (L.q == 3);
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const T pr = quad_swap<DPP_XOR2>(re[k]), pi = quad_swap<DPP_XOR2>(im[k]);
+            const T pr = dpp_mov<DPP_XOR2>(re[k]), pi = dpp_mov<DPP_XOR2>(im[k]);
             T ar = pr + s1 * re[k], ai = pi + s1 * im[k];
             const T tr = rot ? ai : ar, ti = rot ? -ar : ai;      // times -i on lane 3
-            const T qr = quad_swap<DPP_XOR1>(tr), qi = quad_swap<DPP_XOR1>(ti);
+            const T qr = dpp_mov<DPP_XOR1>(tr), qi = dpp_mov<DPP_XOR1>(ti);
             re[k] = qr + s2 * tr;
             im[k] = qi + s2 * ti;
         }
@@ -134,33 +156,21 @@ struct QuadLine {
         const bool rot = (L.q == 3);
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const T pr = quad_swap<DPP_XOR1>(re[k]), pi = quad_swap<DPP_XOR1>(im[k]);
+            const T pr = dpp_mov<DPP_XOR1>(re[k]), pi = dpp_mov<DPP_XOR1>(im[k]);
             T cr = pr + s1 * re[k], ci = pi + s1 * im[k];
             const T tr = rot ? -ci : cr, ti = rot ? cr : ci;      // times +i on lane 3
-            const T qr = quad_swap<DPP_XOR2>(tr), qi = quad_swap<DPP_XOR2>(ti);
+            const T qr = dpp_mov<DPP_XOR2>(tr), qi = dpp_mov<DPP_XOR2>(ti);
             re[k] = qr + s2 * tr;
             im[k] = qi + s2 * ti;
         }
     }
 
-    // Forward: gathered line -> X_k (k = k1 + P k2) and X_{N-k}, written by st(index, value).
-    template <typename LD, typename ST>
-    __device__ __forceinline__ static void forward(const Lane &L, LD &&ld, ST &&st)
-    {
-        T zr[P], zi[P];
-        static_for<0, P>([&](auto Mi) {
-            constexpr int m1 = Mi;
-            constexpr int p = bitrev(m1, LOGP);
-            const int j = 2 * (4 * m1 + L.q);
-            zr[p] = ld(vsrc(j));
-            zi[p] = ld(vsrc(j + 1));
-        });
-        forward_from(L, zr, zi, st);
-    }
-
-    // Same, from values already in registers (bit-reversed m1 order).
-    template <typename ST>
-    __device__ __forceinline__ static void forward_from(const Lane &L, T (&zr)[P], T (&zi)[P], ST &&st)
+    // Forward, from the lane's 2P line values (bit-reversed m1 order: zr[bitrev(m1)]
+    // at position vsrc(2(4 m1 + q)), zi[...] at the next one) to its spectral
+    // values: xa[k1] = X_k, xb[k1] = X_{N-k}, k = k1 + P k2 (xb = 0 where k = 0),
+    // and xm = X_M on lane q = 0.  zr/zi are destroyed.
+    __device__ __forceinline__ static void forward_regs(const Lane &L, T (&zr)[P], T (&zi)[P], T (&xa)[P],
+                                                        T (&xb)[P], T &xm)
     {
         fftP<-1>(zr, zi);
 #pragma unroll
@@ -171,88 +181,102 @@ struct QuadLine {
             zi[k1] = i;
         }
         cross_fwd(L, zr, zi);
-        const int kb = P * L.k2;
-        static_for<0, P>([&](auto Ki) {
-            constexpr int k1 = Ki;
+        // k1 and P - k1 are each other's partners: take them together so that
+        // both Z values die at once
+        static_for<0, P>([&](auto Ji) {
+            constexpr int J = Ji;
+            constexpr int k1 = (J == 0) ? 0 : ((J & 1) ? (J + 1) / 2 : P - J / 2);
             // partner conj(Z_{M-k}): lane q ^ 3 at P - k1; for k1 = 0 lane q (q < 2) or q ^ 1
             T c, d;
             if constexpr (k1 == 0) {
-                const T sr = quad_swap<DPP_XOR1>(zr[0]), si = quad_swap<DPP_XOR1>(zi[0]);
+                const T sr = dpp_mov<DPP_XOR1>(zr[0]), si = dpp_mov<DPP_XOR1>(zi[0]);
                 c = L.q < 2 ? zr[0] : sr;
                 d = L.q < 2 ? -zi[0] : -si;
             } else {
-                c = quad_swap<DPP_XOR3>(zr[P - k1]);
-                d = -quad_swap<DPP_XOR3>(zi[P - k1]);
+                c = dpp_mov<DPP_XOR3>(zr[P - k1]);
+                d = -dpp_mov<DPP_XOR3>(zi[P - k1]);
             }
             const T a = zr[k1], b = zi[k1];
             const T Er = a + c, Ei = b + d, Or = b - d, Oi = c - a;
-            // w = exp(-2 pi i k / N) = lit(k1) * alpha;  ph = exp(-i pi k / 2N) = lit'(k1) * beta
+            // V = E + w O with w = exp(-2 pi i k / N) = lit1(k1) alpha, and
+            // X_k - i X_{N-k} = ph V with ph = exp(-i pi k / 2N) = lit2(k1) beta.
+            // The lane constant multiplies the data first, then the literal:
+            // the same operation count as forming w and ph, and no per-k1 lane
+            // twiddles that the compiler could precompute and keep live.
             constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
             constexpr T l2r = (T)ce_cospi(k1, 2 * N), l2i = (T)(-ce_sinpi(k1, 2 * N));
-            const T wr = l1r * L.al_r - l1i * L.al_i, wi = l1r * L.al_i + l1i * L.al_r;
-            const T hr = l2r * L.be_r - l2i * L.be_i, hi = l2r * L.be_i + l2i * L.be_r;
-            const T Vr = Er + (wr * Or - wi * Oi), Vi = Ei + (wr * Oi + wi * Or);
-            const int k = k1 + kb;
-            st(k, hr * Vr - hi * Vi);
-            if (k != 0) st(N - k, -(hr * Vi + hi * Vr));
+            const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
+            const T Vr = Er + (l1r * ar - l1i * ai), Vi = Ei + (l1r * ai + l1i * ar);
+            const T br = L.be_r * Vr - L.be_i * Vi, bi = L.be_r * Vi + L.be_i * Vr;      // beta V
+            xa[k1] = l2r * br - l2i * bi;
+            xb[k1] = -(l2r * bi + l2i * br);
             if constexpr (k1 == 0) {
-                if (L.q == 0) {      // k = M from the same pair: w = -1, ph = exp(-i pi / 4)
-                    constexpr T c4 = (T)ce_cospi(1, 4);
-                    const T Ur = Er - Or, Ui = Ei - Oi;
-                    st(M, c4 * (Ur + Ui));
-                }
+                // k = M from the same pair on lane 0: w = -1, ph = exp(-i pi / 4)
+                constexpr T c4 = (T)ce_cospi(1, 4);
+                xm = c4 * ((Er - Or) + (Ei - Oi));
+                if (L.q == 0) xb[0] = T(0);
             }
         });
     }
 
-    // Backward: reads X at k, N-k, M-k, M+k through ld; writes the line through st.
-    template <typename LD, typename ST>
-    __device__ __forceinline__ static void inverse(const Lane &L, LD &&ld, ST &&st)
+    // Inverse, from the lane's spectral values (as forward_regs leaves them) to
+    // its 2P line values in natural m1 order: zr[m1] at position
+    // vsrc(2(4 m1 + q)), zi[m1] at the next.  The split step needs X_{M-k} and
+    // X_{M+k} too, which lane q ^ 3 holds as its own pair at P - k1 (for
+    // k1 = 0: lane q itself, its xor-1 neighbour, or X_M on lane 0).
+    __device__ __forceinline__ static void inverse_regs(const Lane &L, const T (&xa)[P], const T (&xb)[P], T xm,
+                                                        T (&zr)[P], T (&zi)[P])
     {
-        T zr[P], zi[P];
-        const int kb = P * L.k2;
-        static_for<0, P>([&](auto Ki) {
-            constexpr int k1 = Ki;
-            const int k = k1 + kb;
-            const T xk = ld(k), xn = (k == 0) ? T(0) : ld(N - k);
-            const T ym = ld(M - k), yp = ld(M + k);         // X_{M-k}, X_{N-(M-k)} (both X_M at k = 0)
-            build_z_c<k1>(L, xk, xn, ym, yp, zr, zi);
+        static_for<0, P>([&](auto Ji) {          // partners k1, P - k1 together
+            constexpr int J = Ji;
+            constexpr int k1 = (J == 0) ? 0 : ((J & 1) ? (J + 1) / 2 : P - J / 2);
+            T ym, yp;
+            if constexpr (k1 == 0) {
+                const T sa = dpp_mov<DPP_XOR1>(xa[0]), sb = dpp_mov<DPP_XOR1>(xb[0]);
+                ym = L.q == 0 ? xm : (L.q == 1 ? xa[0] : sa);
+                yp = L.q == 0 ? xm : (L.q == 1 ? xb[0] : sb);
+            } else {
+                ym = dpp_mov<DPP_XOR3>(xa[P - k1]);
+                yp = dpp_mov<DPP_XOR3>(xb[P - k1]);
+            }
+            build_z_c<k1>(L, xa[k1], xb[k1], ym, yp, zr, zi);
         });
-        inverse_from(L, zr, zi, st);
+        inverse_core(L, zr, zi);
     }
 
     // Z_k for one k1 from X_k, X_{N-k}, X_{M-k}, X_{M+k}; stored bit-reversed.
+    // ph = exp(-i pi k/2N) = lit2 beta, w = exp(-2 pi i k/N) = lit1 alpha;
+    //   V_k     = conj(ph) (X_k - i X_{N-k}),
+    //   V_{M-k} = e^{i pi/4} ph (X_{M-k} - i X_{M+k}),
+    //   Z_k     = E + i O, E = V_k + conj(V_{M-k}), O = (V_k - conj(V_{M-k})) conj(w).
+    // As in the forward, lane constants multiply data before literals.
     template <int K1>
     __device__ __forceinline__ static void build_z_c(const Lane &L, T xk, T xn, T ym, T yp, T (&zr)[P], T (&zi)[P])
     {
-        // ph = exp(-i pi k/2N); V_k = conj(ph) (X_k - i X_{N-k});
-        // V_{M-k} = exp(i pi M/2N) exp(-i pi k/2N) (X_{M-k} - i X_{M+k}) = e^{i pi/4} ph (..)
         constexpr T l2r = (T)ce_cospi(K1, 2 * N), l2i = (T)(-ce_sinpi(K1, 2 * N));
         constexpr T l1r = (T)ce_cospi(2 * K1, N), l1i = (T)(-ce_sinpi(2 * K1, N));
         constexpr T c4 = (T)ce_cospi(1, 4);
-        const T hr = l2r * L.be_r - l2i * L.be_i, hi = l2r * L.be_i + l2i * L.be_r;   // ph
-        const T wr = l1r * L.al_r - l1i * L.al_i, wi = l1r * L.al_i + l1i * L.al_r;   // w = exp(-2 pi i k/N)
-        // V_k = (hr - i hi)(xk - i xn)
-        const T ar = hr * xk - hi * xn, ai = -(hr * xn + hi * xk);
-        // g = e^{i pi/4} ph = c4 (1 + i)(hr + i hi)
-        const T gr = c4 * (hr - hi), gi = c4 * (hr + hi);
-        // V_{M-k} = g (ym - i yp); c + i d = conj(V_{M-k})
-        const T vr = gr * ym + gi * yp, vi = gi * ym - gr * yp;
-        const T c = vr, d = -vi;
+        constexpr T gr = c4 * (l2r - l2i), gi = c4 * (l2r + l2i);     // e^{i pi/4} lit2
+        // conj(beta) (xk - i xn), then conj(lit2)
+        const T t1r = L.be_r * xk - L.be_i * xn, t1i = -(L.be_r * xn + L.be_i * xk);
+        const T ar = l2r * t1r + l2i * t1i, ai = l2r * t1i - l2i * t1r;
+        // beta (ym - i yp), then e^{i pi/4} lit2; c + i d = conj(V_{M-k})
+        const T t2r = L.be_r * ym + L.be_i * yp, t2i = L.be_i * ym - L.be_r * yp;
+        const T c = gr * t2r - gi * t2i, d = -(gr * t2i + gi * t2r);
         const T Er = ar + c, Ei = ai + d;
         const T pr = ar - c, pi = ai - d;
-        // O = (p) conj(w)
-        const T Or = pr * wr + pi * wi, Oi = pi * wr - pr * wi;
+        // O = p conj(alpha) conj(lit1)
+        const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;
+        const T Or = l1r * t3r + l1i * t3i, Oi = l1r * t3i - l1i * t3r;
         constexpr int p = bitrev(K1, LOGP);
         zr[p] = Er - Oi;
         zi[p] = Ei + Or;
     }
 
-    template <typename ST>
-    __device__ __forceinline__ static void inverse_from(const Lane &L, T (&zr)[P], T (&zi)[P], ST &&st)
+    // zr/zi arrive bit-reversed in k1; the cross-lane stage works elementwise,
+    // the lane twiddle needs the natural index.  Leaves natural m1 order.
+    __device__ __forceinline__ static void inverse_core(const Lane &L, T (&zr)[P], T (&zi)[P])
     {
-        // zr/zi arrive bit-reversed in k1; the cross-lane stage works elementwise,
-        // the lane twiddle needs the natural index
         cross_bwd(L, zr, zi);
         static_for<1, P>([&](auto Ki) {
             constexpr int k1 = Ki;
@@ -263,12 +287,6 @@ struct QuadLine {
             zi[p] = i;
         });
         fftP<+1>(zr, zi);
-        static_for<0, P>([&](auto Mi) {
-            constexpr int m1 = Mi;
-            const int j = 2 * (4 * m1 + L.q);
-            st(vsrc(j), zr[m1]);
-            st(vsrc(j + 1), zi[m1]);
-        });
     }
 };
 

@@ -232,3 +232,34 @@ def test_fused_unsupported_size_is_an_error(cil):
     with pytest.raises(cil.CilError) as e:
         cil.cil_simulate_patterns(0, st, cil.make_problems(20, 1.0, (0.1, 0.1), (1, 1, 1)), 0.01, 5, path=2)
     assert e.value.code == cil.CIL_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("prec,case,n,L,dt,steps", [("fp64", FHN, 32, 1.0, 0.01, 200), ("fp64", GMS, 64, 120.0, 0.2, 150),
+                                                    ("fp32", FHN, 32, 1.0, 0.01, 200), ("fp32", GMS, 64, 120.0, 0.2, 150),
+                                                    ("fp32", BZ, 128, 1.0, 0.05, 60)])
+def test_every_quad_shape_matches_oracle(cil, oracle_mod, shape, prec, case, n, L, dt, steps):
+    """Each code shape of the fused quad-lane stepper takes the same steps:
+    trajectory parity and the stop rule (resid checked every 25 steps)."""
+    model, p, nu = case
+    base = oracle_mod.homogeneous_state(model, p)
+    print("quad shape %d %s model=%d n=%d" % (shape, prec, model, n), flush=True)
+    ics = cs.initial_conditions(base, n, 3, seed=40 + model, law="additive_pos")
+    if prec == "fp32":
+        ics = ics.astype(np.float32).astype(np.float64)
+    cil.cil_set_option(cil.CIL_OPT_QUAD_SHAPE, shape)
+    try:
+        g, rep, o, osteps, ores, ostat = run_both(cil, oracle_mod, model, p, nu, n, L, dt, steps, ics, prec, 4,
+                                                  check=25)
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_QUAD_SHAPE, -1)
+    assert rel_err(g, o) <= (1e-10 if prec == "fp64" else 1e-4)
+    assert np.array_equal(rep["steps_taken"], osteps)
+    if prec == "fp64":
+        assert np.allclose(rep["final_resid"], ores, rtol=1e-6, atol=1e-14)
+
+
+def test_quad_shape_option_range(cil):
+    with pytest.raises(cil.CilError) as e:
+        cil.cil_set_option(cil.CIL_OPT_QUAD_SHAPE, 3)
+    assert e.value.code == cil.CIL_EINVAL
