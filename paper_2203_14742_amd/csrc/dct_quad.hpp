@@ -219,6 +219,77 @@ struct QuadLine {
         });
     }
 
+    // Forward as far as the split step's V_k = E_k + w_k O_k (k = k1 + P k2),
+    // with X_k - i X_{N-k} = ph_k V_k; xm = X_M on lane q = 0 as in forward_regs.
+    __device__ __forceinline__ static void forward_v(const Lane &L, T (&zr)[P], T (&zi)[P], T (&vr)[P], T (&vi)[P],
+                                                     T &xm)
+    {
+        fftP<-1>(zr, zi);
+#pragma unroll
+        for (int k1 = 1; k1 < P; ++k1) {
+            const T r = zr[k1] * L.tw_r[k1] - zi[k1] * L.tw_i[k1];
+            const T i = zr[k1] * L.tw_i[k1] + zi[k1] * L.tw_r[k1];
+            zr[k1] = r;
+            zi[k1] = i;
+        }
+        cross_fwd(L, zr, zi);
+        static_for<0, P>([&](auto Ji) {
+            constexpr int J = Ji;
+            constexpr int k1 = (J == 0) ? 0 : ((J & 1) ? (J + 1) / 2 : P - J / 2);
+            T c, d;
+            if constexpr (k1 == 0) {
+                const T sr = dpp_mov<DPP_XOR1>(zr[0]), si = dpp_mov<DPP_XOR1>(zi[0]);
+                c = L.q < 2 ? zr[0] : sr;
+                d = L.q < 2 ? -zi[0] : -si;
+            } else {
+                c = dpp_mov<DPP_XOR3>(zr[P - k1]);
+                d = -dpp_mov<DPP_XOR3>(zi[P - k1]);
+            }
+            const T a = zr[k1], b = zi[k1];
+            const T Er = a + c, Ei = b + d, Or = b - d, Oi = c - a;
+            constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
+            const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
+            vr[k1] = Er + (l1r * ar - l1i * ai);
+            vi[k1] = Ei + (l1r * ai + l1i * ar);
+            if constexpr (k1 == 0) {
+                constexpr T c4 = (T)ce_cospi(1, 4);
+                xm = c4 * ((Er - Or) + (Ei - Oi));
+            }
+        });
+    }
+
+    // Inverse from V'_k (as forward_v leaves them, after a spectral operator)
+    // and X'_M on lane 0: Z_k = E + i O with E = V'_k + conj(V'_{M-k}),
+    // O = (V'_k - conj(V'_{M-k})) conj(w_k); V'_{M-k} comes from lane q ^ 3 at
+    // P - k1 (k1 = 0: the lane itself, its xor-1 neighbour, or V'_M = sqrt(2) X'_M).
+    __device__ __forceinline__ static void inverse_v(const Lane &L, const T (&vr)[P], const T (&vi)[P], T xm,
+                                                     T (&zr)[P], T (&zi)[P])
+    {
+        static_for<0, P>([&](auto Ji) {
+            constexpr int J = Ji;
+            constexpr int k1 = (J == 0) ? 0 : ((J & 1) ? (J + 1) / 2 : P - J / 2);
+            T mr, mi;     // V'_{M-k}
+            if constexpr (k1 == 0) {
+                constexpr T s2 = (T)1.4142135623730950488;
+                const T sr = dpp_mov<DPP_XOR1>(vr[0]), si = dpp_mov<DPP_XOR1>(vi[0]);
+                mr = L.q == 0 ? s2 * xm : (L.q == 1 ? vr[0] : sr);
+                mi = L.q == 0 ? T(0) : (L.q == 1 ? vi[0] : si);
+            } else {
+                mr = dpp_mov<DPP_XOR3>(vr[P - k1]);
+                mi = dpp_mov<DPP_XOR3>(vi[P - k1]);
+            }
+            const T Er = vr[k1] + mr, Ei = vi[k1] - mi;
+            const T pr = vr[k1] - mr, pi = vi[k1] + mi;
+            constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
+            const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;   // p conj(alpha)
+            const T Or = l1r * t3r + l1i * t3i, Oi = l1r * t3i - l1i * t3r;
+            constexpr int p = bitrev(k1, LOGP);
+            zr[p] = Er - Oi;
+            zi[p] = Ei + Or;
+        });
+        inverse_core(L, zr, zi);
+    }
+
     // Inverse, from the lane's spectral values (as forward_regs leaves them) to
     // its 2P line values in natural m1 order: zr[m1] at position
     // vsrc(2(4 m1 + q)), zi[m1] at the next.  The split step needs X_{M-k} and

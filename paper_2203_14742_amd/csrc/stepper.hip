@@ -51,6 +51,24 @@ struct StepResults {               // indexed by solve
     int *bad;                      // non-finite value seen
 };
 
+// 1/w from the hardware reciprocal and Newton steps e = 1 - w r, r += r e
+// (two in FP64, one in FP32): within about one unit in the last place of
+// the correctly rounded quotient, at half the instructions of IEEE division.
+template <typename T>
+__device__ __forceinline__ T recip(T w)
+{
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rcp(w);
+        double e = fma(-w, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-w, r, 1.0);
+        return fma(r, e, r);
+    } else {
+        const float r = __builtin_amdgcn_rcpf(w);
+        return fmaf(r, fmaf(-w, r, 1.0f), r);
+    }
+}
+
 // -------------------------------------------------------------- kinetics
 // Sec. 4.1 reaction terms; the model is uniform over a launch.
 template <int MODEL, typename T>
@@ -60,10 +78,10 @@ __device__ __forceinline__ void kinetics(const T *p, T v, T w, T &f, T &g)
         f = p[1] * (w - p[2] * v);
         g = -v + p[0] * w - w * w * w;
     } else if constexpr (MODEL == CIL_GM) {
-        f = -p[0] * v + v * v / w;
+        f = -p[0] * v + v * v * recip(w);
         g = -p[1] * w + v * v;
     } else if constexpr (MODEL == CIL_GM_SOURCE) {
-        f = p[0] - p[1] * v + v * v / w;
+        f = p[0] - p[1] * v + v * v * recip(w);
         g = v * v - w;
     } else if constexpr (MODEL == CIL_BRUSSELATOR) {
         f = p[0] - (p[1] + T(1)) * v + v * v * w;
@@ -385,7 +403,7 @@ __global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *l
 // threads; group g of eight lanes owns row/column g, species s = (t / 4) & 1,
 // quad position q = t & 3 for v and 3 - (t & 3) for w, so that lane t ^ 7 -
 // the DPP half-row mirror - holds the other species at the same points).
-template <typename T, int N, int SPL, typename MD>
+template <typename T, int N, int SPL, bool VF, typename MD>
 __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, const DevSolve &s, int b, T *state,
                                               const T *tables, double dt, const PersistArgs &pa)
 {
@@ -419,10 +437,13 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
     T *const rk = smp + g * LD + kb;                            // X_k of row g at rk[k1]
     T *const rn = smp + g * LD + (N - kb) - (P - 1);            // X_{N-k} at rn[P - 1 - k1]
     T *const rm = smp + g * LD + M;
-    const auto tb = make_rsrc(tables + (size_t)s.tab * 2 * NN, 2 * NN * sizeof(T));   // [species][k][l]
-    const unsigned tko = (sp0 * NN + kb * N + g) * sizeof(T);
-    const unsigned tno = (sp0 * NN + (N - kb - (P - 1)) * N + g) * sizeof(T);
-    const unsigned tmo = (sp0 * NN + M * N + g) * sizeof(T);
+    // Spectral divisor of the column pass.  VF: in the split step's V form,
+    // [species][A | B | Ci][k = 0..M][l] (k_make_vtables); else the plain
+    // divisors [species][k][l] (k_make_tables) applied to X_k and X_{N-k}.
+    constexpr int VPL = (M + 1) * N, VSP = VF ? 3 * VPL : NN;
+    const auto tb = make_rsrc(tables + (size_t)s.tab * 2 * VSP, 2 * VSP * sizeof(T));
+    const unsigned tko = (sp0 * VSP + kb * N + g) * sizeof(T), tmo = (sp0 * VSP + M * N + g) * sizeof(T);
+    const unsigned tno = (sp0 * VSP + (N - kb - (P - 1)) * N + g) * sizeof(T);
 
     T ur[SPL][P], ui[SPL][P];     // the lane's 2P values of each of its species along row g, natural order
     auto hbm_ld = [&](auto m1c, auto hc, int c) -> T {
@@ -543,16 +564,31 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
                 xr[c][pb] = cc[line_off(Mi, I0{}) * LD];
                 xi[c][pb] = cc[line_off(Mi, I1{}) * LD];
             });
-            Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
-            const int cso = c * NN * sizeof(T);
-            static_for<0, P>([&](auto Ki) {
-                constexpr int k1 = Ki;
-                xa[c][k1] *= buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
-                if constexpr (k1 == 0) xb[c][0] *= buf_load<T>(tb, kb == 0 ? tmo : tno + (P - 1) * N * sizeof(T), cso);
-                else xb[c][k1] *= buf_load<T>(tb, tno + (P - 1 - k1) * N * sizeof(T), cso);
-            });
-            xm[c] *= buf_load<T>(tb, tmo, cso);
-            Q::inverse_regs(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
+            const int cso = c * VSP * sizeof(T);
+            if constexpr (VF) {
+                Q::forward_v(L, xr[c], xi[c], xa[c], xb[c], xm[c]);       // xa/xb: Re/Im V_k
+                static_for<0, P>([&](auto Ki) {
+                    constexpr int k1 = Ki;
+                    const T A = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
+                    const T B = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + VPL * sizeof(T));
+                    const T C = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + 2 * VPL * sizeof(T));
+                    const T re = xa[c][k1], im = xb[c][k1];
+                    xa[c][k1] = A * re + C * im;
+                    xb[c][k1] = B * im + C * re;
+                });
+                xm[c] *= buf_load<T>(tb, tmo, cso);
+                Q::inverse_v(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
+            } else {
+                Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
+                static_for<0, P>([&](auto Ki) {
+                    constexpr int k1 = Ki;
+                    xa[c][k1] *= buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
+                    if constexpr (k1 == 0) xb[c][0] *= buf_load<T>(tb, kb == 0 ? tmo : tno + (P - 1) * N * sizeof(T), cso);
+                    else xb[c][k1] *= buf_load<T>(tb, tno + (P - 1 - k1) * N * sizeof(T), cso);
+                });
+                xm[c] *= buf_load<T>(tb, tmo, cso);
+                Q::inverse_regs(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
+            }
             static_for<0, P>([&](auto Mi) {
                 constexpr int m1 = Mi;
                 T *cc = (m1 < P / 2 ? cb0 : cb1) + c * SP;
@@ -597,7 +633,7 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
 // The first row pass loads u from HBM instead; the last stores it there.
 // The model is dispatched once, outside the step loop.  WPE is the occupancy
 // the register allocation aims at (waves per SIMD).
-template <typename T, int N, int SPL, int WPE>
+template <typename T, int N, int SPL, int WPE, bool VF>
 __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(WPE))) void k_fused_q(
     const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt, PersistArgs pa)
 {
@@ -608,7 +644,7 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(W
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
     dispatch_model(model, [&](auto MD) {
-        fused_q_solve<T, N, SPL, decltype(MD)>(sm, red, sbad, s, b, state, tables, dt, pa);
+        fused_q_solve<T, N, SPL, VF, decltype(MD)>(sm, red, sbad, s, b, state, tables, dt, pa);
     });
 }
 
@@ -629,6 +665,49 @@ __global__ void k_make_tables(const TabSpec *specs, int ntab, int n, double dt, 
     const double lam = 4.0 * (sk * sk + sl * sl) * ts.inv_h2;
     const double nu = sp ? ts.nu1 : ts.nu0;
     out[(size_t)t * 2 * n * n + e] = T(1.0 / (4.0 * n * (double)n * (1.0 + dt * nu * lam)));
+}
+
+// Quad-variant table: the column pass applies the divisor in the split
+// step's V form.  With Y = X_k - i X_{N-k} = ph V (ph = exp(-i pi k / 2N)),
+// dividing X_k by D_k and X_{N-k} by D_{N-k} is Y' = S Y + Delta conj(Y),
+// S = (D_k + D_{N-k}) / 2, Delta = (D_k - D_{N-k}) / 2, so
+// V' = S V + Delta exp(i pi k / N) conj(V):
+//   Re V' = A Re V + Ci Im V,  Im V' = B Im V + Ci Re V,
+//   A = S + Delta cos(pi k/N), B = S - Delta cos(pi k/N), Ci = Delta sin(pi k/N).
+// k = 0 keeps only Re V (X_N does not exist): A = D_0, B = Ci = 0.  Row k = M
+// of plane A holds D_M (X_M is carried as a real value).
+// Layout: vt[t][s][plane A|B|Ci][k = 0..M][l], M = n/2 (D indexed as tab above).
+template <typename T>
+__global__ void k_make_vtables(const TabSpec *specs, int ntab, int n, double dt, T *out)
+{
+    const int t = blockIdx.y;
+    const int M = n / 2, rows = M + 1;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntab || e >= 2 * rows * n) return;
+    const int sp = e / (rows * n), k = (e / n) % rows, l = e % n;
+    const TabSpec ts = specs[t];
+    const double nu = sp ? ts.nu1 : ts.nu0;
+    auto D = [&](int kk) {
+        const double sk = sinpi((double)kk / (2.0 * n)), sl = sinpi((double)l / (2.0 * n));
+        const double lam = 4.0 * (sk * sk + sl * sl) * ts.inv_h2;
+        return 1.0 / (4.0 * n * (double)n * (1.0 + dt * nu * lam));
+    };
+    double A, B = 0.0, C = 0.0;
+    if (k == 0 || k == M) {
+        A = D(k);
+    } else {
+        const double dk = D(k), dn = D(n - k);
+        const double S = 0.5 * (dk + dn), Dl = 0.5 * (dk - dn);
+        double sn, cs;
+        sincospi((double)k / n, &sn, &cs);
+        A = S + Dl * cs;
+        B = S - Dl * cs;
+        C = Dl * sn;
+    }
+    T *o = out + (size_t)t * 2 * 3 * rows * n + (size_t)sp * 3 * rows * n + (size_t)k * n + l;
+    o[0] = T(A);
+    o[(size_t)rows * n] = T(B);
+    o[(size_t)2 * rows * n] = T(C);
 }
 
 template <typename S, typename D>
@@ -696,22 +775,22 @@ int fused_supported(int n, bool f32)
     return f32 ? (n == 32 || n == 64 || n == 128) : (n == 32 || n == 64);
 }
 
-// Code shapes of the quad variant: species per lane and the occupancy the
-// register allocation aims at.  Chosen per (precision, n) by the register
-// budget that lets every solve of a large batch be resident (two or more
-// workgroups per CU); cil_set_option(CIL_OPT_QUAD_SHAPE) overrides.
+// Code shapes of the quad variant: species per lane, the occupancy the
+// register allocation aims at, and the form of the column-pass divisor (V
+// form: fewer operations, one more table plane).  Chosen per (precision, n)
+// from measurements; cil_set_option(CIL_OPT_QUAD_SHAPE) overrides.
 struct QuadShape {
-    int spl, wpe;
+    int spl, wpe, vform;
 };
-constexpr int kQuadShapes = 3;
-constexpr QuadShape kQuadShape[kQuadShapes] = {{2, 2}, {1, 4}, {1, 2}};
+constexpr int kQuadShapes = 6;
+constexpr QuadShape kQuadShape[kQuadShapes] = {{2, 2, 0}, {1, 4, 0}, {1, 2, 0}, {2, 2, 1}, {1, 4, 1}, {1, 2, 1}};
 int g_quad_shape_option = -1;
 
-template <typename T, int N, int SPL, int WPE>
+template <typename T, int N, int SPL, int WPE, bool VF>
 void launch_q1(int nl, const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt,
                const PersistArgs &pa, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fused_q<T, N, SPL, WPE>), dim3(nl), dim3((8 / SPL) * N), 0, st, S, list, state, tables,
+    hipLaunchKernelGGL((k_fused_q<T, N, SPL, WPE, VF>), dim3(nl), dim3((8 / SPL) * N), 0, st, S, list, state, tables,
                        model, dt, pa);
 }
 
@@ -720,9 +799,12 @@ void launch_q(int shape, int nl, const DevSolve *S, const int *list, T *state, c
               const PersistArgs &pa, hipStream_t st)
 {
     switch (shape) {
-    case 0: launch_q1<T, N, 2, 2>(nl, S, list, state, tables, model, dt, pa, st); break;
-    case 1: launch_q1<T, N, 1, 4>(nl, S, list, state, tables, model, dt, pa, st); break;
-    default: launch_q1<T, N, 1, 2>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 0: launch_q1<T, N, 2, 2, false>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 1: launch_q1<T, N, 1, 4, false>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 2: launch_q1<T, N, 1, 2, false>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 3: launch_q1<T, N, 2, 2, true>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 4: launch_q1<T, N, 1, 4, true>(nl, S, list, state, tables, model, dt, pa, st); break;
+    default: launch_q1<T, N, 1, 2, true>(nl, S, list, state, tables, model, dt, pa, st); break;
     }
 }
 
@@ -731,7 +813,7 @@ int quad_shape(bool f32, int n)
     if (g_quad_shape_option >= 0) return g_quad_shape_option;
     // measured on MI355X, GM 64^2 / BZ 32^2 and 128^2 batches: both species per
     // lane wins wherever its registers allow two or more solves per CU
-    if (f32) return n == 64 ? 0 : 1;
+    if (f32) return 3;
     return 0;
 }
 
@@ -851,7 +933,7 @@ struct SimCtx {
 // Spectral tables for the solves in `ids` (side n): one per distinct (h, nu);
 // sets hs[b].tab.  Returns the device table buffer.
 template <typename T>
-int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSolve> &hs, void **tables)
+int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSolve> &hs, void **tables, bool vform)
 {
     std::map<std::tuple<double, double, double>, int> uniq;
     std::vector<TabSpec> specs;
@@ -867,6 +949,14 @@ int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSo
     void *dspecs;
     CIL_TRY(c.cb->alloc(&dspecs, sizeof(TabSpec) * specs.size()));
     CIL_HIP(hipMemcpyAsync(dspecs, specs.data(), sizeof(TabSpec) * specs.size(), hipMemcpyHostToDevice, c.st));
+    if (vform) {
+        const size_t per = (size_t)2 * 3 * (n / 2 + 1) * n;
+        CIL_TRY(c.cb->alloc(tables, sizeof(T) * per * specs.size()));
+        dim3 grid((unsigned)((2 * (n / 2 + 1) * n + 255) / 256), (unsigned)specs.size());
+        hipLaunchKernelGGL(k_make_vtables<T>, grid, dim3(256), 0, c.st, (const TabSpec *)dspecs, (int)specs.size(), n,
+                           c.dt, (T *)*tables);
+        return check_launch("k_make_vtables");
+    }
     CIL_TRY(c.cb->alloc(tables, sizeof(T) * (size_t)2 * n * n * specs.size()));
     dim3 grid((2 * n * n + 255) / 256, (unsigned)specs.size());
     hipLaunchKernelGGL(k_make_tables<T>, grid, dim3(256), 0, c.st, (const TabSpec *)dspecs, (int)specs.size(), n, c.dt,
@@ -885,7 +975,8 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
     std::vector<void *> tabs;
     for (auto &kv : byn) {
         void *t;
-        CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &t));
+        CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &t,
+                               quad && kQuadShape[quad_shape(std::is_same<T, float>::value, kv.first)].vform));
         tabs.push_back(t);
     }
     const int B = (int)hs.size();
