@@ -65,6 +65,38 @@ def fused_step_flops(n: int, reaction_flops: int) -> int:
 REACTION_FLOPS = {0: 12, 1: 13, 2: 13, 3: 13, 4: 4}   # kinetics + the explicit update, per point
 
 
+# Sources that define the fused stepper kernels (device code, launch shape).
+STEPPER_SOURCES = ["stepper.hip", "stepper_common.hpp", "stepper_quad.hpp", "stepper_quad_f32.hip",
+                   "stepper_quad_f64.hip", "dct_quad.hpp", "cil_internal.hpp"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_q_f64_n64_gm_source64_hbm_bytes.md")
+
+
+def stepper_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEPPER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_14742_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kname: str):
+    """HBM bytes per launch of `kname` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration),
+    or None when there is none or the stepper sources changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            lines = [ln.split() for ln in fh if ln.startswith("traffic ")]
+    except OSError:
+        return None
+    for ln in lines:
+        kv = dict(x.split("=", 1) for x in ln[2:])
+        if ln[1] == kname and kv.get("sources") == stepper_sources_sha256():
+            return int(round(1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                                       float(kv["write_kib"]) * float(kv["write_scale"]))))
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +106,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32-stepping", action="store_true")
     ap.add_argument("--cpu-sample-solves", type=int, default=96)
+    ap.add_argument("--sources-sha256", action="store_true",
+                    help="print the hash of the stepper sources (recorded beside the HBM counters) and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "that scales HBM byte counters)")
@@ -82,6 +116,9 @@ def parse():
 
 def main():
     args = parse()
+    if args.sources_sha256:
+        print(stepper_sources_sha256())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(solves and pair tiles would shard by index with no communication but one all-reduce "
@@ -191,7 +228,7 @@ def main():
         achieved = flops / cnt / (avg_ms * 1e-3) / 1e12
         peak = VALU_FP64_PEAK_TFLOPS if f64 else VALU_FP32_PEAK_TFLOPS
         roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "launches": cnt,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname), "launches": cnt,
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_solve_step": fused_step_flops(n, REACTION_FLOPS[w["model"]]),
                 "solve_steps": solve_steps}
     gram = None

@@ -231,11 +231,10 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  * CIL_OPT_FORCE_EXACT_SUM (value 0/1): every canonical distance is taken by
  *   the exact (slow) summation instead of the certified double-double one;
  *   for testing that path.
- * CIL_OPT_QUAD_SHAPE (value -1..5): code shape of the fused quad-lane stepper,
- *   -1 = chosen by precision and grid side (default); 0 = both species of a
- *   grid line in one lane, 4n threads per solve; 1 = one species per lane, 8n
- *   threads, register target 128; 2 = the same with register target 256;
- *   3..5 = shapes 0..2 with the column-pass divisor applied in the split
+ * CIL_OPT_QUAD_SHAPE (value -1..3): code shape of the fused quad-lane stepper,
+ *   -1 = chosen by precision (default); 0 = both species of a grid line in
+ *   one lane, 4n threads per solve; 1 = one species per lane, 8n threads;
+ *   2, 3 = shapes 0, 1 with the column-pass divisor applied in the split
  *   step's complex form (fewer operations, a larger table).  Every shape
  *   computes the same step; timing and register use differ. */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2 };

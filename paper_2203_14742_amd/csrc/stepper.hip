@@ -31,91 +31,10 @@
 #include <vector>
 
 #include "cil_internal.hpp"
-#include "dct_quad.hpp"
 #include "dct_reg.hpp"
+#include "stepper_common.hpp"
 
 namespace cil {
-
-struct DevSolve {
-    int64_t off;     // element offset of the solve's state
-    int32_t n;
-    int32_t tab;     // spectral-table index (fused back-end)
-    double inv_h2;   // 1/h^2, h = L/(n-1)
-    double nu[2];
-    double p[4];
-};
-
-struct StepResults {               // indexed by solve
-    unsigned long long *resid;     // bits of a non-negative double: max |du|
-    unsigned long long *maxabs;    // bits of max |u|
-    int *bad;                      // non-finite value seen
-};
-
-// 1/w from the hardware reciprocal and Newton steps e = 1 - w r, r += r e
-// (two in FP64, one in FP32): within about one unit in the last place of
-// the correctly rounded quotient, at half the instructions of IEEE division.
-template <typename T>
-__device__ __forceinline__ T recip(T w)
-{
-    if constexpr (sizeof(T) == 8) {
-        double r = __builtin_amdgcn_rcp(w);
-        double e = fma(-w, r, 1.0);
-        r = fma(r, e, r);
-        e = fma(-w, r, 1.0);
-        return fma(r, e, r);
-    } else {
-        const float r = __builtin_amdgcn_rcpf(w);
-        return fmaf(r, fmaf(-w, r, 1.0f), r);
-    }
-}
-
-// -------------------------------------------------------------- kinetics
-// Sec. 4.1 reaction terms; the model is uniform over a launch.
-template <int MODEL, typename T>
-__device__ __forceinline__ void kinetics(const T *p, T v, T w, T &f, T &g)
-{
-    if constexpr (MODEL == CIL_FHN) {
-        f = p[1] * (w - p[2] * v);
-        g = -v + p[0] * w - w * w * w;
-    } else if constexpr (MODEL == CIL_GM) {
-        f = -p[0] * v + v * v * recip(w);
-        g = -p[1] * w + v * v;
-    } else if constexpr (MODEL == CIL_GM_SOURCE) {
-        f = p[0] - p[1] * v + v * v * recip(w);
-        g = v * v - w;
-    } else if constexpr (MODEL == CIL_BRUSSELATOR) {
-        f = p[0] - (p[1] + T(1)) * v + v * v * w;
-        g = p[1] * v - v * v * w;
-    } else {
-        f = T(0);
-        g = T(0);
-    }
-}
-
-template <typename F>
-__device__ __forceinline__ void dispatch_model(int model, F &&f)
-{
-    switch (model) {
-    case CIL_FHN: f(std::integral_constant<int, CIL_FHN>{}); break;
-    case CIL_GM: f(std::integral_constant<int, CIL_GM>{}); break;
-    case CIL_GM_SOURCE: f(std::integral_constant<int, CIL_GM_SOURCE>{}); break;
-    case CIL_BRUSSELATOR: f(std::integral_constant<int, CIL_BRUSSELATOR>{}); break;
-    default: f(std::integral_constant<int, CIL_HEAT>{}); break;
-    }
-}
-
-__device__ __forceinline__ double wave_max(double x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-    return x;
-}
-__device__ __forceinline__ int wave_or(int x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
-    return x;
-}
 
 __global__ void k_clear_results(const int *list, int nlist, StepResults R)
 {
@@ -251,15 +170,6 @@ __global__ void k_plain_rows_inv(const DevSolve *S, const int *list, const T *in
 // max |u^s - u^{s-1}| / dt, max |u| and a non-finite flag over both species,
 // and retires when the stop rule fires.  No host round trip per step.
 
-struct PersistArgs {
-    long long max_steps;
-    double tol;
-    int check;
-    double floor_coef;          // FP32 stepping: floor_ulps 2^-24 / dt, so the floor is floor_coef max|u|; 0 = off
-    long long *steps;           // per solve: steps taken (in: start, out: end)
-    double *resid;              // per solve: residual of the last evaluated step
-    int *status;                // per solve: cil_solve_status
-};
 
 template <int N>
 __device__ __forceinline__ int lds_addr(int e)
@@ -398,256 +308,6 @@ __global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *l
     });
 }
 
-// One solve of the quad variant (below), for one model.  SPL = species per
-// lane: 2 (4N threads; quad g owns row/column g of both species) or 1 (8N
-// threads; group g of eight lanes owns row/column g, species s = (t / 4) & 1,
-// quad position q = t & 3 for v and 3 - (t & 3) for w, so that lane t ^ 7 -
-// the DPP half-row mirror - holds the other species at the same points).
-template <typename T, int N, int SPL, bool VF, typename MD>
-__device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, const DevSolve &s, int b, T *state,
-                                              const T *tables, double dt, const PersistArgs &pa)
-{
-    using Q = QuadLine<T, N>;
-    constexpr int P = Q::P, M = N / 2;
-    constexpr int LD = N + 1, SP = N * LD, NN = N * N;
-    constexpr int THREADS = (8 / SPL) * N, WAVES = THREADS / 64;
-    const int tid = threadIdx.x;
-    const int g = SPL == 2 ? tid >> 2 : tid >> 3;
-    const int sp0 = SPL == 2 ? 0 : (tid >> 2) & 1;          // the lane's first species
-    const int q = (SPL == 1 && sp0) ? 3 - (tid & 3) : (tid & 3);
-    typename Q::Lane L;
-    Q::init(L, q);
-    const T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
-    const T tdt = T(dt);
-    const int kb = P * L.k2;
-    // Addresses: a uniform base, a per-lane offset and a compile-time offset
-    // that is never negative (so LDS and buffer instructions take it as an
-    // immediate).  Line values: pairs m1 < P/2 at lo + 16 m1 + 2h, the others
-    // at hi - 16 m1 - 2h = hi0 + (16 (P - 1) + 2 - 16 m1 - 2h).
-    constexpr int HI_SPAN = 16 * (P - 1) + 2;
-    const int lo = Q::template pos_base<0>(q), hi0 = Q::template pos_base<P - 1>(q) - HI_SPAN;
-    auto line_off = [&](auto m1c, auto hc) {        // offset of a line value from its base
-        constexpr int m1 = decltype(m1c)::value, h = decltype(hc)::value;
-        return m1 < P / 2 ? 16 * m1 + 2 * h : HI_SPAN - 16 * m1 - 2 * h;
-    };
-    const auto ub = make_rsrc(state + s.off, 2 * NN * sizeof(T));                    // the solve's state
-    const unsigned hu0 = (sp0 * NN + g * N + lo) * sizeof(T), hu1 = (sp0 * NN + g * N + hi0) * sizeof(T);
-    T *const smp = sm + sp0 * SP;
-    T *const cb0 = smp + lo * LD + g, *const cb1 = smp + hi0 * LD + g;   // column g, first species
-    T *const rk = smp + g * LD + kb;                            // X_k of row g at rk[k1]
-    T *const rn = smp + g * LD + (N - kb) - (P - 1);            // X_{N-k} at rn[P - 1 - k1]
-    T *const rm = smp + g * LD + M;
-    // Spectral divisor of the column pass.  VF: in the split step's V form,
-    // [species][A | B | Ci][k = 0..M][l] (k_make_vtables); else the plain
-    // divisors [species][k][l] (k_make_tables) applied to X_k and X_{N-k}.
-    constexpr int VPL = (M + 1) * N, VSP = VF ? 3 * VPL : NN;
-    const auto tb = make_rsrc(tables + (size_t)s.tab * 2 * VSP, 2 * VSP * sizeof(T));
-    const unsigned tko = (sp0 * VSP + kb * N + g) * sizeof(T), tmo = (sp0 * VSP + M * N + g) * sizeof(T);
-    const unsigned tno = (sp0 * VSP + (N - kb - (P - 1)) * N + g) * sizeof(T);
-
-    T ur[SPL][P], ui[SPL][P];     // the lane's 2P values of each of its species along row g, natural order
-    auto hbm_ld = [&](auto m1c, auto hc, int c) -> T {
-        constexpr int m1 = decltype(m1c)::value;
-        return buf_load<T>(ub, (m1 < P / 2 ? hu0 : hu1) + line_off(m1c, hc) * sizeof(T), c * NN * sizeof(T));
-    };
-    auto hbm_st = [&](T v, auto m1c, auto hc, int c) {
-        constexpr int m1 = decltype(m1c)::value;
-        buf_store<T>(v, ub, (m1 < P / 2 ? hu0 : hu1) + line_off(m1c, hc) * sizeof(T), c * NN * sizeof(T));
-    };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    static_for<0, P>([&](auto Mi) {
-#pragma unroll
-        for (int c = 0; c < SPL; ++c) {
-            ur[c][Mi] = hbm_ld(Mi, I0{}, c);
-            ui[c][Mi] = hbm_ld(Mi, I1{}, c);
-        }
-    });
-    const long long start = pa.steps[b];
-    long long step = start;
-    while (true) {
-        const bool eval_now = step > start && ((step % pa.check == 0) || step == pa.max_steps);
-        if (eval_now) {       // stop rule on u^step against the snapshot of u^(step-1)
-            double d = 0.0, a = 0.0;
-            int bad = 0;
-            static_for<0, P>([&](auto Mi) {
-#pragma unroll
-                for (int c = 0; c < SPL; ++c) {
-                    const T o0 = hbm_ld(Mi, I0{}, c), o1 = hbm_ld(Mi, I1{}, c);
-                    const double v0 = (double)ur[c][Mi], v1 = (double)ui[c][Mi];
-                    const double d0 = fabs(v0 - (double)o0), d1 = fabs(v1 - (double)o1);
-                    bad |= !isfinite(v0) || !isfinite(v1);
-                    d = fmax(d, fmax(isnan(d0) ? 0.0 : d0, isnan(d1) ? 0.0 : d1));
-                    a = fmax(a, fmax(isnan(v0) ? 0.0 : fabs(v0), isnan(v1) ? 0.0 : fabs(v1)));
-                }
-            });
-            d = wave_max(d);
-            a = wave_max(a);
-            bad = wave_or(bad);
-            if ((tid & 63) == 0) {
-                red[tid >> 6] = d;
-                red[WAVES + (tid >> 6)] = a;
-                sbad[tid >> 6] = bad;
-            }
-            __syncthreads();
-            double dm = 0.0, am = 0.0;
-            int anybad = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                dm = fmax(dm, red[w]);
-                am = fmax(am, red[WAVES + w]);
-                anybad |= sbad[w];
-            }
-            const double r = dm / dt;
-            int st = -1;
-            if (anybad) st = CIL_SOLVE_NONFINITE;
-            else if (pa.tol > 0.0 && r < pa.tol) st = CIL_SOLVE_OK;
-            else if (pa.tol > 0.0 && pa.floor_coef > 0.0 && r < pa.floor_coef * am) st = CIL_SOLVE_FP32_FLOOR;
-            else if (step == pa.max_steps) st = pa.tol > 0.0 ? CIL_SOLVE_MAXSTEPS : CIL_SOLVE_OK;
-            if (tid == 0) {
-                pa.resid[b] = anybad ? (double)NAN : r;
-                if (st >= 0) pa.status[b] = st;
-            }
-            if (st >= 0) break;
-        }
-        if (step >= pa.max_steps) break;
-        const long long next = step + 1;
-        if ((next % pa.check == 0) || next == pa.max_steps) {     // snapshot u^step for the next stop rule
-            static_for<0, P>([&](auto Mi) {
-#pragma unroll
-                for (int c = 0; c < SPL; ++c) {
-                    hbm_st(ur[c][Mi], Mi, I0{}, c);
-                    hbm_st(ui[c][Mi], Mi, I1{}, c);
-                }
-            });
-        }
-        // explicit reaction from old values, into bit-reversed order for the forward
-        T xr[SPL][P], xi[SPL][P];
-        static_for<0, P>([&](auto Mi) {
-            constexpr int m1 = Mi;
-            constexpr int pb = bitrev(m1, Q::LOGP);
-            T f, gg;
-            if constexpr (SPL == 2) {
-                kinetics<MD::value>(p, ur[0][m1], ur[1][m1], f, gg);
-                xr[0][pb] = ur[0][m1] + tdt * f;
-                xr[1][pb] = ur[1][m1] + tdt * gg;
-                kinetics<MD::value>(p, ui[0][m1], ui[1][m1], f, gg);
-                xi[0][pb] = ui[0][m1] + tdt * f;
-                xi[1][pb] = ui[1][m1] + tdt * gg;
-            } else {
-                const T pr = dpp_mov<DPP_HALF_MIRROR>(ur[0][m1]), pi = dpp_mov<DPP_HALF_MIRROR>(ui[0][m1]);
-                kinetics<MD::value>(p, sp0 ? pr : ur[0][m1], sp0 ? ur[0][m1] : pr, f, gg);
-                xr[0][pb] = ur[0][m1] + tdt * (sp0 ? gg : f);
-                kinetics<MD::value>(p, sp0 ? pi : ui[0][m1], sp0 ? ui[0][m1] : pi, f, gg);
-                xi[0][pb] = ui[0][m1] + tdt * (sp0 ? gg : f);
-            }
-        });
-        T xa[SPL][P], xb[SPL][P], xm[SPL];
-#pragma unroll
-        for (int c = 0; c < SPL; ++c) {
-            Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
-            static_for<0, P>([&](auto Ki) {
-                constexpr int k1 = Ki;
-                rk[c * SP + k1] = xa[c][k1];
-                if (k1 != 0 || kb != 0) rn[c * SP + (P - 1 - k1)] = xb[c][k1];
-            });
-            if (q == 0) rm[c * SP] = xm[c];
-        }
-        __syncthreads();
-        // column g: forward, divide, inverse
-#pragma unroll
-        for (int c = 0; c < SPL; ++c) {
-            static_for<0, P>([&](auto Mi) {
-                constexpr int m1 = Mi;
-                constexpr int pb = bitrev(m1, Q::LOGP);
-                const T *cc = (m1 < P / 2 ? cb0 : cb1) + c * SP;
-                xr[c][pb] = cc[line_off(Mi, I0{}) * LD];
-                xi[c][pb] = cc[line_off(Mi, I1{}) * LD];
-            });
-            const int cso = c * VSP * sizeof(T);
-            if constexpr (VF) {
-                Q::forward_v(L, xr[c], xi[c], xa[c], xb[c], xm[c]);       // xa/xb: Re/Im V_k
-                static_for<0, P>([&](auto Ki) {
-                    constexpr int k1 = Ki;
-                    const T A = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
-                    const T B = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + VPL * sizeof(T));
-                    const T C = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + 2 * VPL * sizeof(T));
-                    const T re = xa[c][k1], im = xb[c][k1];
-                    xa[c][k1] = A * re + C * im;
-                    xb[c][k1] = B * im + C * re;
-                });
-                xm[c] *= buf_load<T>(tb, tmo, cso);
-                Q::inverse_v(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
-            } else {
-                Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
-                static_for<0, P>([&](auto Ki) {
-                    constexpr int k1 = Ki;
-                    xa[c][k1] *= buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
-                    if constexpr (k1 == 0) xb[c][0] *= buf_load<T>(tb, kb == 0 ? tmo : tno + (P - 1) * N * sizeof(T), cso);
-                    else xb[c][k1] *= buf_load<T>(tb, tno + (P - 1 - k1) * N * sizeof(T), cso);
-                });
-                xm[c] *= buf_load<T>(tb, tmo, cso);
-                Q::inverse_regs(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
-            }
-            static_for<0, P>([&](auto Mi) {
-                constexpr int m1 = Mi;
-                T *cc = (m1 < P / 2 ? cb0 : cb1) + c * SP;
-                cc[line_off(Mi, I0{}) * LD] = xr[c][m1];
-                cc[line_off(Mi, I1{}) * LD] = xi[c][m1];
-            });
-        }
-        __syncthreads();
-        // row g inverse: u^(step+1)
-#pragma unroll
-        for (int c = 0; c < SPL; ++c) {
-            static_for<0, P>([&](auto Ki) {
-                constexpr int k1 = Ki;
-                xa[c][k1] = rk[c * SP + k1];
-                if constexpr (k1 == 0) xb[c][0] = (kb == 0) ? T(0) : rn[c * SP + (P - 1)];
-                else xb[c][k1] = rn[c * SP + (P - 1 - k1)];
-            });
-            xm[c] = rm[c * SP];
-            Q::inverse_regs(L, xa[c], xb[c], xm[c], ur[c], ui[c]);
-        }
-        step = next;
-    }
-    static_for<0, P>([&](auto Mi) {
-#pragma unroll
-        for (int c = 0; c < SPL; ++c) {
-            hbm_st(ur[c][Mi], Mi, I0{}, c);
-            hbm_st(ui[c][Mi], Mi, I1{}, c);
-        }
-    });
-    if (tid == 0) pa.steps[b] = step;
-}
-
-// Quad variant: every line is transformed by a quad of lanes (dct_quad.hpp);
-// each workgroup runs one solve.  Between steps the state is kept in LDS as
-// the row-spectral field (after the column inverse).  One step is two passes,
-// each ending with the workgroup barrier:
-//   row pass     row inverse (u^s in registers), stop rule and snapshot at
-//                evaluation steps, explicit reaction (both species of a point
-//                in one lane, or in lanes t and t ^ 7), row forward -> LDS;
-//   column pass  column forward, spectral divide, column inverse, all in
-//                registers (the split-step partners come by DPP) -> LDS.
-// The first row pass loads u from HBM instead; the last stores it there.
-// The model is dispatched once, outside the step loop.  WPE is the occupancy
-// the register allocation aims at (waves per SIMD).
-template <typename T, int N, int SPL, int WPE, bool VF>
-__global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(WPE))) void k_fused_q(
-    const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt, PersistArgs pa)
-{
-    constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64;
-    __shared__ T sm[2 * SP];
-    __shared__ double red[2 * WAVES];
-    __shared__ int sbad[WAVES];
-    const int b = list[blockIdx.x];
-    const DevSolve s = S[b];
-    dispatch_model(model, [&](auto MD) {
-        fused_q_solve<T, N, SPL, VF, decltype(MD)>(sm, red, sbad, s, b, state, tables, dt, pa);
-    });
-}
-
 // Spectral tables for the fused back-end:
 // tab[s][k][l] = 1 / (4 N^2 (1 + dt nu_s (lam_k + lam_l) / h^2)), in FP64 then T.
 struct TabSpec {
@@ -775,46 +435,15 @@ int fused_supported(int n, bool f32)
     return f32 ? (n == 32 || n == 64 || n == 128) : (n == 32 || n == 64);
 }
 
-// Code shapes of the quad variant: species per lane, the occupancy the
-// register allocation aims at, and the form of the column-pass divisor (V
-// form: fewer operations, one more table plane).  Chosen per (precision, n)
-// from measurements; cil_set_option(CIL_OPT_QUAD_SHAPE) overrides.
-struct QuadShape {
-    int spl, wpe, vform;
-};
-constexpr int kQuadShapes = 6;
-constexpr QuadShape kQuadShape[kQuadShapes] = {{2, 2, 0}, {1, 4, 0}, {1, 2, 0}, {2, 2, 1}, {1, 4, 1}, {1, 2, 1}};
 int g_quad_shape_option = -1;
-
-template <typename T, int N, int SPL, int WPE, bool VF>
-void launch_q1(int nl, const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt,
-               const PersistArgs &pa, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_fused_q<T, N, SPL, WPE, VF>), dim3(nl), dim3((8 / SPL) * N), 0, st, S, list, state, tables,
-                       model, dt, pa);
-}
-
-template <typename T, int N>
-void launch_q(int shape, int nl, const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt,
-              const PersistArgs &pa, hipStream_t st)
-{
-    switch (shape) {
-    case 0: launch_q1<T, N, 2, 2, false>(nl, S, list, state, tables, model, dt, pa, st); break;
-    case 1: launch_q1<T, N, 1, 4, false>(nl, S, list, state, tables, model, dt, pa, st); break;
-    case 2: launch_q1<T, N, 1, 2, false>(nl, S, list, state, tables, model, dt, pa, st); break;
-    case 3: launch_q1<T, N, 2, 2, true>(nl, S, list, state, tables, model, dt, pa, st); break;
-    case 4: launch_q1<T, N, 1, 4, true>(nl, S, list, state, tables, model, dt, pa, st); break;
-    default: launch_q1<T, N, 1, 2, true>(nl, S, list, state, tables, model, dt, pa, st); break;
-    }
-}
 
 int quad_shape(bool f32, int n)
 {
     if (g_quad_shape_option >= 0) return g_quad_shape_option;
-    // measured on MI355X, GM 64^2 / BZ 32^2 and 128^2 batches: both species per
-    // lane wins wherever its registers allow two or more solves per CU
-    if (f32) return 3;
-    return 0;
+    // measured on MI355X (GM 64^2, BZ 32^2 and 128^2 batches): both species
+    // per lane; the V-form divisor pays in FP32, not in FP64 (its third table
+    // plane costs more load latency than it saves operations)
+    return f32 ? 2 : 0;
 }
 
 }  // namespace
@@ -842,12 +471,10 @@ int launch_persistent(int n, bool quad, int shape, int nl, const DevSolve *S, co
     if (!f32 && n == 128) return set_error(CIL_EUNSUPPORTED, "fused FP64 stepper supports n = 32, 64");
     const ProfMark pm = prof_begin(name, st);
     if (quad) {
-        if (n == 32)
-            launch_q<T, 32>(shape, nl, S, list, state, tables, model, dt, pa, st);
-        else if (n == 64)
-            launch_q<T, 64>(shape, nl, S, list, state, tables, model, dt, pa, st);
-        else if constexpr (std::is_same<T, float>::value)
-            launch_q<T, 128>(shape, nl, S, list, state, tables, model, dt, pa, st);
+        const int rc = f32 ? launch_quad_f32(n, shape, nl, S, list, (float *)state, (const float *)tables, model, dt, pa, st)
+                           : launch_quad_f64(n, shape, nl, S, list, (double *)state, (const double *)tables, model, dt,
+                                             pa, st);
+        if (rc) return set_error(rc, "no fused quad kernel for n = %d", n);
     } else {
         if (n == 32)
             hipLaunchKernelGGL((k_fused<T, 32>), dim3(nl), dim3(64), 0, st, S, list, state, tables, model, dt, pa);

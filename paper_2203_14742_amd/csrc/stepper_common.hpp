@@ -1,0 +1,123 @@
+// Device-side pieces shared by the stepper's translation units: the solve
+// descriptor, the Sec. 4.1 kinetics, wave reductions and the persistent
+// kernels' stop-rule arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "cil.h"
+#include "cil_internal.hpp"
+
+namespace cil {
+
+struct DevSolve {
+    int64_t off;     // element offset of the solve's state
+    int32_t n;
+    int32_t tab;     // spectral-table index (fused back-end)
+    double inv_h2;   // 1/h^2, h = L/(n-1)
+    double nu[2];
+    double p[4];
+};
+
+struct StepResults {               // indexed by solve
+    unsigned long long *resid;     // bits of a non-negative double: max |du|
+    unsigned long long *maxabs;    // bits of max |u|
+    int *bad;                      // non-finite value seen
+};
+
+// 1/w from the hardware reciprocal and Newton steps e = 1 - w r, r += r e
+// (two in FP64, one in FP32): within about one unit in the last place of
+// the correctly rounded quotient, at half the instructions of IEEE division.
+template <typename T>
+__device__ __forceinline__ T recip(T w)
+{
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rcp(w);
+        double e = fma(-w, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-w, r, 1.0);
+        return fma(r, e, r);
+    } else {
+        const float r = __builtin_amdgcn_rcpf(w);
+        return fmaf(r, fmaf(-w, r, 1.0f), r);
+    }
+}
+
+// -------------------------------------------------------------- kinetics
+// Sec. 4.1 reaction terms; the model is uniform over a launch.
+template <int MODEL, typename T>
+__device__ __forceinline__ void kinetics(const T *p, T v, T w, T &f, T &g)
+{
+    if constexpr (MODEL == CIL_FHN) {
+        f = p[1] * (w - p[2] * v);
+        g = -v + p[0] * w - w * w * w;
+    } else if constexpr (MODEL == CIL_GM) {
+        f = -p[0] * v + v * v * recip(w);
+        g = -p[1] * w + v * v;
+    } else if constexpr (MODEL == CIL_GM_SOURCE) {
+        f = p[0] - p[1] * v + v * v * recip(w);
+        g = v * v - w;
+    } else if constexpr (MODEL == CIL_BRUSSELATOR) {
+        f = p[0] - (p[1] + T(1)) * v + v * v * w;
+        g = p[1] * v - v * v * w;
+    } else {
+        f = T(0);
+        g = T(0);
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ void dispatch_model(int model, F &&f)
+{
+    switch (model) {
+    case CIL_FHN: f(std::integral_constant<int, CIL_FHN>{}); break;
+    case CIL_GM: f(std::integral_constant<int, CIL_GM>{}); break;
+    case CIL_GM_SOURCE: f(std::integral_constant<int, CIL_GM_SOURCE>{}); break;
+    case CIL_BRUSSELATOR: f(std::integral_constant<int, CIL_BRUSSELATOR>{}); break;
+    default: f(std::integral_constant<int, CIL_HEAT>{}); break;
+    }
+}
+
+__device__ __forceinline__ inline double wave_max(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ inline int wave_or(int x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+    return x;
+}
+
+struct PersistArgs {
+    long long max_steps;
+    double tol;
+    int check;
+    double floor_coef;          // FP32 stepping: floor_ulps 2^-24 / dt, so the floor is floor_coef max|u|; 0 = off
+    long long *steps;           // per solve: steps taken (in: start, out: end)
+    double *resid;              // per solve: residual of the last evaluated step
+    int *status;                // per solve: cil_solve_status
+};
+
+// Quad-variant launch, one translation unit per precision (stepper_quad_*.hip).
+int launch_quad_f32(int n, int shape, int nl, const DevSolve *S, const int *list, float *state, const float *tables,
+                    int model, double dt, const PersistArgs &pa, hipStream_t st);
+int launch_quad_f64(int n, int shape, int nl, const DevSolve *S, const int *list, double *state, const double *tables,
+                    int model, double dt, const PersistArgs &pa, hipStream_t st);
+
+// Code shapes of the quad variant: species per lane, the occupancy the
+// register allocation aims at, and the form of the column-pass divisor (V
+// form: fewer operations, one more table plane).  Chosen per (precision, n)
+// from measurements; cil_set_option(CIL_OPT_QUAD_SHAPE) overrides.
+struct QuadShape {
+    int spl, wpe, vform;
+};
+constexpr int kQuadShapes = 4;
+constexpr QuadShape kQuadShape[kQuadShapes] = {{2, 2, 0}, {1, 2, 0}, {2, 2, 1}, {1, 2, 1}};
+
+}  // namespace cil

@@ -1,0 +1,280 @@
+// The quad-lane persistent stepper (templates), instantiated per precision
+// by stepper_quad_f32.hip and stepper_quad_f64.hip.
+#pragma once
+
+#include "dct_quad.hpp"
+#include "stepper_common.hpp"
+
+namespace cil {
+
+// One solve of the quad variant (below), for one model.  SPL = species per
+// lane: 2 (4N threads; quad g owns row/column g of both species) or 1 (8N
+// threads; group g of eight lanes owns row/column g, species s = (t / 4) & 1,
+// quad position q = t & 3 for v and 3 - (t & 3) for w, so that lane t ^ 7 -
+// the DPP half-row mirror - holds the other species at the same points).
+template <typename T, int N, int SPL, bool VF, typename MD>
+__device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, const DevSolve &s, int b, T *state,
+                                              const T *tables, double dt, const PersistArgs &pa)
+{
+    using Q = QuadLine<T, N>;
+    constexpr int P = Q::P, M = N / 2;
+    constexpr int LD = N + 1, SP = N * LD, NN = N * N;
+    constexpr int THREADS = (8 / SPL) * N, WAVES = THREADS / 64;
+    const int tid = threadIdx.x;
+    const int g = SPL == 2 ? tid >> 2 : tid >> 3;
+    const int sp0 = SPL == 2 ? 0 : (tid >> 2) & 1;          // the lane's first species
+    const int q = (SPL == 1 && sp0) ? 3 - (tid & 3) : (tid & 3);
+    typename Q::Lane L;
+    Q::init(L, q);
+    const T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
+    const T tdt = T(dt);
+    const int kb = P * L.k2;
+    // Addresses: a uniform base, a per-lane offset and a compile-time offset
+    // that is never negative (so LDS and buffer instructions take it as an
+    // immediate).  Line values: pairs m1 < P/2 at lo + 16 m1 + 2h, the others
+    // at hi - 16 m1 - 2h = hi0 + (16 (P - 1) + 2 - 16 m1 - 2h).
+    constexpr int HI_SPAN = 16 * (P - 1) + 2;
+    const int lo = Q::template pos_base<0>(q), hi0 = Q::template pos_base<P - 1>(q) - HI_SPAN;
+    auto line_off = [&](auto m1c, auto hc) {        // offset of a line value from its base
+        constexpr int m1 = decltype(m1c)::value, h = decltype(hc)::value;
+        return m1 < P / 2 ? 16 * m1 + 2 * h : HI_SPAN - 16 * m1 - 2 * h;
+    };
+    const auto ub = make_rsrc(state + s.off, 2 * NN * sizeof(T));                    // the solve's state
+    const unsigned hu0 = (sp0 * NN + g * N + lo) * sizeof(T), hu1 = (sp0 * NN + g * N + hi0) * sizeof(T);
+    T *const smp = sm + sp0 * SP;
+    T *const cb0 = smp + lo * LD + g, *const cb1 = smp + hi0 * LD + g;   // column g, first species
+    T *const rk = smp + g * LD + kb;                            // X_k of row g at rk[k1]
+    T *const rn = smp + g * LD + (N - kb) - (P - 1);            // X_{N-k} at rn[P - 1 - k1]
+    T *const rm = smp + g * LD + M;
+    // Spectral divisor of the column pass.  VF: in the split step's V form,
+    // [species][A | B | Ci][k = 0..M][l] (k_make_vtables); else the plain
+    // divisors [species][k][l] (k_make_tables) applied to X_k and X_{N-k}.
+    constexpr int VPL = (M + 1) * N, VSP = VF ? 3 * VPL : NN;
+    const auto tb = make_rsrc(tables + (size_t)s.tab * 2 * VSP, 2 * VSP * sizeof(T));
+    const unsigned tko = (sp0 * VSP + kb * N + g) * sizeof(T), tmo = (sp0 * VSP + M * N + g) * sizeof(T);
+    const unsigned tno = (sp0 * VSP + (N - kb - (P - 1)) * N + g) * sizeof(T);
+
+    T ur[SPL][P], ui[SPL][P];     // the lane's 2P values of each of its species along row g, natural order
+    auto hbm_ld = [&](auto m1c, auto hc, int c) -> T {
+        constexpr int m1 = decltype(m1c)::value;
+        return buf_load<T>(ub, (m1 < P / 2 ? hu0 : hu1) + line_off(m1c, hc) * sizeof(T), c * NN * sizeof(T));
+    };
+    auto hbm_st = [&](T v, auto m1c, auto hc, int c) {
+        constexpr int m1 = decltype(m1c)::value;
+        buf_store<T>(v, ub, (m1 < P / 2 ? hu0 : hu1) + line_off(m1c, hc) * sizeof(T), c * NN * sizeof(T));
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    static_for<0, P>([&](auto Mi) {
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+            ur[c][Mi] = hbm_ld(Mi, I0{}, c);
+            ui[c][Mi] = hbm_ld(Mi, I1{}, c);
+        }
+    });
+    const long long start = pa.steps[b];
+    long long step = start;
+    while (true) {
+        const bool eval_now = step > start && ((step % pa.check == 0) || step == pa.max_steps);
+        if (eval_now) {       // stop rule on u^step against the snapshot of u^(step-1)
+            double d = 0.0, a = 0.0;
+            int bad = 0;
+            static_for<0, P>([&](auto Mi) {
+#pragma unroll
+                for (int c = 0; c < SPL; ++c) {
+                    const T o0 = hbm_ld(Mi, I0{}, c), o1 = hbm_ld(Mi, I1{}, c);
+                    const double v0 = (double)ur[c][Mi], v1 = (double)ui[c][Mi];
+                    const double d0 = fabs(v0 - (double)o0), d1 = fabs(v1 - (double)o1);
+                    bad |= !isfinite(v0) || !isfinite(v1);
+                    d = fmax(d, fmax(isnan(d0) ? 0.0 : d0, isnan(d1) ? 0.0 : d1));
+                    a = fmax(a, fmax(isnan(v0) ? 0.0 : fabs(v0), isnan(v1) ? 0.0 : fabs(v1)));
+                }
+            });
+            d = wave_max(d);
+            a = wave_max(a);
+            bad = wave_or(bad);
+            if ((tid & 63) == 0) {
+                red[tid >> 6] = d;
+                red[WAVES + (tid >> 6)] = a;
+                sbad[tid >> 6] = bad;
+            }
+            __syncthreads();
+            double dm = 0.0, am = 0.0;
+            int anybad = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                dm = fmax(dm, red[w]);
+                am = fmax(am, red[WAVES + w]);
+                anybad |= sbad[w];
+            }
+            const double r = dm / dt;
+            int st = -1;
+            if (anybad) st = CIL_SOLVE_NONFINITE;
+            else if (pa.tol > 0.0 && r < pa.tol) st = CIL_SOLVE_OK;
+            else if (pa.tol > 0.0 && pa.floor_coef > 0.0 && r < pa.floor_coef * am) st = CIL_SOLVE_FP32_FLOOR;
+            else if (step == pa.max_steps) st = pa.tol > 0.0 ? CIL_SOLVE_MAXSTEPS : CIL_SOLVE_OK;
+            if (tid == 0) {
+                pa.resid[b] = anybad ? (double)NAN : r;
+                if (st >= 0) pa.status[b] = st;
+            }
+            if (st >= 0) break;
+        }
+        if (step >= pa.max_steps) break;
+        const long long next = step + 1;
+        if ((next % pa.check == 0) || next == pa.max_steps) {     // snapshot u^step for the next stop rule
+            static_for<0, P>([&](auto Mi) {
+#pragma unroll
+                for (int c = 0; c < SPL; ++c) {
+                    hbm_st(ur[c][Mi], Mi, I0{}, c);
+                    hbm_st(ui[c][Mi], Mi, I1{}, c);
+                }
+            });
+        }
+        // explicit reaction from old values, into bit-reversed order for the forward
+        T xr[SPL][P], xi[SPL][P];
+        static_for<0, P>([&](auto Mi) {
+            constexpr int m1 = Mi;
+            constexpr int pb = bitrev(m1, Q::LOGP);
+            T f, gg;
+            if constexpr (SPL == 2) {
+                kinetics<MD::value>(p, ur[0][m1], ur[1][m1], f, gg);
+                xr[0][pb] = ur[0][m1] + tdt * f;
+                xr[1][pb] = ur[1][m1] + tdt * gg;
+                kinetics<MD::value>(p, ui[0][m1], ui[1][m1], f, gg);
+                xi[0][pb] = ui[0][m1] + tdt * f;
+                xi[1][pb] = ui[1][m1] + tdt * gg;
+            } else {
+                const T pr = dpp_mov<DPP_HALF_MIRROR>(ur[0][m1]), pi = dpp_mov<DPP_HALF_MIRROR>(ui[0][m1]);
+                kinetics<MD::value>(p, sp0 ? pr : ur[0][m1], sp0 ? ur[0][m1] : pr, f, gg);
+                xr[0][pb] = ur[0][m1] + tdt * (sp0 ? gg : f);
+                kinetics<MD::value>(p, sp0 ? pi : ui[0][m1], sp0 ? ui[0][m1] : pi, f, gg);
+                xi[0][pb] = ui[0][m1] + tdt * (sp0 ? gg : f);
+            }
+        });
+        T xa[SPL][P], xb[SPL][P], xm[SPL];
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+            Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
+            static_for<0, P>([&](auto Ki) {
+                constexpr int k1 = Ki;
+                rk[c * SP + k1] = xa[c][k1];
+                if (k1 != 0 || kb != 0) rn[c * SP + (P - 1 - k1)] = xb[c][k1];
+            });
+            if (q == 0) rm[c * SP] = xm[c];
+        }
+        __syncthreads();
+        // column g: forward, divide, inverse
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+            static_for<0, P>([&](auto Mi) {
+                constexpr int m1 = Mi;
+                constexpr int pb = bitrev(m1, Q::LOGP);
+                const T *cc = (m1 < P / 2 ? cb0 : cb1) + c * SP;
+                xr[c][pb] = cc[line_off(Mi, I0{}) * LD];
+                xi[c][pb] = cc[line_off(Mi, I1{}) * LD];
+            });
+            const int cso = c * VSP * sizeof(T);
+            if constexpr (VF) {
+                Q::forward_v(L, xr[c], xi[c], xa[c], xb[c], xm[c]);       // xa/xb: Re/Im V_k
+                static_for<0, P>([&](auto Ki) {
+                    constexpr int k1 = Ki;
+                    const T A = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
+                    const T B = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + VPL * sizeof(T));
+                    const T C = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + 2 * VPL * sizeof(T));
+                    const T re = xa[c][k1], im = xb[c][k1];
+                    xa[c][k1] = A * re + C * im;
+                    xb[c][k1] = B * im + C * re;
+                });
+                xm[c] *= buf_load<T>(tb, tmo, cso);
+                Q::inverse_v(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
+            } else {
+                Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
+                static_for<0, P>([&](auto Ki) {
+                    constexpr int k1 = Ki;
+                    xa[c][k1] *= buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
+                    if constexpr (k1 == 0) xb[c][0] *= buf_load<T>(tb, kb == 0 ? tmo : tno + (P - 1) * N * sizeof(T), cso);
+                    else xb[c][k1] *= buf_load<T>(tb, tno + (P - 1 - k1) * N * sizeof(T), cso);
+                });
+                xm[c] *= buf_load<T>(tb, tmo, cso);
+                Q::inverse_regs(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
+            }
+            static_for<0, P>([&](auto Mi) {
+                constexpr int m1 = Mi;
+                T *cc = (m1 < P / 2 ? cb0 : cb1) + c * SP;
+                cc[line_off(Mi, I0{}) * LD] = xr[c][m1];
+                cc[line_off(Mi, I1{}) * LD] = xi[c][m1];
+            });
+        }
+        __syncthreads();
+        // row g inverse: u^(step+1)
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+            static_for<0, P>([&](auto Ki) {
+                constexpr int k1 = Ki;
+                xa[c][k1] = rk[c * SP + k1];
+                if constexpr (k1 == 0) xb[c][0] = (kb == 0) ? T(0) : rn[c * SP + (P - 1)];
+                else xb[c][k1] = rn[c * SP + (P - 1 - k1)];
+            });
+            xm[c] = rm[c * SP];
+            Q::inverse_regs(L, xa[c], xb[c], xm[c], ur[c], ui[c]);
+        }
+        step = next;
+    }
+    static_for<0, P>([&](auto Mi) {
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+            hbm_st(ur[c][Mi], Mi, I0{}, c);
+            hbm_st(ui[c][Mi], Mi, I1{}, c);
+        }
+    });
+    if (tid == 0) pa.steps[b] = step;
+}
+
+// Quad variant: every line is transformed by a quad of lanes (dct_quad.hpp);
+// each workgroup runs one solve.  Between steps the state is kept in LDS as
+// the row-spectral field (after the column inverse).  One step is two passes,
+// each ending with the workgroup barrier:
+//   row pass     row inverse (u^s in registers), stop rule and snapshot at
+//                evaluation steps, explicit reaction (both species of a point
+//                in one lane, or in lanes t and t ^ 7), row forward -> LDS;
+//   column pass  column forward, spectral divide, column inverse, all in
+//                registers (the split-step partners come by DPP) -> LDS.
+// The first row pass loads u from HBM instead; the last stores it there.
+// The model is dispatched once, outside the step loop.  WPE is the occupancy
+// the register allocation aims at (waves per SIMD).
+template <typename T, int N, int SPL, int WPE, bool VF>
+__global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(WPE))) void k_fused_q(
+    const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt, PersistArgs pa)
+{
+    constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64;
+    __shared__ T sm[2 * SP];
+    __shared__ double red[2 * WAVES];
+    __shared__ int sbad[WAVES];
+    const int b = list[blockIdx.x];
+    const DevSolve s = S[b];
+    dispatch_model(model, [&](auto MD) {
+        fused_q_solve<T, N, SPL, VF, decltype(MD)>(sm, red, sbad, s, b, state, tables, dt, pa);
+    });
+}
+
+template <typename T, int N, int SPL, int WPE, bool VF>
+void launch_q1(int nl, const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt,
+               const PersistArgs &pa, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_fused_q<T, N, SPL, WPE, VF>), dim3(nl), dim3((8 / SPL) * N), 0, st, S, list, state, tables,
+                       model, dt, pa);
+}
+
+template <typename T, int N>
+void launch_q(int shape, int nl, const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt,
+              const PersistArgs &pa, hipStream_t st)
+{
+    switch (shape) {
+    case 0: launch_q1<T, N, 2, 2, false>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 1: launch_q1<T, N, 1, 2, false>(nl, S, list, state, tables, model, dt, pa, st); break;
+    case 2: launch_q1<T, N, 2, 2, true>(nl, S, list, state, tables, model, dt, pa, st); break;
+    default: launch_q1<T, N, 1, 2, true>(nl, S, list, state, tables, model, dt, pa, st); break;
+    }
+}
+
+}  // namespace cil

@@ -1,0 +1,15 @@
+// FP64 instances of the quad-lane persistent stepper (n = 32, 64).
+#include "stepper_quad.hpp"
+
+namespace cil {
+
+int launch_quad_f64(int n, int shape, int nl, const DevSolve *S, const int *list, double *state, const double *tables,
+                    int model, double dt, const PersistArgs &pa, hipStream_t st)
+{
+    if (n == 32) launch_q<double, 32>(shape, nl, S, list, state, tables, model, dt, pa, st);
+    else if (n == 64) launch_q<double, 64>(shape, nl, S, list, state, tables, model, dt, pa, st);
+    else return CIL_EUNSUPPORTED;
+    return CIL_OK;
+}
+
+}  // namespace cil
