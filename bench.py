@@ -120,7 +120,7 @@ def main():
         print(stepper_sources_sha256())
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(solves and pair tiles would shard by index with no communication but one all-reduce "
               "of integer counts); run with --gpus 1", file=sys.stderr)
         sys.exit(2)

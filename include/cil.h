@@ -39,7 +39,7 @@ extern "C" {
 enum {
     CIL_OK = 0,
     CIL_EINVAL = -1,        /* bad argument (message in cil_last_error)        */
-    CIL_EUNSUPPORTED = -2,  /* valid but not supported by this build           */
+    CIL_EUNSUPPORTED = -2,  /* valid but not supported by this library         */
     CIL_ENOMEM = -3,        /* device workspace allocation failed              */
     CIL_EDEVICE = -4,       /* HIP runtime error, or no gfx950 device          */
     CIL_ENOTSPD = -5,       /* covariance not positive definite                */

@@ -7,8 +7,8 @@ Cholesky diffusion solve, canonical distances, counts, bootstrap counts) live
 in ``cil_oracle.c``; the small statistics (radii ladder, mean/covariance,
 Cholesky, cost) are written out here with plain loops.
 
-Every function names the passage of the paper it follows.  Readings of the
-paper where it is silent are listed in the design doc of the repository.
+Every function names the passage of the paper it follows; where the paper is
+silent, the docstring states the reading taken.
 """
 from __future__ import annotations
 
