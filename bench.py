@@ -5,7 +5,8 @@ One step = one pass of the whole hot path over one batch of synthetic input:
   initial states (+-1% multiplicative noise) to stationarity (FP64 residual
   < 1e-8), stepped by the persistent fused kernel in FP64, then the CIL
   statistic of the two 250-pattern halves stored as FP32: canonical distance
-  range, 13 power-law radii fitted to it, per-pair radius bins (62 500 pairs,
+  range, 13 power-law radii fitted to it and per-pair radius bins from one
+  fast pass over the pairs (62 500 pairs,
   d = 8192, split-bf16x3 Gram + canonical re-check), 200 bootstrap resamples
   (Alg. 2bst halves), FP64 mean/covariance/Cholesky and the Gaussian
   log-likelihood of the full-halves vector.
@@ -100,6 +101,9 @@ def measured_traffic(kname: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "features4096"],
+                    help="the default is the benchmarked configuration; features4096 times the CIL "
+                         "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -127,6 +131,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.workload == "features4096":
+        features_main(args)
+        return
 
     import cil_synth as cs
     import paper_2203_14742_amd as cil
@@ -172,9 +180,7 @@ def main():
         else:
             pats = state.reshape(B, d)
         A, Bs = pats[:half], pats[half:]
-        lo, hi = cil.cil_distance_range(A, Bs)
-        radii = cil.cil_radii(lo, hi, M)
-        _, counts = cil.cil_pair_bins(A, Bs, radii, bins=bins)
+        lo, hi, radii, _, counts = cil.cil_pair_bins_adaptive(A, Bs, M, bins=bins)
         _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
         y_obs = torch.tensor(counts / float(half * half), dtype=torch.float64, device=dev)
         out = cil.cil_gaussian_loglik(Y, y_obs)
@@ -278,6 +284,89 @@ def main():
         "all_converged": status_ok,
         "roofline": roof, "roofline_gram": gram, "kernels": kernels, "fp32_stepping": fp32_stepping,
         "plain_fp64": plain, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def features_main(args):
+    """CIL statistic alone: 4096 stand-in patterns of dimension 32768 (FP32),
+    cross pairs of the two 2048-pattern halves, canonical range, 32 power-law
+    radii, bins (split-bf16x3 Gram + canonical re-check), 200 bootstrap
+    resamples, likelihood.  `value` is distance pairs/s."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS["features4096"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    count, n, M, n_boot = w["count"], w["n"], w["M"], w["n_boot"]
+    half, d = count // 2, 2 * n * n
+    host = cs.stripe_patterns(count, n, seed=w["seeds"][0]).reshape(count, d)
+    pats = torch.from_numpy(host).to(dev)
+    A, Bs = pats[:half], pats[half:]
+    ia, ib = cs.resample_halves(half, half, half, half, n_boot, seed=w["boot_seed"])
+    idxA = torch.from_numpy(ia).to(dev)
+    idxB = torch.from_numpy(ib).to(dev)
+    bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    pairs = half * half
+
+    def one_step():
+        lo, hi, radii, _, counts = cil.cil_pair_bins_adaptive(A, Bs, M, bins=bins)
+        _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
+        y_obs = torch.tensor(counts / float(pairs), dtype=torch.float64, device=dev)
+        return cil.cil_gaussian_loglik(Y, y_obs), counts
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    cil.cil_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, counts = one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
+    cil.cil_profile(False)
+    stats = cil.cil_last_distance_stats()
+    K = args.steps
+    roof = None
+    if "k_gram_bf16x3" in prof:
+        cnt, tot_ms = prof["k_gram_bf16x3"]
+        executed = 6.0 * d * pairs * cnt        # one Gram per step (range and bins share it)
+        ach = executed / (tot_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_gram_bf16x3", "bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                "launches": cnt, "avg_launch_ms": round(tot_ms / cnt, 4),
+                "flops_per_pair_executed": 6 * d, "algorithmic_flops_per_pair": 2 * d}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
+        k = 256
+        t1 = time.perf_counter()
+        D = oracle.pair_d2(host[:k], host[half:half + k], nthreads=threads)
+        tp = time.perf_counter() - t1
+        cpu = {"value": round(D.size / tp, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": "%d x %d canonical pair distances of the same sets (%.1f s)" % (k, k, tp)}
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(pairs * K / el, 1), "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "features4096", "patterns": count, "dim": d, "pairs_per_step": pairs, "radii": M,
+                   "bootstrap": n_boot, "statistic": "fp32 patterns, split-bf16x3 MFMA Gram + canonical re-check",
+                   "parallelism": "none (1 GPU)"},
+        "rechecked_pairs": stats["rechecked"], "exact_fallbacks": stats["exact_fallbacks"],
+        "counts": [int(c) for c in counts],
+        "loglik_status": int(out[3].cpu()[0]),
+        "roofline": roof,
+        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

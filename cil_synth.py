@@ -127,4 +127,7 @@ WORKLOADS = {
         model=GM_SOURCE, params=(0.5, 1.0), nu=(1.0, 100.0), n=64, L=120.0, dt=0.2,
         max_steps=20000, tol=1e-8, check_every=25, count=500, seeds=(3,),
         ic_law="multiplicative", M=13, n_boot=200),
+    # Features alone: 4096 FP32 stand-in patterns of side 128 (d = 32768),
+    # halves of 2048, 32 power-law radii, 200 bootstrap resamples of the halves.
+    "features4096": dict(count=4096, n=128, M=32, n_boot=200, seeds=(5,), boot_seed=6),
 }

@@ -22,6 +22,9 @@ template <typename T>
 int pair_bins_impl(const T *, long long, const T *, long long, long long, const double *, int, uint8_t *,
                    std::vector<unsigned long long> &, hipStream_t);
 template <typename T>
+int adaptive_bins_impl(const T *, long long, const T *, long long, long long, int, int, double *, double *, double *,
+                       uint8_t *, std::vector<unsigned long long> &, hipStream_t);
+template <typename T>
 int distance_range_impl(const T *, long long, const T *, long long, long long, int, double *, double *,
                         hipStream_t);
 template <typename T>
@@ -220,6 +223,24 @@ int fill_zero(void *p, size_t bytes, hipStream_t st)
     return check_launch("k_fill_zero");
 }
 
+int radii_ladder(double d2min, double d2max, int M, int law, double *radii)
+{
+    if (!radii || M < 1) return set_error(CIL_EINVAL, "bad arguments");
+    const double R0 = std::sqrt(d2max), RM = std::sqrt(d2min);
+    if (!(RM > 0.0) || !(R0 > RM) || !std::isfinite(R0))
+        return set_error(CIL_EINVAL, "degenerate distance range [%g, %g]", d2min, d2max);
+    if (law == 0) {
+        const double b = std::pow(R0 / RM, 1.0 / M);
+        for (int m = 1; m <= M; ++m) radii[m - 1] = R0 * std::pow(b, (double)-m);
+    } else if (law == 1) {
+        const double h = (R0 - RM) / M;
+        for (int m = 1; m <= M; ++m) radii[m - 1] = R0 - m * h;
+    } else {
+        return set_error(CIL_EINVAL, "unknown radius law %d", law);
+    }
+    return CIL_OK;
+}
+
 }  // namespace cil
 
 using namespace cil;
@@ -408,18 +429,34 @@ int cil_approx_d2(const void *setA, int64_t nA, const void *setB, int64_t nB, in
 int cil_radii(double d2min, double d2max, int32_t M, int32_t law, double *radii)
 {
     API_BEGIN();
-    if (!radii || M < 1) return set_error(CIL_EINVAL, "bad arguments");
-    const double R0 = std::sqrt(d2max), RM = std::sqrt(d2min);
-    if (!(RM > 0.0) || !(R0 > RM) || !std::isfinite(R0))
-        return set_error(CIL_EINVAL, "degenerate distance range [%g, %g]", d2min, d2max);
-    if (law == 0) {
-        const double b = std::pow(R0 / RM, 1.0 / M);
-        for (int m = 1; m <= M; ++m) radii[m - 1] = R0 * std::pow(b, (double)-m);
-    } else if (law == 1) {
-        const double h = (R0 - RM) / M;
-        for (int m = 1; m <= M; ++m) radii[m - 1] = R0 - m * h;
-    } else {
-        return set_error(CIL_EINVAL, "unknown radius law %d", law);
+    return cil::radii_ladder(d2min, d2max, M, law, radii);
+}
+
+int cil_pair_bins_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                           cil_precision prec, int32_t M, int32_t law, double *d2min, double *d2max, double *radii,
+                           uint8_t *bins, int64_t *counts, void *hip_stream)
+{
+    API_BEGIN();
+    CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
+    if (!d2min || !d2max || !radii) return set_error(CIL_EINVAL, "null output");
+    if (M < 1 || M > 255) return set_error(CIL_EINVAL, "M must be in [1, 255]");
+    if (law != 0 && law != 1) return set_error(CIL_EINVAL, "unknown radius law %d", law);
+    if (nA * nB <= 0) return set_error(CIL_EINVAL, "no pairs");
+    CIL_TRY(check_device());
+    std::vector<unsigned long long> hist;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == CIL_FP64)
+        CIL_TRY(adaptive_bins_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim, M, law, d2min,
+                                           d2max, radii, bins, hist, st));
+    else
+        CIL_TRY(adaptive_bins_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, M, law, d2min, d2max,
+                                          radii, bins, hist, st));
+    if (counts) {
+        unsigned long long run = 0;
+        for (int m = M; m >= 1; --m) {
+            run += hist[m];
+            counts[m - 1] = (int64_t)run;
+        }
     }
     return CIL_OK;
 }

@@ -111,6 +111,10 @@ constexpr double ce_cospi(long p, long q)
 
 constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
 
+// Radii ladder from a squared-distance range (host; shared by cil_radii and the
+// adaptive counting call so both give the same doubles).
+int radii_ladder(double d2min, double d2max, int M, int law, double *radii);
+
 // ------------------------------------------------------- buffer accesses
 // Raw buffer loads/stores: the base lives in a uniform resource (SGPRs), so a
 // lane address is one 32-bit byte offset plus compile-time offsets, instead

@@ -508,20 +508,20 @@ int last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact)
 }
 
 // Bins / counts for all pairs.  hist_host[M+1] gets the per-bin pair counts.
+namespace {
+
+// Bins of every pair from a computed fast pass: classify against the squared
+// radii, re-check the listed pairs canonically.  hist_host[m] = #{bin == m}.
 template <typename T>
-int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim, const double *radii, int M,
-                   uint8_t *bins, std::vector<unsigned long long> &hist_host, hipStream_t st)
+int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long long dim, Approx &ap, DistScratch &s,
+                     const double *radii, int M, uint8_t *bins, std::vector<unsigned long long> &hist_host,
+                     hipStream_t st)
 {
-    const long long npairs = nA * nB;
-    DistScratch s;
-    CIL_TRY(scratch(npairs, &s));
     std::vector<double> thr(M);
     for (int m = 0; m < M; ++m) thr[m] = radii[m] * radii[m];
     CIL_HIP(hipMemcpyAsync(s.thr, thr.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
     CIL_TRY(fill_zero(s.hist, sizeof(unsigned long long) * (M + 1), st));
     CIL_TRY(fill_zero(s.nlist, sizeof(unsigned long long) * 2, st));
-    Approx ap;
-    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
     ClassifyArgs &c = ap.c;
     c.mode = MODE_BINS;
     c.thr = s.thr;
@@ -553,31 +553,22 @@ int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long
     CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipMemcpyAsync(&nex, s.nexact, sizeof(nex), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
-    t_pairs = npairs;
+    t_pairs = nA * nB;
     t_rechecked = (long long)nre;
     t_exact = (long long)nex;
     return CIL_OK;
 }
 
-template int pair_bins_impl<double>(const double *, long long, const double *, long long, long long, const double *,
-                                    int, uint8_t *, std::vector<unsigned long long> &, hipStream_t);
-template int pair_bins_impl<float>(const float *, long long, const float *, long long, long long, const double *, int,
-                                   uint8_t *, std::vector<unsigned long long> &, hipStream_t);
-
-// Canonical extremes: pass 1 bounds them by min(D~ + eps) and max(D~ - eps);
-// pass 2 lists every pair whose interval reaches those bounds; the listed
-// pairs are recomputed canonically and the extremes taken over them.
+// Canonical extremes from a computed fast pass: pass 1 bounds them by
+// min(D~ + eps) and max(D~ - eps); pass 2 lists every pair whose interval
+// reaches those bounds; the listed pairs are recomputed canonically and the
+// extremes taken over them.
 template <typename T>
-int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int excl, double *dmin,
-                        double *dmax, hipStream_t st)
+int range_from_approx(const T *A, long long nA, const T *B, long long nB, long long dim, Approx &ap, DistScratch &s,
+                      int excl, double *dmin, double *dmax, hipStream_t st)
 {
-    const long long npairs = nA * nB;
-    DistScratch s;
-    CIL_TRY(scratch(npairs, &s));
     unsigned long long init[4] = {0ull, 0ull, (unsigned long long)0x7ff0000000000000ull, 0ull};  // nlist, nexact, +inf, 0
     CIL_HIP(hipMemcpyAsync(s.nlist, init, sizeof(init), hipMemcpyHostToDevice, st));
-    Approx ap;
-    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
     ClassifyArgs &c = ap.c;
     c.exclude_diag = excl;
     c.minmax = s.minmax;
@@ -618,10 +609,66 @@ int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long
     }
     *dmin = lo;
     *dmax = hi;
-    t_pairs = npairs;
+    t_pairs = nA * nB;
     t_rechecked = (long long)nc;
     t_exact = (long long)nex;
     return CIL_OK;
+}
+
+}  // namespace
+
+template <typename T>
+int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim, const double *radii, int M,
+                   uint8_t *bins, std::vector<unsigned long long> &hist_host, hipStream_t st)
+{
+    DistScratch s;
+    CIL_TRY(scratch(nA * nB, &s));
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    return bins_from_approx(A, nA, B, nB, dim, ap, s, radii, M, bins, hist_host, st);
+}
+
+// Range, radii and bins from one fast pass (the partials stay in their
+// workspace between the two classifications).
+template <typename T>
+int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int M, int law,
+                       double *dmin, double *dmax, double *radii, uint8_t *bins,
+                       std::vector<unsigned long long> &hist_host, hipStream_t st)
+{
+    DistScratch s;
+    CIL_TRY(scratch(nA * nB, &s));
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    CIL_TRY(range_from_approx(A, nA, B, nB, dim, ap, s, 0, dmin, dmax, st));
+    const long long nrange = t_rechecked, nrange_exact = t_exact;
+    CIL_TRY(radii_ladder(*dmin, *dmax, M, law, radii));
+    CIL_TRY(bins_from_approx(A, nA, B, nB, dim, ap, s, radii, M, bins, hist_host, st));
+    t_rechecked += nrange;
+    t_exact += nrange_exact;
+    return CIL_OK;
+}
+
+template int adaptive_bins_impl<double>(const double *, long long, const double *, long long, long long, int, int,
+                                        double *, double *, double *, uint8_t *, std::vector<unsigned long long> &,
+                                        hipStream_t);
+template int adaptive_bins_impl<float>(const float *, long long, const float *, long long, long long, int, int,
+                                       double *, double *, double *, uint8_t *, std::vector<unsigned long long> &,
+                                       hipStream_t);
+
+template int pair_bins_impl<double>(const double *, long long, const double *, long long, long long, const double *,
+                                    int, uint8_t *, std::vector<unsigned long long> &, hipStream_t);
+template int pair_bins_impl<float>(const float *, long long, const float *, long long, long long, const double *, int,
+                                   uint8_t *, std::vector<unsigned long long> &, hipStream_t);
+
+template <typename T>
+int distance_range_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int excl, double *dmin,
+                        double *dmax, hipStream_t st)
+{
+    DistScratch s;
+    CIL_TRY(scratch(nA * nB, &s));
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    return range_from_approx(A, nA, B, nB, dim, ap, s, excl, dmin, dmax, st);
 }
 
 template int distance_range_impl<double>(const double *, long long, const double *, long long, long long, int,

@@ -181,6 +181,29 @@ def test_distance_range_bit_exact(cil, oracle_mod, dtype, excl):
     assert got == want
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("law", ["power", "linear"])
+def test_adaptive_bins_bit_exact(cil, oracle_mod, dtype, law):
+    """Range, radii and bins from one fast pass equal the oracle's canonical
+    range, its radii ladder and its bins (both radius laws of Sec. 2.1)."""
+    A, B = sets(70, 90, 515, seed=8, dtype=dtype)
+    M = 16
+    lo, hi, radii, bins, counts = cil.cil_pair_bins_adaptive(dev(A), dev(B), M, law=0 if law == "power" else 1)
+    D = oracle_mod.pair_d2(A, B)
+    assert (lo, hi) == (D.min(), D.max())
+    want_r = oracle_mod.radii_ladder(D.min(), D.max(), M, law=law)
+    assert np.array_equal(radii, want_r)
+    assert np.array_equal(bins.cpu().numpy(), oracle_mod.bins_from_d2(D, want_r))
+    assert np.array_equal(counts, oracle_mod.counts_from_d2(D, want_r))
+
+
+def test_adaptive_bins_rejects_a_degenerate_range(cil):
+    A = np.ones((3, 8), dtype=np.float64)
+    with pytest.raises(cil.CilError) as e:
+        cil.cil_pair_bins_adaptive(dev(A), dev(A), 4)
+    assert e.value.code == cil.CIL_EINVAL
+
+
 @pytest.mark.parametrize("M", [13, 32, 70])
 def test_bootstrap_counts_bit_exact(cil, oracle_mod, M):
     A, B = sets(90, 75, 64, seed=M, dtype=np.float64)

@@ -61,13 +61,14 @@ def test_full_workload_statistic(cil, oracle_mod, stepped):
     A, Bs = P[:half], P[half:]
     An, Bn = A.cpu().numpy(), Bs.cpu().numpy()
     D = oracle_mod.pair_d2(An, Bn, nthreads=8)
-    lo, hi = cil.cil_distance_range(A, Bs)
+    lo, hi, radii, bins, counts = cil.cil_pair_bins_adaptive(A, Bs, M)     # as the benchmark runs it
     assert (lo, hi) == (D.min(), D.max())
-    radii = cil.cil_radii(lo, hi, M)
     assert np.array_equal(radii, oracle_mod.radii_ladder(D.min(), D.max(), M))
-    bins, counts = cil.cil_pair_bins(A, Bs, radii)
     assert np.array_equal(bins.cpu().numpy(), oracle_mod.bins_from_d2(D, radii))
     assert np.array_equal(counts, oracle_mod.counts_from_d2(D, radii))
+    assert cil.cil_distance_range(A, Bs) == (lo, hi)
+    bins2, counts2 = cil.cil_pair_bins(A, Bs, cil.cil_radii(lo, hi, M))
+    assert torch.equal(bins2, bins) and np.array_equal(counts2, counts)
     ia, ib = cs.resample_halves(half, half, half, half, w["n_boot"], seed=6)
     Yc, Y = cil.cil_bootstrap_features(bins, torch.from_numpy(ia), torch.from_numpy(ib), M)
     want_c, want_y = oracle_mod.bootstrap_vectors(D, ia, ib, radii, nthreads=8)
