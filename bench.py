@@ -101,7 +101,7 @@ def measured_traffic(kname: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "features4096"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "features4096", "bz_uneven2048"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -134,6 +134,9 @@ def main():
 
     if args.workload == "features4096":
         features_main(args)
+        return
+    if args.workload == "bz_uneven2048":
+        uneven_main(args)
         return
 
     import cil_synth as cs
@@ -367,6 +370,72 @@ def features_main(args):
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def uneven_main(args):
+    """Uneven batch alone: 2048 Brusselator solves of sides 32, 64, 128 with
+    per-solve parameters around a Turing point, 2000 FP32 steps (T = 100), one
+    simulate call (the three sides' persistent kernels run side by side).
+    `value` is stationary patterns/s."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS["bz_uneven2048"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ns, ps, nus = cs.brusselator_uneven(w["count"], w["seed"], sides=w["sides"], rel=w["rel"])
+    bases = [cil.cil_homogeneous_state(w["model"], p) for p in ps]
+    flat = cs.uneven_initial_states(bases, ns, seed=w["ic_seed"])
+    probs = cil.make_problems(ns, w["L"], nus, ps)
+    ics = torch.tensor(flat, dtype=torch.float32, device=dev)
+    st = torch.empty_like(ics)
+
+    def one_step():
+        st.copy_(ics)
+        return cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"],
+                                         check_every=w["check_every"])
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    cil.cil_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep = one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
+    cil.cil_profile(False)
+    K, B = args.steps, len(ns)
+    kname = max(prof, key=lambda k: prof[k][1])
+    cnt, tot_ms = prof[kname]
+    side = int(kname.rsplit("_n", 1)[1])
+    solves_side = sum(1 for n in ns if n == side)
+    flops = solves_side * w["max_steps"] * fused_step_flops(side, REACTION_FLOPS[w["model"]]) * cnt
+    ach = flops / (tot_ms * 1e-3) / 1e12
+    total_flops = sum(w["max_steps"] * fused_step_flops(n, REACTION_FLOPS[w["model"]]) for n in ns) * K
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": VALU_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None, "launches": cnt,
+            "avg_launch_ms": round(tot_ms / cnt, 3),
+            "flops_per_solve_step": fused_step_flops(side, REACTION_FLOPS[w["model"]]),
+            "whole_batch_tflops": round(total_flops / el / 1e12, 3)}
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(B * K / el, 2), "unit": "patterns/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bz_uneven2048", "solves": B, "sides": list(w["sides"]), "dt": w["dt"],
+                   "steps_per_solve": w["max_steps"], "stepping": "fp32 fused persistent, one kernel per side on "
+                   "forked streams", "parallelism": "none (1 GPU)"},
+        "all_ok": bool(np.all(rep["status"] == 0)),
+        "roofline": roof,
+        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -111,6 +111,53 @@ def stripe_patterns(count: int, n: int, seed: int, ring: float = 8.0, modes: int
     return np.ascontiguousarray(out, dtype=dtype)
 
 
+def turing_unstable_bz(A: float, B: float, Du: float, Dv: float, n: int, L: float = 1.0) -> bool:
+    """Input-recipe filter for Brusselator parameter draws: the homogeneous
+    state (A, B/A) is stable without diffusion (trace < 0, det > 0 of the
+    kinetic Jacobian [[B - 1, A^2], [-B, -A^2]]) and some mode of the grid's
+    five-point Laplacian (eigenvalue Lam = lam_k + lam_l, lam_k = 4 sin^2(pi k
+    / 2n) / h^2, h = L/(n-1)) grows: det(J - Lam diag(Du, Dv)) < 0."""
+    tr, det = B - 1.0 - A * A, A * A
+    if not (tr < 0.0 and det > 0.0):
+        return False
+    h = L / (n - 1)
+    lam = 4.0 * np.sin(np.pi * np.arange(n) / (2.0 * n)) ** 2 / (h * h)
+    Lam = (lam[:, None] + lam[None, :]).ravel()
+    dets = (B - 1.0 - Lam * Du) * (-A * A - Lam * Dv) + A * A * B
+    return bool(np.any(dets < 0.0))
+
+
+def brusselator_uneven(count: int, seed: int, sides=(32, 64, 128), L: float = 1.0, rel: float = 0.05,
+                       theta0=(4.5, 6.96, 0.0016, 0.0132)):
+    """Per-solve Brusselator problems around a Turing point: solve b has grid
+    side sides[b mod len(sides)] and (A, B, Du, Dv) = theta0 (1 + U(-rel, rel))
+    drawn until the draw is Turing-unstable on that grid.  Returns the lists
+    (sides, params [(A, B)], nus [(Du, Dv)])."""
+    g = rng(seed)
+    t0 = np.asarray(theta0, dtype=np.float64)
+    ns, ps, nus = [], [], []
+    while len(ns) < count:
+        n = sides[len(ns) % len(sides)]
+        A, B, Du, Dv = t0 * (1.0 + g.uniform(-rel, rel, 4))
+        if turing_unstable_bz(A, B, Du, Dv, n, L):
+            ns.append(n)
+            ps.append((A, B))
+            nus.append((Du, Dv))
+    return ns, ps, nus
+
+
+def uneven_initial_states(bases, ns, seed: int, delta: float = 1e-2) -> np.ndarray:
+    """Concatenated [species][n][n] states of solves of different sides: the
+    solve's homogeneous state + U(0, delta) per point (draw order: solve,
+    species, row-major), FP64."""
+    g = rng(seed)
+    out = []
+    for base, n in zip(bases, ns):
+        noise = g.uniform(0.0, delta, size=(2, n, n))
+        out.append((np.asarray(base, dtype=np.float64)[:, None, None] + noise).reshape(-1))
+    return np.concatenate(out) if out else np.zeros(0)
+
+
 # --------------------------------------------------------------------------
 # Workload configurations.  Parameter values from Table exp1 where the paper
 # gives them; the source form of Gierer-Meinhardt and its Turing parameters are
@@ -130,4 +177,8 @@ WORKLOADS = {
     # Features alone: 4096 FP32 stand-in patterns of side 128 (d = 32768),
     # halves of 2048, 32 power-law radii, 200 bootstrap resamples of the halves.
     "features4096": dict(count=4096, n=128, M=32, n_boot=200, seeds=(5,), boot_seed=6),
+    # Uneven batch: 2048 Brusselator solves, sides 32/64/128 in turn, each with
+    # its own (A, B, Du, Dv) around Table exp1's point, FP32, T = 100 at dt = 0.05.
+    "bz_uneven2048": dict(model=BRUSSELATOR, count=2048, sides=(32, 64, 128), L=1.0, dt=0.05, max_steps=2000,
+                          check_every=2000, seed=4, ic_seed=4, rel=0.05),
 }

@@ -20,8 +20,11 @@
  *     stream-ordered on it.  A call that returns results in host memory
  *     synchronises that stream before it returns; a call whose outputs are
  *     all device memory returns without synchronising.
- *   - The library keeps internal device workspaces, DCT tables and tuning
- *     state per device; cil_shutdown() frees them.
+ *   - The library keeps internal device workspaces, DCT tables, auxiliary
+ *     streams and tuning state per device; cil_shutdown() frees them.  A
+ *     simulate call with several grid sides runs each side's persistent
+ *     kernel on an auxiliary stream forked from, and joined back into, the
+ *     caller's stream.
  *   - Pattern layout (Sec. 2.1 "patterns s in R^d", App. B.1.1 grid values):
  *     one pattern is [species v: n x n row-major][species w: n x n row-major],
  *     d = 2 n^2; a pattern set is nA rows of d contiguous elements.
@@ -262,7 +265,9 @@ int cil_profile(int32_t enable);
 int cil_profile_read(const char *name, int64_t *count, double *total_ms);
 int cil_profile_names(char *buf, int64_t len);
 
-/* Free every internal workspace, table and cached state on all devices. */
+/* Free every internal workspace, table, auxiliary stream and cached state on
+ * all devices (waits for the device to be idle first).  The library stays
+ * usable: later calls allocate again. */
 int cil_shutdown(void);
 
 #ifdef __cplusplus

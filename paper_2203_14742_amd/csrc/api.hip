@@ -39,6 +39,7 @@ int loglik_impl(const double *, int, int, int, const double *, double *, double 
 int last_distance_stats(int64_t *, int64_t *, int64_t *);
 void set_force_exact(int);
 int set_quad_shape(int64_t);
+int stepper_release();
 
 // ------------------------------------------------------------------ errors
 namespace {
@@ -542,6 +543,8 @@ int cil_shutdown(void)
 {
     API_BEGIN();
     prof_flush();
+    (void)hipDeviceSynchronize();
+    CIL_TRY(stepper_release());
     return release_all();
 }
 

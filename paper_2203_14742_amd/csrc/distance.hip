@@ -189,13 +189,29 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
         for (int m = tid; m <= c.M; m += 256)
             if (hist[m]) atomicAdd(&c.hist[m], (unsigned long long)hist[m]);
     } else if (c.mode == MODE_RANGE1) {
+        // bounds over the wavefront first, then one atomic per wavefront (the
+        // bit patterns of non-negative doubles order as the values)
+        unsigned long long lo = ~0ull, hi = 0ull;
+        int bad = 0;
         if (!skip) {
             if (!finite) {
-                atomicOr(c.nlist, 1ull << 63);   // flag: non-finite distance
+                bad = 1;
             } else {
-                atomicMin(&c.minmax[0], (unsigned long long)__double_as_longlong(D + eps));
-                atomicMax(&c.minmax[1], (unsigned long long)__double_as_longlong(fmax(D - eps, 0.0)));
+                lo = (unsigned long long)__double_as_longlong(D + eps);
+                hi = (unsigned long long)__double_as_longlong(fmax(D - eps, 0.0));
             }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
+            lo = l2 < lo ? l2 : lo;
+            hi = h2 > hi ? h2 : hi;
+            bad |= __shfl_xor(bad, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            if (bad) atomicOr(c.nlist, 1ull << 63);   // flag: non-finite distance
+            if (lo != ~0ull) atomicMin(&c.minmax[0], lo);
+            if (hi != 0ull) atomicMax(&c.minmax[1], hi);
         }
     } else if (c.mode == MODE_RANGE2) {
         if (!skip) {

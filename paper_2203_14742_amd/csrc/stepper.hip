@@ -430,6 +430,33 @@ int plain_tables(int n, PlainTables *out)
     return CIL_OK;
 }
 
+// Auxiliary streams (default priority) for running the persistent kernels of
+// different grid sides side by side, and fork/join events; per device.
+struct AuxStreams {
+    std::vector<hipStream_t> st;
+    std::vector<hipEvent_t> ev;     // ev[0] fork, ev[1 + g] join of stream g
+};
+std::map<int, AuxStreams> g_aux;
+
+int aux_streams(int count, AuxStreams **out)
+{
+    int dev;
+    CIL_TRY(current_device(&dev));
+    AuxStreams &a = g_aux[dev];
+    while ((int)a.st.size() < count) {
+        hipStream_t s;
+        CIL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        a.st.push_back(s);
+    }
+    while ((int)a.ev.size() < count + 1) {
+        hipEvent_t e;
+        CIL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        a.ev.push_back(e);
+    }
+    *out = &a;
+    return CIL_OK;
+}
+
 int fused_supported(int n, bool f32)
 {
     return f32 ? (n == 32 || n == 64 || n == 128) : (n == 32 || n == 64);
@@ -447,6 +474,30 @@ int quad_shape(bool f32, int n)
 }
 
 }  // namespace
+
+// Library-owned stepper resources (cached DCT matrices of the plain path,
+// auxiliary streams and events), freed by cil_shutdown.
+int stepper_release()
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_plain_tables) {
+        (void)hipSetDevice(std::get<0>(kv.first));
+        (void)hipFree(kv.second.C);
+        (void)hipFree(kv.second.Ct);
+        (void)hipFree(kv.second.Cw);
+        (void)hipFree(kv.second.lam);
+    }
+    g_plain_tables.clear();
+    for (auto &kv : g_aux) {
+        (void)hipSetDevice(kv.first);
+        for (hipStream_t st : kv.second.st) (void)hipStreamDestroy(st);
+        for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+    }
+    g_aux.clear();
+    (void)hipSetDevice(cur);
+    return CIL_OK;
+}
 
 int set_quad_shape(int64_t v)
 {
@@ -611,14 +662,48 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
     std::vector<long long> hsteps(c.steps.begin(), c.steps.end());
     CIL_HIP(hipMemcpyAsync(dsteps, hsteps.data(), sizeof(long long) * B, hipMemcpyHostToDevice, c.st));
     PersistArgs pa{(long long)c.max_steps, c.tol, c.check, floor_coef, dsteps, dres, dstat};
-    size_t gi = 0;
+    // Several grid sides: each side's persistent kernel on its own stream, the
+    // most expensive (n^2 log n x solves) launched first, joined back into the
+    // caller's stream, so the call stays ordered on it.
+    std::vector<std::pair<double, int>> order;
+    {
+        int gi = 0;
+        for (auto &kv : byn) {
+            const double n = kv.first;
+            order.push_back({-n * n * std::log2(n) * (double)kv.second.size(), gi++});
+        }
+        std::sort(order.begin(), order.end());
+    }
+    std::vector<int *> dls;
     for (auto &kv : byn) {
         int *dl;
         CIL_TRY(c.cb->alloc((void **)&dl, sizeof(int) * kv.second.size()));
         CIL_HIP(hipMemcpyAsync(dl, kv.second.data(), sizeof(int) * kv.second.size(), hipMemcpyHostToDevice, c.st));
+        dls.push_back(dl);
+    }
+    AuxStreams *aux = nullptr;
+    const int ng = (int)byn.size();
+    if (ng > 1) {
+        CIL_TRY(aux_streams(ng, &aux));
+        CIL_HIP(hipEventRecord(aux->ev[0], c.st));
+    }
+    std::vector<const std::pair<const int, std::vector<int>> *> groups;
+    for (auto &kv : byn) groups.push_back(&kv);
+    for (auto &o : order) {
+        const int gi = o.second;
+        const auto &kv = *groups[gi];
+        hipStream_t gst = c.st;
+        if (aux) {
+            gst = aux->st[gi];
+            CIL_HIP(hipStreamWaitEvent(gst, aux->ev[0], 0));
+        }
         const int shape = quad_shape(std::is_same<T, float>::value, kv.first);
-        CIL_TRY(launch_persistent<T>(kv.first, quad, shape, (int)kv.second.size(), dS, dl, state, (const T *)tabs[gi++],
-                                     c.model, c.dt, pa, c.st));
+        CIL_TRY(launch_persistent<T>(kv.first, quad, shape, (int)kv.second.size(), dS, dls[gi], state,
+                                     (const T *)tabs[gi], c.model, c.dt, pa, gst));
+        if (aux) {
+            CIL_HIP(hipEventRecord(aux->ev[1 + gi], gst));
+            CIL_HIP(hipStreamWaitEvent(c.st, aux->ev[1 + gi], 0));
+        }
     }
     std::vector<double> hres(B);
     std::vector<int> hstat(B);
