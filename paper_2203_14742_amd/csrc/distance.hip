@@ -155,21 +155,25 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
 {
     __shared__ unsigned int hist[MAX_M + 1];
     __shared__ double sthr[MAX_M];
+    __shared__ unsigned long long rlo[4], rhi[4];
+    __shared__ int rbad[4];
     const int tid = threadIdx.x;
     if (c.mode == MODE_BINS) {
         for (int m = tid; m <= c.M; m += 256) hist[m] = 0;
         for (int m = tid; m < c.M; m += 256) sthr[m] = c.thr[m];
         __syncthreads();
     }
-    const long long e = (long long)blockIdx.x * 256 + tid;
-    const bool live = e < nA * nB;
-    const long long i = live ? e / nB : 0, j = live ? e % nB : 0;
-    const bool skip = !live || (c.exclude_diag && i == j);
-    double D = 0.0, eps = 0.0;
-    if (!skip) approx_pair(c, i, j, nA, nB, D, eps);
-    const bool finite = isfinite(D) && isfinite(eps);
-    if (c.mode == MODE_BINS) {
-        if (!skip) {
+    const long long n = nA * nB;
+    unsigned long long lo = ~0ull, hi = 0ull;     // RANGE1: bounds over this thread's pairs
+    int bad = 0;
+    // grid-stride over the pairs (the grid is capped, so per-block reductions stay few)
+    for (long long e = (long long)blockIdx.x * 256 + tid; e < n; e += (long long)gridDim.x * 256) {
+        const long long i = e / nB, j = e % nB;
+        if (c.exclude_diag && i == j) continue;
+        double D, eps;
+        approx_pair(c, i, j, nA, nB, D, eps);
+        const bool finite = isfinite(D) && isfinite(eps);
+        if (c.mode == MODE_BINS) {
             int bin = 0;
             bool amb = !finite;
             for (int m = 0; m < c.M; ++m) {
@@ -184,23 +188,34 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
                 atomicAdd(&hist[bin], 1u);
                 if (c.bins) c.bins[i * nB + j] = (uint8_t)bin;
             }
+        } else if (c.mode == MODE_RANGE1) {
+            // the bit patterns of non-negative doubles order as the values
+            if (!finite) {
+                bad = 1;
+            } else {
+                const unsigned long long l = (unsigned long long)__double_as_longlong(D + eps);
+                const unsigned long long h = (unsigned long long)__double_as_longlong(fmax(D - eps, 0.0));
+                lo = l < lo ? l : lo;
+                hi = h > hi ? h : hi;
+            }
+        } else if (c.mode == MODE_RANGE2) {
+            const double mnub = __longlong_as_double((long long)c.minmax[0]);
+            const double mxlb = __longlong_as_double((long long)c.minmax[1]);
+            if (D - eps <= mnub || D + eps >= mxlb) {
+                const unsigned long long slot = atomicAdd(c.nlist, 1ull);
+                if ((long long)slot < c.cap) c.list[slot] = make_int2((int)i, (int)j);
+            }
+        } else {
+            c.dump_d[e] = D;
+            c.dump_eps[e] = eps;
         }
+    }
+    if (c.mode == MODE_BINS) {
         __syncthreads();
         for (int m = tid; m <= c.M; m += 256)
             if (hist[m]) atomicAdd(&c.hist[m], (unsigned long long)hist[m]);
     } else if (c.mode == MODE_RANGE1) {
-        // bounds over the wavefront first, then one atomic per wavefront (the
-        // bit patterns of non-negative doubles order as the values)
-        unsigned long long lo = ~0ull, hi = 0ull;
-        int bad = 0;
-        if (!skip) {
-            if (!finite) {
-                bad = 1;
-            } else {
-                lo = (unsigned long long)__double_as_longlong(D + eps);
-                hi = (unsigned long long)__double_as_longlong(fmax(D - eps, 0.0));
-            }
-        }
+        // wavefront, then workgroup, then one atomic per workgroup
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const unsigned long long l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
@@ -209,28 +224,27 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
             bad |= __shfl_xor(bad, o, 64);
         }
         if ((tid & 63) == 0) {
+            rlo[tid >> 6] = lo;
+            rhi[tid >> 6] = hi;
+            rbad[tid >> 6] = bad;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < 4; ++w) {
+                lo = rlo[w] < lo ? rlo[w] : lo;
+                hi = rhi[w] > hi ? rhi[w] : hi;
+                bad |= rbad[w];
+            }
             if (bad) atomicOr(c.nlist, 1ull << 63);   // flag: non-finite distance
             if (lo != ~0ull) atomicMin(&c.minmax[0], lo);
             if (hi != 0ull) atomicMax(&c.minmax[1], hi);
         }
-    } else if (c.mode == MODE_RANGE2) {
-        if (!skip) {
-            const double mnub = __longlong_as_double((long long)c.minmax[0]);
-            const double mxlb = __longlong_as_double((long long)c.minmax[1]);
-            if (D - eps <= mnub || D + eps >= mxlb) {
-                const unsigned long long slot = atomicAdd(c.nlist, 1ull);
-                if ((long long)slot < c.cap) c.list[slot] = make_int2((int)i, (int)j);
-            }
-        }
-    } else if (live) {
-        c.dump_d[e] = D;
-        c.dump_eps[e] = eps;
     }
 }
 
 // ---------------------------------------------------------------- canonical
-// Double-double accumulation of the exact squares, one wavefront per pair,
-// then a certified rounding.  The accumulation records whether any of its
+// Double-double accumulation of the exact squares, one wavefront per pair (or
+// sixteen, when few pairs are re-checked), then a certified rounding.  The accumulation records whether any of its
 // roundings lost bits: if none did, hi + lo is the exact sum and the
 // hardware's RN(hi + lo) is the correctly rounded value, ties included (the
 // common case for FP32 sets, whose squares are exact).  Otherwise, with the
@@ -344,11 +358,17 @@ struct CanonOut {
     int force_exact;
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_canonical(const T *A, const T *B, long long dim, CanonOut o)
+// WPP wavefronts per pair: 1 (four pairs per 256-thread block; many pairs, the
+// pass is bandwidth-bound) or 16 (one pair per 1024-thread block; few pairs,
+// latency-bound).  The certified rounding makes the result independent of
+// the summation order, so both give the same doubles.
+template <typename T, int WPP>
+__global__ __launch_bounds__(WPP == 1 ? 256 : 64 * WPP) void k_canonical(const T *A, const T *B, long long dim,
+                                                                         CanonOut o)
 {
     const int lane = threadIdx.x & 63;
-    const long long w = (long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int sub = WPP == 1 ? 0 : threadIdx.x / 64;
+    const long long w = WPP == 1 ? (long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64 : (long long)blockIdx.x;
     const long long np = o.pairs ? (long long)min((unsigned long long)o.cap, *o.npairs_dev) : o.npairs;
     if (w >= np) return;
     long long i, j;
@@ -370,7 +390,7 @@ __global__ __launch_bounds__(256) void k_canonical(const T *A, const T *B, long 
     const T *b = B + j * dim;
     double hi = 0.0, lo = 0.0;
     int inexact = 0;
-    for (long long k = lane; k < dim; k += 64) {
+    for (long long k = lane + 64LL * sub; k < dim; k += 64LL * WPP) {
         const double d = ld(a + k) - ld(b + k);
         const double p = d * d;
         dd_add_t(hi, lo, p, fma(d, d, -p), inexact);
@@ -381,9 +401,24 @@ __global__ __launch_bounds__(256) void k_canonical(const T *A, const T *B, long 
         dd_add_t(hi, lo, oh, ol, inexact);
         inexact |= __shfl_xor(inexact, off, 64);
     }
+    if constexpr (WPP > 1) {      // combine the pair's wavefronts; wavefront 0 finishes
+        __shared__ double phi[WPP], plo[WPP];
+        __shared__ int pin[WPP];
+        if (lane == 0) {
+            phi[sub] = hi;
+            plo[sub] = lo;
+            pin[sub] = inexact;
+        }
+        __syncthreads();
+        if (sub != 0) return;
+        for (int v = 1; v < WPP; ++v) {
+            dd_add_t(hi, lo, phi[v], plo[v], inexact);
+            inexact |= pin[v];
+        }
+    }
     double R, e;
     two_sum(hi, lo, R, e);
-    const double delta = (double)(dim + 64) * 0x1p-100;   // relative error bound
+    const double delta = (double)(dim + 65 * WPP + 64) * 0x1p-100;   // relative error bound
     int ex;
     const double frac = frexp(R, &ex);                   // R = frac 2^ex, frac in [0.5, 1)
     // rounding boundaries of R: R +- half an ulp (ulp = 2^(ex-53)), except
@@ -444,9 +479,11 @@ template <typename T>
 int run_canonical(const T *A, const T *B, long long dim, CanonOut &co, long long nwaves, hipStream_t st)
 {
     if (nwaves <= 0) return CIL_OK;
-    const long long blocks = (nwaves + 3) / 4;
     const ProfMark pm = prof_begin("k_canonical", st);
-    hipLaunchKernelGGL(k_canonical<T>, dim3((unsigned)blocks), dim3(256), 0, st, A, B, dim, co);
+    if (nwaves < 2048 && dim >= 4096)
+        hipLaunchKernelGGL((k_canonical<T, 16>), dim3((unsigned)nwaves), dim3(1024), 0, st, A, B, dim, co);
+    else
+        hipLaunchKernelGGL((k_canonical<T, 1>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, st, A, B, dim, co);
     prof_end(pm, st);
     return check_launch("k_canonical");
 }
@@ -506,8 +543,9 @@ int classify(ClassifyArgs &c, long long nA, long long nB, hipStream_t st)
 {
     const long long n = nA * nB;
     if (n <= 0) return CIL_OK;
+    const long long blocks = std::min<long long>((n + 255) / 256, 4096);
     const ProfMark pm = prof_begin("k_classify", st);
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, nA, nB);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)blocks), dim3(256), 0, st, c, nA, nB);
     prof_end(pm, st);
     return check_launch("k_classify");
 }

@@ -165,11 +165,14 @@ int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const
 // - (m_eff/2) log 2 pi.  FP64 throughout.
 constexpr int LMAX = 64;
 
-__global__ __launch_bounds__(64) void k_loglik(const double *Y, int n, int M, const double *yobs,
-                                               double *f, double *loglik, int *meff, int *status)
+__global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, const double *yobs,
+                                                double *f, double *loglik, int *meff, int *status)
 {
+    constexpr int RC = 32;                                   // rows staged per chunk
+    constexpr int NE = (LMAX * (LMAX + 1) / 2 + 255) / 256;  // covariance entries per thread
     __shared__ double mu[LMAX];
     __shared__ double S[LMAX][LMAX + 1];
+    __shared__ double Yc[RC][LMAX];
     __shared__ int keep[LMAX];
     __shared__ int nk;
     __shared__ double z[LMAX];
@@ -183,20 +186,44 @@ __global__ __launch_bounds__(64) void k_loglik(const double *Y, int n, int M, co
         mu[lane] = s / n;
     }
     __syncthreads();
-    // covariance entries (i, j), i >= j, spread over the lanes
+    // covariance entries (i, j), i >= j, spread over the threads; the centred
+    // rows are staged in LDS a chunk at a time, each entry sums over r in order
     const int ne = M * (M + 1) / 2;
-    for (int e = lane; e < ne; e += 64) {
-        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
-        while ((i + 1) * (i + 2) / 2 <= e) ++i;
-        while (i * (i + 1) / 2 > e) --i;
-        const int j = e - i * (i + 1) / 2;
-        double s = 0.0;
-        const double mi = mu[i], mj = mu[j];
-        for (int r = 0; r < n; ++r) s += (Yp[(size_t)r * M + i] - mi) * (Yp[(size_t)r * M + j] - mj);
-        s /= (n - 1);
-        S[i][j] = s;
-        S[j][i] = s;
+    double acc[NE];
+    int ei[NE], ej[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+        acc[t] = 0.0;
+        const int e = lane + 256 * t;
+        int i = 0;
+        if (e < ne) {
+            i = (int)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            while (i * (i + 1) / 2 > e) --i;
+        }
+        ei[t] = i;
+        ej[t] = e < ne ? e - i * (i + 1) / 2 : 0;
     }
+    for (int r0 = 0; r0 < n; r0 += RC) {
+        const int rows = min(RC, n - r0);
+        for (int q = lane; q < rows * M; q += 256) {
+            const int r = q / M, m = q % M;
+            Yc[r][m] = Yp[(size_t)(r0 + r) * M + m] - mu[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NE; ++t)
+            if (lane + 256 * t < ne)
+                for (int r = 0; r < rows; ++r) acc[t] += Yc[r][ei[t]] * Yc[r][ej[t]];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < NE; ++t)
+        if (lane + 256 * t < ne) {
+            const double s = acc[t] / (n - 1);
+            S[ei[t]][ej[t]] = s;
+            S[ej[t]][ei[t]] = s;
+        }
     __syncthreads();
     if (lane == 0) {
         int c = 0;
@@ -261,7 +288,7 @@ int loglik_impl(const double *Y, int P, int n, int M, const double *yobs, double
 {
     if (P <= 0) return CIL_OK;
     const ProfMark pm = prof_begin("k_loglik", st);
-    hipLaunchKernelGGL(k_loglik, dim3(P), dim3(64), 0, st, Y, n, M, yobs, f, ll, meff, status);
+    hipLaunchKernelGGL(k_loglik, dim3(P), dim3(256), 0, st, Y, n, M, yobs, f, ll, meff, status);
     prof_end(pm, st);
     return check_launch("k_loglik");
 }
