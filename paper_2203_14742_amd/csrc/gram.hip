@@ -82,13 +82,15 @@ __global__ __launch_bounds__(256) void k_split_rows(const float *X, long long di
 // ------------------------------------------------------------------ Gram
 // Grid (tiles over B, tiles over A, K splits).  Four wavefronts, each a 64 x 64
 // block of the 128 x 128 tile as 2 x 2 MFMA 32 x 32 tiles.  Output: FP64
-// partial Gram P[split][i][j].
+// partial Gram P[split][i][j].  Registers are held to 256 so that two
+// workgroups share a CU (LDS 2 x 74 KB): one stages its next tiles while the
+// other runs its MFMAs.
 //
 // v_mfma_f32_32x32x16_bf16 lane layout: lane l supplies row l%32 of the A
 // block and row l%32 of the B block (a column of B^T), elements
 // k = 8 (l/32) .. 8 (l/32) + 7 of the 16-wide k step; accumulator element r of
 // lane l is C[8 (r/4) + 4 (l/32) + r%4][l%32].
-__global__ __launch_bounds__(256) void k_gram_bf16x3(const __bf16 *Ah, const __bf16 *Al, long long nA,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_bf16x3(const __bf16 *Ah, const __bf16 *Al, long long nA,
                                                      const __bf16 *Bh, const __bf16 *Bl, long long nB,
                                                      long long dimP, long long ksplit, double *P)
 {
