@@ -250,8 +250,12 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   one lane, 4n threads per solve; 1 = one species per lane, 8n threads;
  *   2, 3 = shapes 0, 1 with the column-pass divisor applied in the split
  *   step's complex form (fewer operations, a larger table).  Every shape
- *   computes the same step; timing and register use differ. */
-enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2 };
+ *   computes the same step; timing and register use differ.
+ * CIL_OPT_BOOTSTRAP_GATHER (value 0/1): 1 = bootstrap counts always by the
+ *   per-resample gather kernel; 0 (default) = on the matrix cores when
+ *   M <= 32 and no pattern occurs more than 256 times in a resample (the
+ *   gather kernel otherwise).  Both give the same exact counts. */
+enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

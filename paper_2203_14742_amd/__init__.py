@@ -25,6 +25,7 @@ CIL_PATH_AUTO, CIL_PATH_PLAIN, CIL_PATH_FUSED, CIL_PATH_FUSED_LINE, CIL_PATH_FUS
 CIL_SOLVE_OK, CIL_SOLVE_NONFINITE, CIL_SOLVE_MAXSTEPS, CIL_SOLVE_FP32_FLOOR = 0, 1, 2, 3
 CIL_OPT_FORCE_EXACT_SUM = 1
 CIL_OPT_QUAD_SHAPE = 2
+CIL_OPT_BOOTSTRAP_GATHER = 3
 
 
 class CilError(RuntimeError):

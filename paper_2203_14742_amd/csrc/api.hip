@@ -40,6 +40,7 @@ int last_distance_stats(int64_t *, int64_t *, int64_t *);
 void set_force_exact(int);
 int set_quad_shape(int64_t);
 int stepper_release();
+void set_boot_gather(int);
 
 // ------------------------------------------------------------------ errors
 namespace {
@@ -498,6 +499,10 @@ int cil_set_option(int32_t option, int64_t value)
         return CIL_OK;
     }
     if (option == CIL_OPT_QUAD_SHAPE) return set_quad_shape(value);
+    if (option == CIL_OPT_BOOTSTRAP_GATHER) {
+        set_boot_gather((int)value);
+        return CIL_OK;
+    }
     return set_error(CIL_EINVAL, "unknown option %d", option);
 }
 

@@ -38,7 +38,7 @@ enum WsSlot {
     WS_STEP_SOLVES = 0, WS_STEP_LIST, WS_STEP_RESID, WS_STEP_TABLES, WS_STEP_WORK_A,
     WS_STEP_WORK_B, WS_STEP_STATE64, WS_STEP_LIST64, WS_STEP_DCT,
     WS_DIST_NORMS, WS_DIST_SPLIT_A, WS_DIST_SPLIT_B, WS_DIST_RECHECK, WS_DIST_COUNTS,
-    WS_DIST_MISC, WS_DIST_SAMPLE, WS_BOOT_MISC, WS_STATS_MISC,
+    WS_DIST_MISC, WS_DIST_SAMPLE, WS_BOOT_MISC, WS_BOOT_MULT, WS_STATS_MISC,
     WS_NUM_SLOTS
 };
 int ws_get(int slot, size_t bytes, void **ptr);

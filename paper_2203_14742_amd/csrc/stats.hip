@@ -117,6 +117,158 @@ __global__ void k_boot_finish(const unsigned long long *Ycnt, long long n, doubl
     if (Y) Y[e] = (double)c / denom;
 }
 
+// ------------------------------------------------- bootstrap on MFMA
+// With w_A[r][i], w_B[r][j] the multiplicities of pattern i (j) in resample
+// r, Ycount[r][t-1] = sum_i sum_j w_A[r][i] w_B[r][j] [bins_ij >= t]
+//                   = sum_j w_B[r][j] U_t[r][j],  U_t = W_A T_t,  T_t = [bins >= t].
+// U_t is a product on the matrix cores: w_A in bf16 (integers <= 256 are
+// exact), T_t as bf16 0/1 built from the bin bytes per threshold, FP32
+// accumulation (partial sums are integers <= kA < 2^24: exact); the sum with
+// w_B is taken in integers.  A workgroup owns 32 resamples x 32 columns j;
+// wave w owns thresholds 8 w + 1 .. 8 w + 8.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+int g_boot_mfma = 1;         // 0: always the gather kernel (cil_set_option)
+void set_boot_gather(int v) { g_boot_mfma = v ? 0 : 1; }
+
+constexpr int BKC = 128;     // i per LDS stage
+constexpr int BTPW = 8;      // thresholds per wavefront (M <= 32)
+
+__global__ void k_multiplicity(const int *idx, int k, int n_boot, long long n, int ld, int *cnt, int *bad)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n_boot * k) return;
+    const long long r = e / k;
+    const int v = idx[e];
+    if (v < 0 || v >= n) {
+        atomicOr(bad, 1);
+        return;
+    }
+    atomicAdd(&cnt[r * ld + v], 1);
+}
+
+__global__ void k_mult_to_bf16(const int *cnt, long long total, __bf16 *w, int *over)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int v = cnt[e];
+    if (v > 256) atomicOr(over, 1);
+    w[e] = (__bf16)(float)v;
+}
+
+// 8 bin bytes -> 8 bf16 values [byte >= t] (bytes and t below 128): the high
+// bit of (byte | 0x80) - t marks byte >= t; v_perm moves bytes 0..3 into the
+// low byte of 16-bit halves and 0x80 * 0x7f = 0x3f80 is bf16 1.0.
+__device__ __forceinline__ bf16x8_t thermometer(uint2 b, unsigned t)
+{
+    const unsigned tt = t * 0x01010101u;
+    const unsigned m0 = ((b.x | 0x80808080u) - tt) & 0x80808080u;
+    const unsigned m1 = ((b.y | 0x80808080u) - tt) & 0x80808080u;
+    unsigned d[4];
+    d[0] = __builtin_amdgcn_perm(0u, m0, 0x0c010c00u) * 0x7fu;
+    d[1] = __builtin_amdgcn_perm(0u, m0, 0x0c030c02u) * 0x7fu;
+    d[2] = __builtin_amdgcn_perm(0u, m1, 0x0c010c00u) * 0x7fu;
+    d[3] = __builtin_amdgcn_perm(0u, m1, 0x0c030c02u) * 0x7fu;
+    return __builtin_bit_cast(bf16x8_t, d);
+}
+
+__global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long long nA, long long nB, int M,
+                                                   const __bf16 *WA, long long ldA, const int *WB, int n_boot,
+                                                   unsigned long long *acc)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sA[32][BKC + 8];     // resample x i
+    __shared__ __attribute__((aligned(16))) uint8_t sT[32][BKC + 16];   // column j x i
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const long long r0 = (long long)blockIdx.y * 32, j0 = (long long)blockIdx.x * 32;
+    floatx16_t c[BTPW];
+#pragma unroll
+    for (int q = 0; q < BTPW; ++q)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) c[q][e] = 0.0f;
+    for (long long i0 = 0; i0 < nA; i0 += BKC) {
+        __syncthreads();
+        for (int e = tid; e < 32 * (BKC / 8); e += 256) {          // W_A rows (zero padded)
+            const int row = e / (BKC / 8), ch = e % (BKC / 8);
+            *(bf16x8_t *)&sA[row][8 * ch] = *(const bf16x8_t *)(WA + (r0 + row) * ldA + i0 + 8 * ch);
+        }
+        for (int e = tid; e < BKC * 32; e += 256) {                 // bins rows i, columns j -> sT[j][i]
+            const int i = e / 32, j = e % 32;
+            sT[j][i] = (i0 + i < nA && j0 + j < nB) ? bins[(i0 + i) * nB + j0 + j] : (uint8_t)0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < BKC; kk += 16) {
+            const int kofs = kk + 8 * (lane >> 5);
+            const bf16x8_t a = *(const bf16x8_t *)&sA[lane & 31][kofs];
+            const uint2 braw = *(const uint2 *)&sT[lane & 31][kofs];
+#pragma unroll
+            for (int q = 0; q < BTPW; ++q) {
+                const int t = wv * BTPW + q + 1;
+                if (t <= M) c[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, thermometer(braw, t), c[q], 0, 0, 0);
+            }
+        }
+    }
+    // C[row][col] = U_t[r0 + row][j0 + col]; element e of lane l: row 8 (e/4) + 4 (l/32) + e%4, col l%32
+    const long long j = j0 + (lane & 31);
+    int wb[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const long long r = r0 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
+        wb[e] = (r < n_boot && j < nB) ? WB[r * nB + j] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < BTPW; ++q) {
+        const int t = wv * BTPW + q + 1;
+        if (t > M) break;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int v = (int)c[q][e] * wb[e];
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);   // over the 32 columns of this half
+            const long long r = r0 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
+            if ((lane & 31) == 0 && r < n_boot && v) atomicAdd(&acc[r * M + (t - 1)], (unsigned long long)v);
+        }
+    }
+}
+
+// MFMA path; returns 0 when it ran, 1 when a multiplicity exceeds 256 (the
+// caller then takes the gather path), or an error.
+int bootstrap_mfma(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA, const int *idxB,
+                   int kB, int n_boot, unsigned long long *acc, hipStream_t st, int *ran)
+{
+    *ran = 0;
+    const long long nbP = (n_boot + 31) / 32 * 32, ldA = (nA + BKC - 1) / BKC * BKC;
+    const size_t szA = sizeof(int) * (size_t)(nbP * ldA), szB = sizeof(int) * (size_t)n_boot * nB;
+    const size_t szW = sizeof(__bf16) * (size_t)(nbP * ldA);
+    void *p;
+    CIL_TRY(ws_get(WS_BOOT_MULT, szA + szB + szW + 64, &p));
+    int *cA = (int *)p;
+    int *cB = cA + nbP * ldA;
+    __bf16 *wA = (__bf16 *)(cB + (size_t)n_boot * nB);
+    int *flags = (int *)((char *)wA + szW);          // bad, over
+    CIL_TRY(fill_zero(cA, szA + szB, st));
+    CIL_TRY(fill_zero(flags, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_multiplicity, dim3((unsigned)(((long long)n_boot * kA + 255) / 256)), dim3(256), 0, st, idxA,
+                       kA, n_boot, nA, (int)ldA, cA, flags);
+    hipLaunchKernelGGL(k_multiplicity, dim3((unsigned)(((long long)n_boot * kB + 255) / 256)), dim3(256), 0, st, idxB,
+                       kB, n_boot, nB, (int)nB, cB, flags);
+    hipLaunchKernelGGL(k_mult_to_bf16, dim3((unsigned)((nbP * ldA + 255) / 256)), dim3(256), 0, st, cA, nbP * ldA, wA,
+                       flags + 1);
+    CIL_TRY(check_launch("k_multiplicity"));
+    int hf[2] = {0, 0};
+    CIL_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipStreamSynchronize(st));
+    if (hf[0]) return set_error(CIL_EINVAL, "bootstrap index out of range");
+    if (hf[1]) return CIL_OK;                        // a multiplicity above 256: not exact in bf16
+    dim3 grid((unsigned)((nB + 31) / 32), (unsigned)(nbP / 32));
+    const ProfMark pm = prof_begin("k_bootstrap", st);
+    hipLaunchKernelGGL(k_boot_mfma, grid, dim3(256), 0, st, bins, nA, nB, M, wA, ldA, cB, n_boot, acc);
+    prof_end(pm, st);
+    CIL_TRY(check_launch("k_boot_mfma"));
+    *ran = 1;
+    return CIL_OK;
+}
+
 int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
                    const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st)
 {
@@ -126,7 +278,10 @@ int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const
     unsigned long long *acc = (unsigned long long *)p;
     int *bad = (int *)(acc + n);
     CIL_TRY(fill_zero(acc, sizeof(unsigned long long) * (size_t)(n + 1), st));
-    if (n_boot > 0 && kA > 0 && kB > 0) {
+    int ran = 0;
+    if (n_boot > 0 && kA > 0 && kB > 0 && M <= 4 * BTPW && g_boot_mfma)
+        CIL_TRY(bootstrap_mfma(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, acc, st, &ran));
+    if (!ran && n_boot > 0 && kA > 0 && kB > 0) {
         // split the kA rows of a resample over enough blocks to fill the chip
         int slices = (int)std::max<long long>(1, std::min<long long>(kA, (2048 + n_boot - 1) / n_boot));
         const int rpb = (kA + slices - 1) / slices;

@@ -204,17 +204,39 @@ def test_adaptive_bins_rejects_a_degenerate_range(cil):
     assert e.value.code == cil.CIL_EINVAL
 
 
-@pytest.mark.parametrize("M", [13, 32, 70])
-def test_bootstrap_counts_bit_exact(cil, oracle_mod, M):
-    A, B = sets(90, 75, 64, seed=M, dtype=np.float64)
+@pytest.mark.parametrize("gather", [0, 1])
+@pytest.mark.parametrize("M", [1, 13, 32, 33, 70])
+def test_bootstrap_counts_bit_exact(cil, oracle_mod, M, gather):
+    """Both bootstrap paths (matrix cores; gather) against the oracle, with
+    ragged sizes (nA, nB not multiples of the tiles, n_boot = 50)."""
+    A, B = sets(290, 75, 64, seed=M, dtype=np.float64)
     D = oracle_mod.pair_d2(A, B)
     radii = oracle_mod.radii_ladder(D.min(), D.max(), M)
     bins, _ = cil.cil_pair_bins(dev(A), dev(B), radii)
-    ia, ib = cs.resample_halves(90, 75, 90, 75, 50, seed=M)
+    ia, ib = cs.resample_halves(290, 75, 290, 75, 50, seed=M)
     want_c, want_y = oracle_mod.bootstrap_vectors(D, ia, ib, radii)
-    Yc, Y = cil.cil_bootstrap_features(bins, torch.from_numpy(ia), torch.from_numpy(ib), M)
+    cil.cil_set_option(cil.CIL_OPT_BOOTSTRAP_GATHER, gather)
+    try:
+        Yc, Y = cil.cil_bootstrap_features(bins, torch.from_numpy(ia), torch.from_numpy(ib), M)
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_BOOTSTRAP_GATHER, 0)
     assert np.array_equal(Yc.cpu().numpy(), want_c)
     assert np.array_equal(Y.cpu().numpy(), want_y)
+
+
+def test_bootstrap_high_multiplicity_falls_back_exactly(cil, oracle_mod):
+    """A resample that repeats one pattern 300 times (not exact in bf16) still
+    gives the oracle's counts (the gather path takes over)."""
+    A, B = sets(40, 30, 16, seed=7, dtype=np.float64)
+    D = oracle_mod.pair_d2(A, B)
+    radii = oracle_mod.radii_ladder(D.min(), D.max(), 8)
+    bins, _ = cil.cil_pair_bins(dev(A), dev(B), radii)
+    ia = np.zeros((3, 400), dtype=np.int32)
+    ia[:, 300:] = np.arange(100, dtype=np.int32)[None, :] % 40
+    ib = np.tile(np.arange(30, dtype=np.int32), (3, 2))
+    want_c, _ = oracle_mod.bootstrap_vectors(D, ia, ib, radii)
+    Yc, _ = cil.cil_bootstrap_features(bins, torch.from_numpy(ia), torch.from_numpy(ib), 8)
+    assert np.array_equal(Yc.cpu().numpy(), want_c)
 
 
 def test_bootstrap_rejects_bad_index(cil):
