@@ -101,7 +101,8 @@ def measured_traffic(kname: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "features4096", "bz_uneven2048"],
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "features4096", "bz_uneven2048", "fhn128_mcmc"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -137,6 +138,9 @@ def main():
         return
     if args.workload == "bz_uneven2048":
         uneven_main(args)
+        return
+    if args.workload == "fhn128_mcmc":
+        mcmc_main(args)
         return
 
     import cil_synth as cs
@@ -433,6 +437,100 @@ def uneven_main(args):
                    "steps_per_solve": w["max_steps"], "stepping": "fp32 fused persistent, one kernel per side on "
                    "forked streams", "parallelism": "none (1 GPU)"},
         "all_ok": bool(np.all(rep["status"] == 0)),
+        "roofline": roof,
+        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def mcmc_main(args):
+    """Synthetic-likelihood evaluations (Alg. 3bst) on a window of proposals:
+    the window's synthetic patterns in one simulate call (FP32, per-solve
+    (mu, eps)), then per proposal the adaptive radii and bins of the
+    synthetic self-pairs, 200 resample vectors and the observed vector
+    against the data set, and one batched likelihood call.  `value` is
+    synthetic patterns/s; likelihood evaluations/s are reported too."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS["fhn128_mcmc"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    P, nsyn, nset, nboot, M, n = w["window"], w["n_syn"], w["n_set"], w["n_boot"], w["M"], w["n"]
+    d = 2 * n * n
+    thetas = cs.relative_draws(w["theta0"], P, w["rel"], seed=w["proposal_seed"])
+    params = [(t[0], t[1], w["alpha"]) for t in thetas for _ in range(nsyn)]
+    p0 = (w["theta0"][0], w["theta0"][1], w["alpha"])
+    base = cil.cil_homogeneous_state(w["model"], p0)
+    ics = torch.tensor(np.concatenate([cs.initial_conditions(base, n, nsyn, seed=w["ic_seed"] + p)
+                                       for p in range(P)]), dtype=torch.float32, device=dev)
+    probs = cil.make_problems(n, w["L"], w["nu"], params)
+    data = torch.tensor(cs.initial_conditions(base, n, nset, seed=w["data_seed"]), dtype=torch.float32, device=dev)
+    cil.cil_simulate_patterns(w["model"], data, cil.make_problems(n, w["L"], w["nu"], p0, count=nset), w["dt"],
+                              w["max_steps"], check_every=w["max_steps"])
+    data = data.reshape(nset, d)
+    idx = [cs.resample_synthetic(nsyn, nset, nboot, seed=w["boot_seed"] + p) for p in range(P)]
+    idx = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), torch.from_numpy(c)[None, :].to(dev))
+           for a, b, c in idx]
+    ident = torch.arange(nset, dtype=torch.int32, device=dev)[None, :]
+    st = torch.empty_like(ics)
+    Y = torch.empty((P, nboot, M), dtype=torch.float64, device=dev)
+    yobs = torch.empty((P, M), dtype=torch.float64, device=dev)
+    t_sim = [0.0]
+
+    def one_step():
+        t0 = time.perf_counter()
+        st.copy_(ics)
+        cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], check_every=w["max_steps"])
+        torch.cuda.synchronize()
+        t_sim[0] += time.perf_counter() - t0
+        S = st.reshape(P * nsyn, d)
+        for p in range(P):
+            Sp = S[p * nsyn:(p + 1) * nsyn]
+            _, _, radii, bins, _ = cil.cil_pair_bins_adaptive(Sp, Sp, M, exclude_diagonal=True)
+            _, Y[p] = cil.cil_bootstrap_features(bins, idx[p][0], idx[p][1], M, want_counts=False)
+            dbins, _ = cil.cil_pair_bins(data, Sp, radii, want_counts=False)
+            _, yobs[p] = cil.cil_bootstrap_features(dbins, ident, idx[p][2], M, want_counts=False)
+        return cil.cil_gaussian_loglik(Y, yobs)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t_sim[0] = 0.0
+    cil.cil_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
+    cil.cil_profile(False)
+    K = args.steps
+    kname = "k_fused_q_f32_n128"
+    roof = None
+    if kname in prof:
+        cnt, tot_ms = prof[kname]
+        flops = P * nsyn * w["max_steps"] * fused_step_flops(n, REACTION_FLOPS[w["model"]]) * cnt / K
+        ach = flops / (tot_ms / cnt * 1e-3) / 1e12
+        roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": VALU_FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None, "launches": cnt,
+                "avg_launch_ms": round(tot_ms / cnt, 3), "flops_per_solve_step": fused_step_flops(n, REACTION_FLOPS[w["model"]])}
+    stt = out[3].cpu().numpy()
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(P * nsyn * K / el, 2), "unit": "patterns/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fhn128_mcmc", "proposals_timed": P, "of_proposals": w["proposals"],
+                   "synthetic_per_proposal": nsyn, "data_patterns": nset, "grid": n, "steps_per_solve": w["max_steps"],
+                   "bootstrap": nboot, "radii": M, "parallelism": "none (1 GPU)"},
+        "likelihood_evaluations_per_s": round(P * K / el, 3),
+        "stepping_share": round(t_sim[0] / el, 3),
+        "loglik_ok": int((stt == 0).sum()), "loglik_not_spd": int((stt != 0).sum()),
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": None,

@@ -181,4 +181,11 @@ WORKLOADS = {
     # its own (A, B, Du, Dv) around Table exp1's point, FP32, T = 100 at dt = 0.05.
     "bz_uneven2048": dict(model=BRUSSELATOR, count=2048, sides=(32, 64, 128), L=1.0, dt=0.05, max_steps=2000,
                           check_every=2000, seed=4, ic_seed=4, rel=0.05),
+    # Synthetic-likelihood evaluations for MCMC (Alg. 3bst): FitzHugh-Nagumo
+    # 128^2, proposals (mu, eps) = theta0 (1 +- 10 %), 64 synthetic patterns
+    # each (T = 100, FP32), 8 data patterns at theta0, 200 resamples, 13
+    # adaptive power-law radii; timed on a window of the first 20 proposals.
+    "fhn128_mcmc": dict(model=FHN, n=128, L=1.0, nu=(0.05, 0.00028), theta0=(1.0, 10.0), alpha=1.0, rel=0.1,
+                        proposals=1000, window=20, n_syn=64, n_set=8, n_boot=200, M=13, dt=0.05, max_steps=2000,
+                        proposal_seed=7, data_seed=8, ic_seed=100, boot_seed=9),
 }

@@ -202,13 +202,15 @@ int cil_approx_d2(const void *setA, int64_t nA, const void *setB, int64_t nB, in
 int cil_radii(double d2min, double d2max, int32_t M, int32_t law, double *radii);
 
 /* Range, radii and bins in one call, from a single fast pass over the pairs
- * (the adaptive radii of Sec. 3.2): d2min, d2max as cil_distance_range (all
- * pairs), radii host[M] as cil_radii(d2min, d2max, M, law), then bins and
- * counts as cil_pair_bins with those radii.  bins device uint8[nA][nB] or
- * NULL; counts host[M] or NULL.  Errors as those three calls (CIL_EINVAL for
- * a degenerate range, e.g. all distances equal). */
+ * (the adaptive radii of Sec. 3.2): d2min, d2max as cil_distance_range
+ * (exclude_diagonal != 0: pairs i != j only, requires nA == nB), radii
+ * host[M] as cil_radii(d2min, d2max, M, law), then bins and counts of every
+ * pair (diagonal included) as cil_pair_bins with those radii.  bins device
+ * uint8[nA][nB] or NULL; counts host[M] or NULL.  Errors as those three calls
+ * (CIL_EINVAL for a degenerate range, e.g. all distances equal). */
 int cil_pair_bins_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
-                           cil_precision prec, int32_t M, int32_t law, double *d2min /*host*/,
+                           cil_precision prec, int32_t exclude_diagonal, int32_t M, int32_t law,
+                           double *d2min /*host*/,
                            double *d2max /*host*/, double *radii /*host[M]*/, uint8_t *bins,
                            int64_t *counts /*host[M]*/, void *hip_stream);
 

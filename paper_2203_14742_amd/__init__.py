@@ -71,7 +71,8 @@ def lib() -> ctypes.CDLL:
         L.cil_distance_range.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, vp, vp, vp]
         L.cil_canonical_d2.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, vp, i64, vp, vp]
         L.cil_radii.argtypes = [dbl, dbl, i32, i32, vp]
-        L.cil_pair_bins_adaptive.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.cil_pair_bins_adaptive.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, i32, i32, vp, vp, vp, vp, vp,
+                                             vp]
         L.cil_approx_d2.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, vp, vp]
         L.cil_approx_d2.restype = ctypes.c_int
         L.cil_last_distance_stats.argtypes = [vp, vp, vp]
@@ -226,7 +227,8 @@ def cil_pair_bins(A, B, radii, bins=None, want_counts: bool = True):
     return bins, counts
 
 
-def cil_pair_bins_adaptive(A, B, M: int, law: int = 0, bins=None, want_bins: bool = True):
+def cil_pair_bins_adaptive(A, B, M: int, law: int = 0, bins=None, want_bins: bool = True,
+                           exclude_diagonal: bool = False):
     """Range, radii and bins from one fast pass.  Returns (d2min, d2max,
     radii host float64[M], bins uint8 [nA, nB] device tensor or None, counts int64[M])."""
     import torch
@@ -237,7 +239,8 @@ def cil_pair_bins_adaptive(A, B, M: int, law: int = 0, bins=None, want_bins: boo
     radii = np.zeros(M, dtype=np.float64)
     counts = np.zeros(M, dtype=np.int64)
     _check(lib().cil_pair_bins_adaptive(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1],
-                                        _prec(A2), M, law, ctypes.byref(lo), ctypes.byref(hi), radii.ctypes.data,
+                                        _prec(A2), int(exclude_diagonal), M, law, ctypes.byref(lo), ctypes.byref(hi),
+                                        radii.ctypes.data,
                                         _dev(bins, "bins") if want_bins else None, counts.ctypes.data, _stream(A2)))
     return lo.value, hi.value, radii, (bins if want_bins else None), counts
 

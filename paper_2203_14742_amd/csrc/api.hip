@@ -22,8 +22,8 @@ template <typename T>
 int pair_bins_impl(const T *, long long, const T *, long long, long long, const double *, int, uint8_t *,
                    std::vector<unsigned long long> &, hipStream_t);
 template <typename T>
-int adaptive_bins_impl(const T *, long long, const T *, long long, long long, int, int, double *, double *, double *,
-                       uint8_t *, std::vector<unsigned long long> &, hipStream_t);
+int adaptive_bins_impl(const T *, long long, const T *, long long, long long, int, int, int, double *, double *,
+                       double *, uint8_t *, std::vector<unsigned long long> &, hipStream_t);
 template <typename T>
 int distance_range_impl(const T *, long long, const T *, long long, long long, int, double *, double *,
                         hipStream_t);
@@ -435,24 +435,25 @@ int cil_radii(double d2min, double d2max, int32_t M, int32_t law, double *radii)
 }
 
 int cil_pair_bins_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
-                           cil_precision prec, int32_t M, int32_t law, double *d2min, double *d2max, double *radii,
-                           uint8_t *bins, int64_t *counts, void *hip_stream)
+                           cil_precision prec, int32_t exclude_diagonal, int32_t M, int32_t law, double *d2min,
+                           double *d2max, double *radii, uint8_t *bins, int64_t *counts, void *hip_stream)
 {
     API_BEGIN();
     CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
     if (!d2min || !d2max || !radii) return set_error(CIL_EINVAL, "null output");
     if (M < 1 || M > 255) return set_error(CIL_EINVAL, "M must be in [1, 255]");
     if (law != 0 && law != 1) return set_error(CIL_EINVAL, "unknown radius law %d", law);
-    if (nA * nB <= 0) return set_error(CIL_EINVAL, "no pairs");
+    if (exclude_diagonal && nA != nB) return set_error(CIL_EINVAL, "exclude_diagonal needs nA == nB");
+    if (nA * nB - (exclude_diagonal ? nA : 0) <= 0) return set_error(CIL_EINVAL, "no pairs");
     CIL_TRY(check_device());
     std::vector<unsigned long long> hist;
     hipStream_t st = (hipStream_t)hip_stream;
     if (prec == CIL_FP64)
-        CIL_TRY(adaptive_bins_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim, M, law, d2min,
-                                           d2max, radii, bins, hist, st));
+        CIL_TRY(adaptive_bins_impl<double>((const double *)setA, nA, (const double *)setB, nB, dim, exclude_diagonal,
+                                           M, law, d2min, d2max, radii, bins, hist, st));
     else
-        CIL_TRY(adaptive_bins_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, M, law, d2min, d2max,
-                                          radii, bins, hist, st));
+        CIL_TRY(adaptive_bins_impl<float>((const float *)setA, nA, (const float *)setB, nB, dim, exclude_diagonal, M,
+                                          law, d2min, d2max, radii, bins, hist, st));
     if (counts) {
         unsigned long long run = 0;
         for (int m = M; m >= 1; --m) {

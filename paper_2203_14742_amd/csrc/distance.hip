@@ -685,7 +685,7 @@ int pair_bins_impl(const T *A, long long nA, const T *B, long long nB, long long
 // Range, radii and bins from one fast pass (the partials stay in their
 // workspace between the two classifications).
 template <typename T>
-int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int M, int law,
+int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long long dim, int excl, int M, int law,
                        double *dmin, double *dmax, double *radii, uint8_t *bins,
                        std::vector<unsigned long long> &hist_host, hipStream_t st)
 {
@@ -693,7 +693,8 @@ int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long 
     CIL_TRY(scratch(nA * nB, &s));
     Approx ap;
     CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
-    CIL_TRY(range_from_approx(A, nA, B, nB, dim, ap, s, 0, dmin, dmax, st));
+    CIL_TRY(range_from_approx(A, nA, B, nB, dim, ap, s, excl, dmin, dmax, st));
+    ap.c.exclude_diag = 0;                 // bins of every pair
     const long long nrange = t_rechecked, nrange_exact = t_exact;
     CIL_TRY(radii_ladder(*dmin, *dmax, M, law, radii));
     CIL_TRY(bins_from_approx(A, nA, B, nB, dim, ap, s, radii, M, bins, hist_host, st));
@@ -703,9 +704,9 @@ int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long 
 }
 
 template int adaptive_bins_impl<double>(const double *, long long, const double *, long long, long long, int, int,
-                                        double *, double *, double *, uint8_t *, std::vector<unsigned long long> &,
-                                        hipStream_t);
-template int adaptive_bins_impl<float>(const float *, long long, const float *, long long, long long, int, int,
+                                        int, double *, double *, double *, uint8_t *,
+                                        std::vector<unsigned long long> &, hipStream_t);
+template int adaptive_bins_impl<float>(const float *, long long, const float *, long long, long long, int, int, int,
                                        double *, double *, double *, uint8_t *, std::vector<unsigned long long> &,
                                        hipStream_t);
 
