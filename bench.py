@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32-stepping", action="store_true")
     ap.add_argument("--cpu-sample-solves", type=int, default=96)
+    ap.add_argument("--tune-steps", type=int, default=100,
+                    help="bz_uneven2048: steps per autotuning trial (0 = the plan's own stepping)")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the stepper sources (recorded beside the HBM counters) and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -380,9 +382,11 @@ def features_main(args):
 
 def uneven_main(args):
     """Uneven batch alone: 2048 Brusselator solves of sides 32, 64, 128 with
-    per-solve parameters around a Turing point, 2000 FP32 steps (T = 100), one
-    simulate call (the three sides' persistent kernels run side by side).
-    `value` is stationary patterns/s."""
+    per-solve parameters around a Turing point, 2000 FP32 steps (T = 100), as
+    one simulate plan: a HIP graph holding one persistent kernel per side
+    (forked streams, joined), code shape per side chosen by the plan's
+    autotuner before timing.  A step = restore the initial states + one graph
+    launch.  `value` is stationary patterns/s."""
     import numpy as np
     import torch
 
@@ -397,12 +401,17 @@ def uneven_main(args):
     flat = cs.uneven_initial_states(bases, ns, seed=w["ic_seed"])
     probs = cil.make_problems(ns, w["L"], nus, ps)
     ics = torch.tensor(flat, dtype=torch.float32, device=dev)
-    st = torch.empty_like(ics)
+    st = ics.clone()
+    t0 = time.perf_counter()
+    plan = cil.SimPlan(w["model"], st, probs, w["dt"], w["max_steps"], check_every=w["check_every"])
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    info = plan.tune(steps=args.tune_steps)
+    t_tune = time.perf_counter() - t0
 
     def one_step():
         st.copy_(ics)
-        return cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"],
-                                         check_every=w["check_every"])
+        plan.launch()
 
     for _ in range(args.warmup):
         one_step()
@@ -410,35 +419,34 @@ def uneven_main(args):
     cil.cil_profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rep = one_step()
+        one_step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
     cil.cil_profile(False)
+    rep = plan.report()
+    plan.close()
     K, B = args.steps, len(ns)
-    kname = max(prof, key=lambda k: prof[k][1])
-    cnt, tot_ms = prof[kname]
-    side = int(kname.rsplit("_n", 1)[1])
-    solves_side = sum(1 for n in ns if n == side)
-    flops = solves_side * w["max_steps"] * fused_step_flops(side, REACTION_FLOPS[w["model"]]) * cnt
-    ach = flops / (tot_ms * 1e-3) / 1e12
-    total_flops = sum(w["max_steps"] * fused_step_flops(n, REACTION_FLOPS[w["model"]]) for n in ns) * K
-    roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": VALU_FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None, "launches": cnt,
-            "avg_launch_ms": round(tot_ms / cnt, 3),
-            "flops_per_solve_step": fused_step_flops(side, REACTION_FLOPS[w["model"]]),
-            "whole_batch_tflops": round(total_flops / el / 1e12, 3)}
+    cnt, tot_ms = prof["sim_plan_graph"]
+    total_flops = sum(w["max_steps"] * fused_step_flops(n, REACTION_FLOPS[w["model"]]) for n in ns)
+    ach = total_flops / (tot_ms / cnt * 1e-3) / 1e12
+    roof = {"kernel": "sim_plan_graph (one persistent kernel per side)", "bound": "alu", "achieved": round(ach, 3),
+            "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / VALU_FP32_PEAK_TFLOPS, 4),
+            "traffic": None, "launches": cnt, "avg_launch_ms": round(tot_ms / cnt, 3),
+            "flops_per_solve_step": {str(n): fused_step_flops(n, REACTION_FLOPS[w["model"]]) for n in w["sides"]}}
     line = {
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
         "value": round(B * K / el, 2), "unit": "patterns/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
         "ms_per_step": round(1e3 * el / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "bz_uneven2048", "solves": B, "sides": list(w["sides"]), "dt": w["dt"],
-                   "steps_per_solve": w["max_steps"], "stepping": "fp32 fused persistent, one kernel per side on "
-                   "forked streams", "parallelism": "none (1 GPU)"},
-        "all_ok": bool(np.all(rep["status"] == 0)),
+                   "steps_per_solve": w["max_steps"], "stepping": "fp32 fused persistent, one HIP graph launch "
+                   "(one kernel per side on forked streams)", "parallelism": "none (1 GPU)"},
+        "autotune": {"trial_steps": args.tune_steps, "seconds": round(t_tune, 3), "plan_seconds": round(t_plan, 3),
+                     "sides": [{"n": g["n"], "solves": g["count"], "shape": g["shape"],
+                                "trial_ms": [round(m, 3) for m in g["tuned_ms"]]} for g in info]},
+        "all_ok": bool(np.all(rep["status"] == 0) and np.all(rep["steps_taken"] == w["max_steps"])),
         "roofline": roof,
-        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)

@@ -148,6 +148,54 @@ int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem
                           void *state, const int64_t *elem_offsets, const cil_stepping *stepping,
                           cil_solve_report *reports, void *hip_stream);
 
+/* Simulate plans.  The paper's experiments draw every statistic from large
+ * batches of independent solves of one model (Sec. 4, many initial states per
+ * parameter value).  A plan binds such a batch -- problems, layout, stepping
+ * and the state buffer -- to device-resident tables and solve descriptors and
+ * to one instantiated HIP graph: a clear of the per-solve results, then one
+ * persistent fused kernel per grid side, the sides forked over plan-owned
+ * streams (default priority) and joined.  cil_sim_plan_launch replays it with
+ * one graph launch, stream-ordered on the caller's stream.
+ *   cil_sim_plan_create: same arguments and checks as cil_simulate_patterns;
+ *     the state pointer is bound to the plan (device, caller-owned, must stay
+ *     valid while the plan lives).  Every grid side must have a fused stepper
+ *     (FP32 n in {32, 64, 128}, FP64 n in {32, 64}), else CIL_EUNSUPPORTED;
+ *     path PLAIN gives CIL_EUNSUPPORTED; an FP32 plan with tol > 0 needs
+ *     polish = 0 (a solve stopping at the FP32 floor then reports status
+ *     FP32_FLOOR), else CIL_EINVAL.  Allocates; synchronises `hip_stream`.
+ *     *plan receives an owned handle (free with cil_sim_plan_destroy).
+ *   cil_sim_plan_tune: the autotuner.  For each grid side, times every code
+ *     shape of the quad-lane stepper (the 4 values of CIL_OPT_QUAD_SHAPE) on
+ *     that side's solves alone from a device copy of the bound state (which it
+ *     leaves unchanged): `steps` > 0 fixed steps per trial (no stop rule), or
+ *     with steps = 0 the plan's own stepping (stop rule and max_steps, so the
+ *     trial time is the side's real completion time).  Keeps the fastest shape
+ *     per side and re-captures the graph.  CIL_EINVAL for steps < 0 or a
+ *     FUSED_LINE plan.  Allocates (a state-sized scratch); synchronises.
+ *   cil_sim_plan_launch: enqueues one graph launch on hip_stream: every solve
+ *     starts at step 0 from what the bound state holds and runs until its stop
+ *     rule fires.  Allocates nothing, does not synchronise; launches of one
+ *     plan must not overlap (they share the result arrays).
+ *   cil_sim_plan_report: after the last launch on hip_stream: per-solve
+ *     results (steps_fp64 is 0), reports host[B] or NULL.  Synchronises.
+ *     Returns CIL_ENONFINITE if a solve ended NONFINITE.
+ *   cil_sim_plan_groups / cil_sim_plan_group_info: the grid sides in launch
+ *     order (most work first): side n, solve count, chosen shape, and the
+ *     tuning times in ms (host[CIL_QUAD_SHAPES] or NULL; 0 before tuning).
+ *   cil_sim_plan_destroy: synchronises the device, frees the plan (NULL ok). */
+typedef struct cil_sim_plan_s cil_sim_plan;
+enum { CIL_QUAD_SHAPES = 4 };
+int cil_sim_plan_create(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B, void *state,
+                        const int64_t *elem_offsets, const cil_stepping *stepping, void *hip_stream,
+                        cil_sim_plan **plan);
+int cil_sim_plan_tune(cil_sim_plan *plan, int64_t steps, void *hip_stream);
+int cil_sim_plan_launch(cil_sim_plan *plan, void *hip_stream);
+int cil_sim_plan_report(cil_sim_plan *plan, cil_solve_report *reports, void *hip_stream);
+int cil_sim_plan_groups(const cil_sim_plan *plan);
+int cil_sim_plan_group_info(const cil_sim_plan *plan, int32_t group, int32_t *n, int32_t *count, int32_t *shape,
+                            double *tuned_ms);
+int cil_sim_plan_destroy(cil_sim_plan *plan);
+
 /* ------------------------------------------------------- CIL statistic */
 /* Squared distances are compared with squared radii: a pair counts under
  * radius R when D < fl(R*R) (strict, eq. eCDF).  D is the canonical squared

@@ -26,6 +26,7 @@ CIL_SOLVE_OK, CIL_SOLVE_NONFINITE, CIL_SOLVE_MAXSTEPS, CIL_SOLVE_FP32_FLOOR = 0,
 CIL_OPT_FORCE_EXACT_SUM = 1
 CIL_OPT_QUAD_SHAPE = 2
 CIL_OPT_BOOTSTRAP_GATHER = 3
+CIL_QUAD_SHAPES = 4
 
 
 class CilError(RuntimeError):
@@ -82,10 +83,19 @@ def lib() -> ctypes.CDLL:
         L.cil_profile.argtypes = [i32]
         L.cil_profile_read.argtypes = [ctypes.c_char_p, vp, vp]
         L.cil_profile_names.argtypes = [vp, i64]
+        L.cil_sim_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, vp, vp]
+        L.cil_sim_plan_tune.argtypes = [vp, i64, vp]
+        L.cil_sim_plan_launch.argtypes = [vp, vp]
+        L.cil_sim_plan_report.argtypes = [vp, vp, vp]
+        L.cil_sim_plan_groups.argtypes = [vp]
+        L.cil_sim_plan_group_info.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.cil_sim_plan_destroy.argtypes = [vp]
         for name in ("cil_homogeneous_state", "cil_simulate_patterns", "cil_features", "cil_pair_bins",
                      "cil_distance_range", "cil_canonical_d2", "cil_radii", "cil_last_distance_stats",
                      "cil_bootstrap_features", "cil_gaussian_loglik", "cil_set_option", "cil_shutdown",
-                     "cil_profile", "cil_profile_read", "cil_profile_names"):
+                     "cil_profile", "cil_profile_read", "cil_profile_names", "cil_sim_plan_create",
+                     "cil_sim_plan_tune", "cil_sim_plan_launch", "cil_sim_plan_report", "cil_sim_plan_groups",
+                     "cil_sim_plan_group_info", "cil_sim_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -189,6 +199,79 @@ def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int
         return out
     _check(rc)
     return out
+
+
+class SimPlan:
+    """A batch of fused solves bound to ``state`` and to one HIP graph
+    (``cil_sim_plan_*``).  ``launch()`` replays it on the current stream: every
+    solve restarts at step 0 from what ``state`` holds.  The tensor must stay
+    alive (and in place) while the plan lives."""
+
+    def __init__(self, model: int, state, problems, dt: float, max_steps: int, tol: float = 0.0,
+                 check_every: int = 1, path: int = CIL_PATH_AUTO, fp32_floor_ulps: int = 0, offsets=None):
+        self.B = len(problems)
+        self.state = state
+        self._h = ctypes.c_void_p()
+        stp = Stepping(dt=dt, max_steps=int(max_steps), tol=tol, check_every=int(check_every), path=int(path),
+                       polish=0, fp32_floor_ulps=int(fp32_floor_ulps))
+        sizes = np.array([2 * problems[b].n * problems[b].n for b in range(self.B)], dtype=np.int64)
+        offs = None
+        if offsets is not None:
+            offs = _arr(offsets, np.int64)
+            need = int((offs + sizes).max()) if self.B else 0
+        else:
+            need = int(sizes.sum())
+        if state.numel() < need:
+            raise ValueError("state holds %d elements, the solves need %d" % (state.numel(), need))
+        self._offs = offs
+        _check(lib().cil_sim_plan_create(model, _prec(state), ctypes.cast(problems, ctypes.c_void_p), self.B,
+                                         _dev(state, "state"), None if offs is None else offs.ctypes.data,
+                                         ctypes.byref(stp), _stream(state), ctypes.byref(self._h)))
+
+    def tune(self, steps: int = 100):
+        """Autotune the code shape per grid side; returns group_info()."""
+        _check(lib().cil_sim_plan_tune(self._h, int(steps), _stream(self.state)))
+        return self.group_info()
+
+    def group_info(self):
+        out = []
+        for g in range(_nonneg(lib().cil_sim_plan_groups(self._h))):
+            n, c, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            ms = (ctypes.c_double * CIL_QUAD_SHAPES)()
+            _check(lib().cil_sim_plan_group_info(self._h, g, ctypes.byref(n), ctypes.byref(c), ctypes.byref(s), ms))
+            out.append(dict(n=n.value, count=c.value, shape=s.value, tuned_ms=list(ms)))
+        return out
+
+    def launch(self):
+        _check(lib().cil_sim_plan_launch(self._h, _stream(self.state)))
+
+    def report(self, raise_on_nonfinite: bool = True):
+        reps = (SolveReport * self.B)()
+        rc = lib().cil_sim_plan_report(self._h, ctypes.cast(reps, ctypes.c_void_p), _stream(self.state))
+        out = dict(steps_taken=np.array([r.steps_taken for r in reps], dtype=np.int64),
+                   final_resid=np.array([r.final_resid for r in reps]),
+                   status=np.array([r.status for r in reps], dtype=np.int32))
+        if rc == CIL_ENONFINITE and not raise_on_nonfinite:
+            return out
+        _check(rc)
+        return out
+
+    def close(self):
+        if self._h:
+            _check(lib().cil_sim_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _nonneg(rc: int) -> int:
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 # ------------------------------------------------------- CIL statistic

@@ -170,6 +170,13 @@ ProfMark prof_begin(const char *name, hipStream_t st)
 {
     ProfMark m;
     if (!g_prof_on) return m;
+    // a stream being captured into a graph gets no timing events
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return m;
+    }
+    if (cs != hipStreamCaptureStatusNone) return m;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     hipEvent_t a = take_event(), b = take_event();
     if (!a || !b) return m;
@@ -332,6 +339,83 @@ int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem
         return CIL_OK;
     }
     return simulate_impl(model, prec, probs, B, state, elem_offsets, stepping, reports, (hipStream_t)hip_stream);
+}
+
+// plan handles are cil::SimPlan objects behind the opaque C type
+static cil::SimPlan *as_plan(cil_sim_plan *p) { return reinterpret_cast<cil::SimPlan *>(p); }
+static const cil::SimPlan *as_cplan(const cil_sim_plan *p) { return reinterpret_cast<const cil::SimPlan *>(p); }
+
+int cil_sim_plan_create(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B, void *state,
+                        const int64_t *elem_offsets, const cil_stepping *stepping, void *hip_stream,
+                        cil_sim_plan **plan)
+{
+    API_BEGIN();
+    if (!plan) return set_error(CIL_EINVAL, "null plan pointer");
+    *plan = nullptr;
+    if ((int)model < CIL_FHN || (int)model > CIL_HEAT) return set_error(CIL_EINVAL, "unknown model %d", (int)model);
+    if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
+    if (B < 1) return set_error(CIL_EINVAL, "a plan needs B >= 1");
+    if (!probs || !state || !stepping) return set_error(CIL_EINVAL, "null pointer");
+    if (!(stepping->dt > 0.0) || !std::isfinite(stepping->dt)) return set_error(CIL_EINVAL, "dt must be > 0");
+    if (stepping->max_steps < 0) return set_error(CIL_EINVAL, "max_steps < 0");
+    if (stepping->check_every < 1) return set_error(CIL_EINVAL, "check_every < 1");
+    if (stepping->path < CIL_PATH_AUTO || stepping->path > CIL_PATH_FUSED_QUAD)
+        return set_error(CIL_EINVAL, "unknown path");
+    for (int b = 0; b < B; ++b) {
+        const cil_problem &p = probs[b];
+        if (p.n < 2 || p.n > 4096) return set_error(CIL_EINVAL, "solve %d: n = %d out of range [2, 4096]", b, p.n);
+        if (!(p.L > 0.0) || !std::isfinite(p.L)) return set_error(CIL_EINVAL, "solve %d: L must be > 0", b);
+        if (!(p.nu[0] >= 0.0) || !(p.nu[1] >= 0.0)) return set_error(CIL_EINVAL, "solve %d: nu must be >= 0", b);
+        if (elem_offsets && elem_offsets[b] < 0) return set_error(CIL_EINVAL, "solve %d: negative offset", b);
+    }
+    CIL_TRY(check_device());
+    cil::SimPlan *p = nullptr;
+    CIL_TRY(plan_create(model, prec, probs, B, state, elem_offsets, stepping, (hipStream_t)hip_stream, &p));
+    *plan = reinterpret_cast<cil_sim_plan *>(p);
+    return CIL_OK;
+}
+
+int cil_sim_plan_tune(cil_sim_plan *plan, int64_t steps, void *hip_stream)
+{
+    API_BEGIN();
+    if (!plan) return set_error(CIL_EINVAL, "null plan");
+    return plan_tune(as_plan(plan), steps, (hipStream_t)hip_stream);
+}
+
+int cil_sim_plan_launch(cil_sim_plan *plan, void *hip_stream)
+{
+    API_BEGIN();
+    if (!plan) return set_error(CIL_EINVAL, "null plan");
+    return plan_launch(as_plan(plan), (hipStream_t)hip_stream);
+}
+
+int cil_sim_plan_report(cil_sim_plan *plan, cil_solve_report *reports, void *hip_stream)
+{
+    API_BEGIN();
+    if (!plan) return set_error(CIL_EINVAL, "null plan");
+    return plan_report(as_plan(plan), reports, (hipStream_t)hip_stream);
+}
+
+int cil_sim_plan_groups(const cil_sim_plan *plan)
+{
+    API_BEGIN();
+    if (!plan) return set_error(CIL_EINVAL, "null plan");
+    return plan_groups(as_cplan(plan));
+}
+
+int cil_sim_plan_group_info(const cil_sim_plan *plan, int32_t group, int32_t *n, int32_t *count, int32_t *shape,
+                            double *tuned_ms)
+{
+    API_BEGIN();
+    if (!plan) return set_error(CIL_EINVAL, "null plan");
+    return plan_group_info(as_cplan(plan), group, n, count, shape, tuned_ms);
+}
+
+int cil_sim_plan_destroy(cil_sim_plan *plan)
+{
+    API_BEGIN();
+    plan_destroy(as_plan(plan));
+    return CIL_OK;
 }
 
 static int check_sets(const void *A, int64_t nA, const void *B, int64_t nB, int64_t dim, cil_precision prec)

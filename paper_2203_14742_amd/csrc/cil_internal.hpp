@@ -111,6 +111,17 @@ constexpr double ce_cospi(long p, long q)
 
 constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
 
+// Simulate plans (stepper.hip): a batch of fused solves bound to one graph.
+struct SimPlan;
+int plan_create(cil_model model, cil_precision prec, const cil_problem *probs, int B, void *state, const int64_t *offs,
+                const cil_stepping *stp, hipStream_t st, SimPlan **out);
+int plan_tune(SimPlan *p, int64_t steps, hipStream_t st);
+int plan_launch(SimPlan *p, hipStream_t st);
+int plan_report(SimPlan *p, cil_solve_report *reports, hipStream_t st);
+int plan_groups(const SimPlan *p);
+int plan_group_info(const SimPlan *p, int g, int *n, int *count, int *shape, double *tuned_ms);
+void plan_destroy(SimPlan *p);
+
 // Radii ladder from a squared-distance range (host; shared by cil_radii and the
 // adaptive counting call so both give the same doubles).
 int radii_ladder(double d2min, double d2max, int M, int law, double *radii);

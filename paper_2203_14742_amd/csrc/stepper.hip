@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <vector>
 
@@ -939,6 +940,298 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     }
     if (rc == CIL_ENONFINITE) set_error(rc, "a solve produced a non-finite value");
     return rc;
+}
+
+// ------------------------------------------------------------------ plans
+// A simulate plan binds one batch of fused solves (problems, layout,
+// stepping, the state buffer) to device-resident spectral tables, solve
+// descriptors and per-solve result arrays, and to one instantiated HIP graph:
+// a clear of the results, then one persistent kernel per grid side, forked
+// over plan-owned streams (default priority) and joined.  Each launch replays
+// the graph: every solve starts at step 0 from what the state holds.
+struct SimPlan {
+    struct Group {
+        int n = 0;
+        std::vector<int> ids;
+        int shape = 0;
+        void *tab[2] = {nullptr, nullptr};    // X-form, V-form divisor tables
+        int *dl = nullptr;
+        double tuned_ms[kQuadShapes] = {};
+    };
+    int dev = 0;
+    int model = 0;
+    bool f32 = false, quad = true;
+    double dt = 0.0;
+    PersistArgs pa{};
+    void *state = nullptr;
+    size_t state_bytes = 0;
+    int B = 0;
+    std::vector<DevSolve> hs;
+    std::vector<Group> groups;            // launch order: most expensive first
+    CallBuffers bufs;
+    DevSolve *dS = nullptr;
+    std::vector<hipStream_t> st;          // st[0] captures; st[g] runs group g
+    std::vector<hipEvent_t> ev;           // ev[0] fork, ev[g] join of group g
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~SimPlan()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipStream_t s : st) (void)hipStreamDestroy(s);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+// tables of group g for the divisor form of `shape` (built once per form)
+int plan_tables(SimPlan &p, SimPlan::Group &g, int shape, hipStream_t st)
+{
+    const int vf = (p.quad && kQuadShape[shape].vform) ? 1 : 0;
+    if (g.tab[vf]) return CIL_OK;
+    SimCtx c;
+    c.model = p.model;
+    c.dt = p.dt;
+    c.st = st;
+    c.cb = &p.bufs;
+    if (p.f32) CIL_TRY(make_tables<float>(c, g.n, g.ids, p.hs, &g.tab[vf], vf != 0));
+    else CIL_TRY(make_tables<double>(c, g.n, g.ids, p.hs, &g.tab[vf], vf != 0));
+    // the table index of each solve depends only on (h, nu) order within the
+    // group, the same for both forms; descriptors are re-sent after a build
+    CIL_HIP(hipMemcpyAsync(p.dS, p.hs.data(), sizeof(DevSolve) * p.B, hipMemcpyHostToDevice, st));
+    return CIL_OK;
+}
+
+int plan_launch_group(SimPlan &p, SimPlan::Group &g, int shape, void *state, const PersistArgs &pa, hipStream_t st)
+{
+    const int vf = (p.quad && kQuadShape[shape].vform) ? 1 : 0;
+    if (p.f32)
+        return launch_persistent<float>(g.n, p.quad, shape, (int)g.ids.size(), p.dS, g.dl, (float *)state,
+                                        (const float *)g.tab[vf], p.model, p.dt, pa, st);
+    return launch_persistent<double>(g.n, p.quad, shape, (int)g.ids.size(), p.dS, g.dl, (double *)state,
+                                     (const double *)g.tab[vf], p.model, p.dt, pa, st);
+}
+
+// the graph's work, enqueued on the capturing stream p.st[0]
+int plan_enqueue(SimPlan &p)
+{
+    hipStream_t cs = p.st[0];
+    CIL_TRY(fill_zero(p.pa.steps, sizeof(long long) * p.B, cs));
+    CIL_TRY(fill_zero(p.pa.resid, sizeof(double) * p.B, cs));
+    CIL_TRY(fill_zero(p.pa.status, sizeof(int) * p.B, cs));
+    const int ng = (int)p.groups.size();
+    if (ng > 1) CIL_HIP(hipEventRecord(p.ev[0], cs));
+    for (int g = 1; g < ng; ++g) CIL_HIP(hipStreamWaitEvent(p.st[g], p.ev[0], 0));
+    for (int g = 0; g < ng; ++g) CIL_TRY(plan_launch_group(p, p.groups[g], p.groups[g].shape, p.state, p.pa, p.st[g]));
+    for (int g = 1; g < ng; ++g) {
+        CIL_HIP(hipEventRecord(p.ev[g], p.st[g]));
+        CIL_HIP(hipStreamWaitEvent(cs, p.ev[g], 0));
+    }
+    return CIL_OK;
+}
+
+int plan_build_graph(SimPlan &p)
+{
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    p.exec = nullptr;
+    p.graph = nullptr;
+    CIL_HIP(hipStreamBeginCapture(p.st[0], hipStreamCaptureModeThreadLocal));
+    const int rc = plan_enqueue(p);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p.st[0], &g);
+    if (rc != CIL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return set_error(CIL_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    p.graph = g;
+    CIL_HIP(hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0));
+    return CIL_OK;
+}
+
+}  // namespace
+
+int plan_create(cil_model model, cil_precision prec, const cil_problem *probs, int B, void *state, const int64_t *offs,
+                const cil_stepping *stp, hipStream_t st, SimPlan **out)
+{
+    const bool f32 = (prec == CIL_FP32);
+    if (stp->path == CIL_PATH_PLAIN) return set_error(CIL_EUNSUPPORTED, "plans run the fused steppers only");
+    if (f32 && stp->polish && stp->tol > 0.0)
+        return set_error(CIL_EINVAL, "plans do not polish in FP64: set polish = 0 (FP32 floor is then a status)");
+    std::unique_ptr<SimPlan> p(new SimPlan());
+    CIL_TRY(current_device(&p->dev));
+    p->model = (int)model;
+    p->f32 = f32;
+    p->quad = stp->path != CIL_PATH_FUSED_LINE;
+    p->dt = stp->dt;
+    p->state = state;
+    p->B = B;
+    p->hs.resize(B);
+    int64_t total = 0, end = 0;
+    std::map<int, std::vector<int>> byn;
+    for (int b = 0; b < B; ++b) {
+        const cil_problem &pr = probs[b];
+        if (!fused_supported(pr.n, f32))
+            return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", pr.n, f32 ? "FP32" : "FP64");
+        DevSolve d{};
+        d.n = pr.n;
+        d.off = offs ? offs[b] : total;
+        const double h = pr.L / (double)(pr.n - 1);
+        d.inv_h2 = 1.0 / (h * h);
+        d.nu[0] = pr.nu[0];
+        d.nu[1] = pr.nu[1];
+        for (int k = 0; k < 4; ++k) d.p[k] = pr.p[k];
+        p->hs[b] = d;
+        total += 2ll * pr.n * pr.n;
+        end = std::max<int64_t>(end, d.off + 2ll * pr.n * pr.n);
+        byn[pr.n].push_back(b);
+    }
+    p->state_bytes = (size_t)end * (f32 ? 4 : 8);
+    std::vector<std::pair<double, int>> order;
+    for (auto &kv : byn) order.push_back({-(double)kv.first * kv.first * std::log2((double)kv.first) * kv.second.size(),
+                                          kv.first});
+    std::sort(order.begin(), order.end());
+    CIL_TRY(p->bufs.alloc((void **)&p->dS, sizeof(DevSolve) * B));
+    long long *dsteps;
+    double *dres;
+    int *dstat;
+    CIL_TRY(p->bufs.alloc((void **)&dsteps, sizeof(long long) * B));
+    CIL_TRY(p->bufs.alloc((void **)&dres, sizeof(double) * B));
+    CIL_TRY(p->bufs.alloc((void **)&dstat, sizeof(int) * B));
+    const double floor_coef =
+        (f32 && stp->tol > 0.0) ? (stp->fp32_floor_ulps > 0 ? stp->fp32_floor_ulps : 8) * std::ldexp(1.0, -24) / stp->dt
+                                : 0.0;
+    p->pa = PersistArgs{(long long)stp->max_steps, stp->tol, stp->check_every, floor_coef, dsteps, dres, dstat};
+    CIL_HIP(hipMemcpyAsync(p->dS, p->hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
+    for (auto &o : order) {
+        SimPlan::Group g;
+        g.n = o.second;
+        g.ids = byn[g.n];
+        g.shape = p->quad ? quad_shape(f32, g.n) : 0;
+        CIL_TRY(p->bufs.alloc((void **)&g.dl, sizeof(int) * g.ids.size()));
+        CIL_HIP(hipMemcpyAsync(g.dl, g.ids.data(), sizeof(int) * g.ids.size(), hipMemcpyHostToDevice, st));
+        p->groups.push_back(g);
+    }
+    for (auto &g : p->groups) CIL_TRY(plan_tables(*p, g, g.shape, st));
+    const int ng = (int)p->groups.size();
+    for (int g = 0; g < std::max(ng, 1); ++g) {
+        hipStream_t s;
+        CIL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        p->st.push_back(s);
+        hipEvent_t e;
+        CIL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->ev.push_back(e);
+    }
+    CIL_HIP(hipStreamSynchronize(st));     // uploads done before capture and before host vectors go
+    CIL_TRY(plan_build_graph(*p));
+    *out = p.release();
+    return CIL_OK;
+}
+
+int plan_tune(SimPlan *p, int64_t steps, hipStream_t st)
+{
+    if (!p->quad) return set_error(CIL_EINVAL, "tuning chooses among the quad-lane shapes (path is FUSED_LINE)");
+    if (steps < 0) return set_error(CIL_EINVAL, "tuning needs steps >= 0");
+    CIL_HIP(hipSetDevice(p->dev));
+    CallBuffers tb;
+    void *scratch;
+    long long *tsteps;
+    double *tres;
+    int *tstat;
+    CIL_TRY(tb.alloc(&scratch, p->state_bytes));
+    CIL_TRY(tb.alloc((void **)&tsteps, sizeof(long long) * p->B));
+    CIL_TRY(tb.alloc((void **)&tres, sizeof(double) * p->B));
+    CIL_TRY(tb.alloc((void **)&tstat, sizeof(int) * p->B));
+    // steps > 0: fixed-length trials (no stop rule); 0: the plan's own stepping
+    const PersistArgs pa = steps > 0 ? PersistArgs{(long long)steps, 0.0, (int)std::min<int64_t>(steps, 1 << 30), 0.0,
+                                                   tsteps, tres, tstat}
+                                     : PersistArgs{p->pa.max_steps, p->pa.tol, p->pa.check, p->pa.floor_coef, tsteps,
+                                                   tres, tstat};
+    hipEvent_t a, b;
+    CIL_HIP(hipEventCreate(&a));
+    CIL_HIP(hipEventCreate(&b));
+    int rc = CIL_OK;
+    for (auto &g : p->groups) {
+        int best = -1;
+        for (int s = 0; s < kQuadShapes && rc == CIL_OK; ++s) {
+            rc = plan_tables(*p, g, s, st);
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && rc == CIL_OK; ++rep) {
+                // every trial starts from the same states (a copy of the bound state)
+                if (hipMemcpyAsync(scratch, p->state, p->state_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                    (rc = fill_zero(tsteps, sizeof(long long) * p->B, st)) != CIL_OK ||
+                    hipEventRecord(a, st) != hipSuccess) {
+                    if (rc == CIL_OK) rc = set_error(CIL_EDEVICE, "tuning copy failed");
+                    break;
+                }
+                rc = plan_launch_group(*p, g, s, scratch, pa, st);
+                if (rc == CIL_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                                     hipEventElapsedTime(&ms, a, b) != hipSuccess))
+                    rc = set_error(CIL_EDEVICE, "tuning timing failed");
+            }
+            if (rc != CIL_OK) break;
+            g.tuned_ms[s] = ms;
+            if (best < 0 || ms < g.tuned_ms[best]) best = s;
+        }
+        if (rc != CIL_OK) break;
+        g.shape = best;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    CIL_TRY(rc);
+    CIL_HIP(hipStreamSynchronize(st));
+    return plan_build_graph(*p);
+}
+
+int plan_launch(SimPlan *p, hipStream_t st)
+{
+    const ProfMark pm = prof_begin("sim_plan_graph", st);
+    CIL_HIP(hipGraphLaunch(p->exec, st));
+    prof_end(pm, st);
+    return CIL_OK;
+}
+
+int plan_report(SimPlan *p, cil_solve_report *reports, hipStream_t st)
+{
+    const int B = p->B;
+    std::vector<long long> hsteps(B);
+    std::vector<double> hres(B);
+    std::vector<int> hstat(B);
+    CIL_HIP(hipMemcpyAsync(hsteps.data(), p->pa.steps, sizeof(long long) * B, hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(hres.data(), p->pa.resid, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(hstat.data(), p->pa.status, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipStreamSynchronize(st));
+    int rc = CIL_OK;
+    for (int b = 0; b < B; ++b) {
+        if (hstat[b] == CIL_SOLVE_NONFINITE) rc = CIL_ENONFINITE;
+        if (reports) reports[b] = cil_solve_report{hsteps[b], 0, hres[b], hstat[b], 0};
+    }
+    if (rc == CIL_ENONFINITE) set_error(rc, "a solve produced a non-finite value");
+    return rc;
+}
+
+int plan_groups(const SimPlan *p) { return (int)p->groups.size(); }
+
+int plan_group_info(const SimPlan *p, int g, int *n, int *count, int *shape, double *tuned_ms)
+{
+    if (g < 0 || g >= (int)p->groups.size()) return set_error(CIL_EINVAL, "group %d out of range", g);
+    const SimPlan::Group &G = p->groups[g];
+    if (n) *n = G.n;
+    if (count) *count = (int)G.ids.size();
+    if (shape) *shape = G.shape;
+    if (tuned_ms)
+        for (int s = 0; s < kQuadShapes; ++s) tuned_ms[s] = G.tuned_ms[s];
+    return CIL_OK;
+}
+
+void plan_destroy(SimPlan *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->dev);
+    (void)hipDeviceSynchronize();
+    delete p;
 }
 
 }  // namespace cil

@@ -1,0 +1,80 @@
+"""Feature mean and covariance of the batched FP32 path against the FP64
+oracle after stationarity (the statistic behind the Gaussian synthetic
+likelihood, eqs. cil:CF and cil:CF_synth).
+
+128 Gierer-Meinhardt (source form) solves on 64x64 grids with the benchmarked
+parameters: the oracle runs them in FP64 to residual < 1e-8; the GPU path
+steps in FP32, either with the FP64 polish to the same residual or stopped at
+the FP32 floor (no polish).  Both sides then take the correlation integral
+vectors of the same 200 resamples (Alg. 2bst halves of 64) under the same 13
+radii (fitted to the oracle's distance range); the GPU side on its FP32
+patterns through the bins and the bootstrap kernels.  The sample mean of the
+vectors must agree within 2 % (relative, Euclidean norm) and the sample
+covariance within 2 % (relative, Frobenius norm).  Per radius, a bin holding
+a few dozen pairs moves by 1/(its pair count) when one pattern lands on a
+neighbouring stationary state, so the bar is taken over the whole vector.
+"""
+import numpy as np
+import pytest
+
+import cil_synth as cs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+COUNT, SEED, BOOT_SEED = 128, 31, 32
+
+
+@pytest.fixture(scope="module")
+def cil():
+    import paper_2203_14742_amd as c
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return c
+
+
+@pytest.fixture(scope="module")
+def reference(oracle_mod):
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    base = oracle_mod.homogeneous_state(w["model"], w["params"])
+    ics = cs.initial_conditions(base, w["n"], COUNT, seed=SEED, law=w["ic_law"])
+    print("oracle: %d GM-source solves to stationarity" % COUNT, flush=True)
+    out, _, res, stat = oracle_mod.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], w["max_steps"],
+                                            w["tol"], w["check_every"], state=ics.copy(), nthreads=16)
+    assert np.all(stat == 0) and np.all(res < w["tol"])
+    half, d = COUNT // 2, 2 * w["n"] ** 2
+    P = out.reshape(COUNT, d)
+    D = oracle_mod.pair_d2(P[:half], P[half:], nthreads=16)
+    radii = oracle_mod.radii_ladder(D.min(), D.max(), w["M"])
+    ia, ib = cs.resample_halves(half, half, half, half, w["n_boot"], seed=BOOT_SEED)
+    _, Y = oracle_mod.bootstrap_vectors(D, ia, ib, radii, nthreads=16)
+    mu, S = oracle_mod.mean_cov(Y)
+    return dict(w=w, ics=ics, out=P, radii=radii, ia=ia, ib=ib, mu=mu, S=S)
+
+
+@pytest.mark.parametrize("polish", [1, 0])
+def test_fp32_feature_moments_within_two_percent(cil, oracle_mod, reference, polish):
+    w = reference["w"]
+    st = torch.tensor(reference["ics"], dtype=torch.float32, device="cuda")
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=COUNT)
+    print("FP32 stepping, polish=%d" % polish, flush=True)
+    rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                    check_every=w["check_every"], polish=polish)
+    want = cil.CIL_SOLVE_OK if polish else cil.CIL_SOLVE_FP32_FLOOR
+    assert np.all(rep["status"] == want)
+    half = COUNT // 2
+    P = st.reshape(COUNT, -1)
+    bins, _ = cil.cil_pair_bins(P[:half], P[half:], reference["radii"])
+    _, Y = cil.cil_bootstrap_features(bins, torch.from_numpy(reference["ia"]), torch.from_numpy(reference["ib"]),
+                                      len(reference["radii"]))
+    mu, S = oracle_mod.mean_cov(Y.cpu().numpy())
+    mu0, S0 = reference["mu"], reference["S"]
+    rel_mu = np.linalg.norm(mu - mu0) / np.linalg.norm(mu0)
+    rel_S = np.linalg.norm(S - S0) / np.linalg.norm(S0)
+    pos = mu0 > 0.0
+    per_radius = np.abs(mu[pos] - mu0[pos]) / mu0[pos]
+    far = np.abs(P.double().cpu().numpy() - reference["out"]).max(axis=1) / np.abs(reference["out"]).max(axis=1)
+    print("polish=%d: rel mean dev %.3e (per radius max %.3e), rel cov dev %.3e; solves off the oracle's "
+          "pattern by > 1e-3: %d of %d" % (polish, rel_mu, per_radius.max(), rel_S, int((far > 1e-3).sum()), COUNT))
+    assert rel_mu <= 0.02
+    assert rel_S <= 0.02
