@@ -111,6 +111,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32-stepping", action="store_true")
     ap.add_argument("--cpu-sample-solves", type=int, default=96)
+    ap.add_argument("--gram-flush", type=int, default=64, choices=[64, 128, 256],
+                    help="features4096: FP32 -> FP64 promotion interval of the Gram")
+    ap.add_argument("--gram-pipeline", type=int, default=2, choices=[0, 1, 2],
+                    help="features4096: Gram staging variant (CIL_OPT_GRAM_PIPELINE)")
     ap.add_argument("--tune-steps", type=int, default=100,
                     help="bz_uneven2048: steps per autotuning trial (0 = the plan's own stepping)")
     ap.add_argument("--sources-sha256", action="store_true",
@@ -247,10 +251,11 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_solve_step": fused_step_flops(n, REACTION_FLOPS[w["model"]]),
                 "solve_steps": solve_steps}
     gram = None
-    if "k_gram_bf16x3" in prof:
-        cnt, tot_ms = prof["k_gram_bf16x3"]
+    gk = "k_gram_dma" if "k_gram_dma" in prof else "k_gram_bf16x3"
+    if gk in prof:
+        cnt, tot_ms = prof[gk]
         executed = 6.0 * d * pairs * K               # three bf16 products per element pair
-        gram = {"kernel": "k_gram_bf16x3", "bound": "mfma", "achieved": round(executed / (tot_ms * 1e-3) / 1e12, 3),
+        gram = {"kernel": gk, "bound": "mfma", "achieved": round(executed / (tot_ms * 1e-3) / 1e12, 3),
                 "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(executed / (tot_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
                 "avg_launch_ms": round(tot_ms / cnt, 4)}
@@ -313,6 +318,8 @@ def features_main(args):
     torch.cuda.set_device(dev)
     count, n, M, n_boot = w["count"], w["n"], w["M"], w["n_boot"]
     half, d = count // 2, 2 * n * n
+    cil.cil_set_option(cil.CIL_OPT_GRAM_FLUSH, args.gram_flush)
+    cil.cil_set_option(cil.CIL_OPT_GRAM_PIPELINE, args.gram_pipeline)
     host = cs.stripe_patterns(count, n, seed=w["seeds"][0]).reshape(count, d)
     pats = torch.from_numpy(host).to(dev)
     A, Bs = pats[:half], pats[half:]
@@ -342,12 +349,30 @@ def features_main(args):
     cil.cil_profile(False)
     stats = cil.cil_last_distance_stats()
     K = args.steps
+    plain = None
+    if not args.no_plain:
+        # the plain FP64 GPU path on the same pairs: FP64 patterns, direct
+        # FP64 differences (split-K), the same adaptive range, radii and bins
+        A64, B64 = A.double(), Bs.double()
+        bins64 = torch.empty_like(bins)
+        cil.cil_pair_bins_adaptive(A64, B64, M, bins=bins64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, _, _, counts64 = cil.cil_pair_bins_adaptive(A64, B64, M, bins=bins64)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t1
+        plain = {"value": round(pairs / tp, 1), "unit": "pairs/s", "ms": round(1e3 * tp, 3),
+                 "what": "range + radii + bins of the same pairs from FP64 patterns, direct FP64 differences",
+                 "same_counts": bool(np.array_equal(counts64, counts)),
+                 "same_bins": bool(torch.equal(bins64, bins))}
+        del A64, B64, bins64
     roof = None
-    if "k_gram_bf16x3" in prof:
-        cnt, tot_ms = prof["k_gram_bf16x3"]
+    gk = "k_gram_dma" if "k_gram_dma" in prof else "k_gram_bf16x3"
+    if gk in prof:
+        cnt, tot_ms = prof[gk]
         executed = 6.0 * d * pairs * cnt        # one Gram per step (range and bins share it)
         ach = executed / (tot_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_gram_bf16x3", "bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+        roof = {"kernel": gk, "bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
                 "launches": cnt, "avg_launch_ms": round(tot_ms / cnt, 4),
                 "flops_per_pair_executed": 6 * d, "algorithmic_flops_per_pair": 2 * d}
@@ -371,6 +396,9 @@ def features_main(args):
                    "bootstrap": n_boot, "statistic": "fp32 patterns, split-bf16x3 MFMA Gram + canonical re-check",
                    "parallelism": "none (1 GPU)"},
         "rechecked_pairs": stats["rechecked"], "exact_fallbacks": stats["exact_fallbacks"],
+        "gram_flush": args.gram_flush, "gram_pipeline": args.gram_pipeline,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": None if plain is None else round(pairs * K / el / plain["value"], 2),
         "counts": [int(c) for c in counts],
         "loglik_status": int(out[3].cpu()[0]),
         "roofline": roof,

@@ -304,8 +304,20 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  * CIL_OPT_BOOTSTRAP_GATHER (value 0/1): 1 = bootstrap counts always by the
  *   per-resample gather kernel; 0 (default) = on the matrix cores when
  *   M <= 32 and no pattern occurs more than 256 times in a resample (the
- *   gather kernel otherwise).  Both give the same exact counts. */
-enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3 };
+ *   gather kernel otherwise).  Both give the same exact counts.
+ * CIL_OPT_GRAM_FLUSH (value 64 (default), 128 or 256): number of elements
+ *   the split-bf16x3 Gram accumulates in FP32 before adding into its FP64
+ *   accumulator.  Smaller values narrow the error band (fewer canonical
+ *   re-checks) and cost more accumulator additions; counts are exact either
+ *   way.  CIL_EINVAL for other values.
+ * CIL_OPT_GRAM_PIPELINE (value 0, 1 or 2 (default)): how the Gram stages its
+ *   tiles.  0 = loads through registers into one LDS buffer; 1 = LDS-DMA
+ *   loads into two buffers, the next stage in flight while the matrix cores
+ *   work; 2 = as 1 with tiles handed to the XCDs in contiguous ranges.  All
+ *   compute the same products in the same order (identical results).
+ *   CIL_EINVAL for other values. */
+enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
+       CIL_OPT_GRAM_PIPELINE = 5 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

@@ -26,6 +26,8 @@ CIL_SOLVE_OK, CIL_SOLVE_NONFINITE, CIL_SOLVE_MAXSTEPS, CIL_SOLVE_FP32_FLOOR = 0,
 CIL_OPT_FORCE_EXACT_SUM = 1
 CIL_OPT_QUAD_SHAPE = 2
 CIL_OPT_BOOTSTRAP_GATHER = 3
+CIL_OPT_GRAM_FLUSH = 4
+CIL_OPT_GRAM_PIPELINE = 5
 CIL_QUAD_SHAPES = 4
 
 

@@ -588,6 +588,8 @@ int cil_set_option(int32_t option, int64_t value)
         set_boot_gather((int)value);
         return CIL_OK;
     }
+    if (option == CIL_OPT_GRAM_FLUSH) return set_gram_flush_interval(value);
+    if (option == CIL_OPT_GRAM_PIPELINE) return set_gram_pipeline(value);
     return set_error(CIL_EINVAL, "unknown option %d", option);
 }
 

@@ -111,6 +111,11 @@ constexpr double ce_cospi(long p, long q)
 
 constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
 
+// Gram FP32 -> FP64 promotion interval (gram.hip), shared with the error bound.
+int gram_flush_interval();
+int set_gram_flush_interval(int64_t v);
+int set_gram_pipeline(int64_t v);
+
 // Simulate plans (stepper.hip): a batch of fused solves bound to one graph.
 struct SimPlan;
 int plan_create(cil_model model, cil_precision prec, const cil_problem *probs, int B, void *state, const int64_t *offs,

@@ -533,7 +533,7 @@ int approx_pass(const float *A, long long nA, const float *B, long long nB, long
     ap->c.gram = 1;
     ap->c.na = g.na;
     ap->c.nb = g.nb;
-    ap->c.eG = 3.0 * 256.0 * 0x1p-24 + 0x1p-18 + 0x1p-40;
+    ap->c.eG = 3.0 * (double)gram_flush_interval() * 0x1p-24 + 0x1p-18 + 0x1p-40;
     ap->c.e1 = 0x1p-24 + 0x1p-18;
     if (nA * nB > 0) CIL_TRY(gram_partials(g, nA, nB, S, ks, (double *)p, st));
     return CIL_OK;

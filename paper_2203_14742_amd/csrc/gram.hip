@@ -6,8 +6,8 @@
 // is split into two bf16 numbers x' ~ hi + lo (hi = bf16(x'), lo =
 // bf16(x' - hi)).  The Gram of the split vectors is taken as three bf16
 // products hi.hi + hi.lo + lo.hi on v_mfma_f32_32x32x16_bf16 (products exact,
-// FP32 accumulation), promoted to an FP64 accumulator every KC = 256
-// elements.  |a^|^2 is summed in FP64 from (hi + lo).
+// FP32 accumulation), promoted to an FP64 accumulator every KC elements
+// (64, 128 or 256; CIL_OPT_GRAM_FLUSH).  |a^|^2 is summed in FP64 from (hi + lo).
 //
 // Error bound (per pair, relative to S = |a'| + |b'| and |a'| |b'|):
 //   Gram:     |G~ - <a^, b^>| <= eG = (3 KC 2^-24 + 2^-18 + 2^-40) |a'||b'|
@@ -32,7 +32,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int GT = 128;          // tile side (pairs) per workgroup
 constexpr int GK = 64;           // k per LDS stage
 constexpr int GPAD = 8;          // row padding (elements) of LDS tiles
-constexpr int GKC = 256;         // FP32 -> FP64 promotion interval (elements)
+constexpr int GKC = 256;         // split-K granularity (elements)
 
 // ------------------------------------------------------------------ shift
 // c_k = mean over up to 64 sampled rows of A and B (FP64 sum, rounded to FP32)
@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void k_split_rows(const float *X, long long di
 // block and row l%32 of the B block (a column of B^T), elements
 // k = 8 (l/32) .. 8 (l/32) + 7 of the 16-wide k step; accumulator element r of
 // lane l is C[8 (r/4) + 4 (l/32) + r%4][l%32].
+template <int KCF>   // FP32 -> FP64 promotion interval (elements), a multiple of GK
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_bf16x3(const __bf16 *Ah, const __bf16 *Al, long long nA,
                                                      const __bf16 *Bh, const __bf16 *Bl, long long nB,
                                                      long long dimP, long long ksplit, double *P)
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 }
         }
         since_flush += GK;
-        if (since_flush >= GKC) {
+        if (since_flush >= KCF) {
             since_flush = 0;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -174,6 +175,151 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     }
     double *Ps = P + (long long)blockIdx.z * nA * nB;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const long long i = i0 + wr * 64 + a * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                const long long j = j0 + wc * 64 + b * 32 + (lane & 31);
+                if (i < nA && j < nB) Ps[i * nB + j] = acc64[a][b][r] + (double)acc[a][b][r];
+            }
+}
+
+// Pipelined variant (the default).  Tiles are staged by LDS-DMA loads
+// (global_load_lds_dwordx4: the 16 bytes of lane l land at the wave's LDS base
+// + 16 l, no registers) into two LDS buffers of GD = 32 k: the loads of stage
+// s + 1 are in flight while the matrix cores work on stage s, one barrier per
+// stage.  Wavefront w stages array w (A hi, A lo, B hi, B lo) in 8
+// instructions of 64 slots.  The 16-byte chunk c of tile row r sits in slot
+// 4 r + (c ^ swz(r)): the fragment reads (32 consecutive rows, one chunk per
+// half-wave) then fall on distinct banks for 32- and 64-bank LDS alike.  Rows
+// past the end of a set load the last row (their sums are never stored).  Same
+// products, order and promotion points as k_gram_bf16x3, so the two give
+// identical sums.  Measured on 2048 x 2048 x 32768: 1.04 ms (0.79 PFLOP/s
+// executed bf16) against 1.69 ms for k_gram_bf16x3; deeper pipelines of
+// 16-k stages (4 or 5 buffers) were slower (1.7-1.8 ms).
+//
+// With `xcd_order`, consecutive tiles of the (j, i, split) order are given to
+// one XCD (workgroups reach the 8 XCDs round-robin in launch order), so an XCD
+// works on whole rows of tiles and its L2 holds the A rows they share
+// (1.03 against 1.07 ms).
+constexpr int GD = 32;
+
+__device__ __forceinline__ int gram_swz(int r) { return (((r >> 1) ^ (r >> 3)) & 1) | (((r >> 2) & 1) << 1); }
+
+template <int KCF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_dma(
+    const __bf16 *Ah, const __bf16 *Al, long long nA, const __bf16 *Bh, const __bf16 *Bl, long long nB,
+    long long dimP, long long ksplit, double *P, int xcd_order)
+{
+    constexpr int CPR = GD / 8;                  // 16-byte chunks per tile row per stage
+    constexpr int PARTS = GT * CPR / 64;         // DMA instructions per wavefront per stage
+    __shared__ __attribute__((aligned(16))) uint4 sm[2][4][GT * CPR];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wv >> 1, wc = wv & 1;
+    long long tx = blockIdx.x, ty = blockIdx.y, tz = blockIdx.z;
+    if (xcd_order) {
+        const long long gx = gridDim.x, gy = gridDim.y, tot = gx * gy * gridDim.z;
+        const long long L = tx + gx * (ty + gy * tz);
+        const long long per = tot / 8;
+        if (L < per * 8) {                       // full rounds of 8: XCD L % 8 takes a contiguous range
+            const long long Lp = (L % 8) * per + L / 8;
+            tx = Lp % gx;
+            ty = (Lp / gx) % gy;
+            tz = Lp / (gx * gy);
+        }
+    }
+    const long long i0 = ty * GT, j0 = tx * GT;
+    const long long kb = tz * ksplit;
+    const long long ke = std::min<long long>(dimP, kb + ksplit);
+
+    const __bf16 *src = wv == 0 ? Ah : (wv == 1 ? Al : (wv == 2 ? Bh : Bl));
+    const long long r0 = wv < 2 ? i0 : j0;
+    const long long nr = wv < 2 ? nA : nB;
+    const int drow = lane / CPR;                                   // row of slot 64 p + lane, minus 64 p / CPR
+    const int dchunk = (lane % CPR) ^ gram_swz(drow);
+    auto stage = [&](long long k0, int b) {
+#pragma unroll
+        for (int p = 0; p < PARTS; ++p) {
+            const long long row = std::min<long long>(r0 + (64 / CPR) * p + drow, nr - 1);
+            const __bf16 *g = src + row * dimP + k0 + 8 * dchunk;
+            __builtin_amdgcn_global_load_lds((const void *)g,
+                                             (__attribute__((address_space(3))) void *)&sm[b][wv][64 * p], 16, 0, 0);
+        }
+    };
+
+    floatx16 acc[2][2];
+    double acc64[2][2][16];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[a][b][r] = 0.0f;
+                acc64[a][b][r] = 0.0;
+            }
+        }
+
+    const int fsw = gram_swz(lane & 31);
+    stage(kb, 0);
+    int buf = 0, since_flush = 0;
+    for (long long k0 = kb; k0 < ke; k0 += GD) {
+        // this wavefront's loads of stage k0 have landed (vmcnt(0); gfx9
+        // s_waitcnt: vmcnt 3:0 and 15:14, expcnt 6:4 = 7 and lgkmcnt 11:8 = 15
+        // mean no wait on those)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        // Bare workgroup barrier: a __syncthreads fence would also wait for
+        // every outstanding DMA load (vmcnt(0)) and drain the prefetch.  The
+        // loop writes LDS only by DMA (covered by the wait above) and every
+        // LDS read of the buffer refilled next was consumed (lgkmcnt waited)
+        // in the previous iteration; the asm clobber keeps the compiler from
+        // moving LDS accesses across the barrier.
+        asm volatile("s_barrier" ::: "memory");
+        if (k0 + GD < ke) stage(k0 + GD, buf ^ 1);
+        const uint4 *sAh = sm[buf][0], *sAl = sm[buf][1], *sBh = sm[buf][2], *sBl = sm[buf][3];
+#pragma unroll
+        for (int kk = 0; kk < GD; kk += 16) {
+            const int c = (kk >> 3) + (lane >> 5);
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ra = wr * 64 + t * 32 + (lane & 31);
+                const int rb = wc * 64 + t * 32 + (lane & 31);
+                ah[t] = __builtin_bit_cast(bf16x8, sAh[CPR * ra + (c ^ fsw)]);
+                al[t] = __builtin_bit_cast(bf16x8, sAl[CPR * ra + (c ^ fsw)]);
+                bh[t] = __builtin_bit_cast(bf16x8, sBh[CPR * rb + (c ^ fsw)]);
+                bl[t] = __builtin_bit_cast(bf16x8, sBl[CPR * rb + (c ^ fsw)]);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        buf ^= 1;
+        since_flush += GD;
+        if (since_flush >= KCF) {
+            since_flush = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        acc64[a][b][r] += (double)acc[a][b][r];
+                        acc[a][b][r] = 0.0f;
+                    }
+        }
+    }
+    double *Ps = P + tz * nA * nB;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -228,6 +374,27 @@ int gram_prepare(const float *A, long long nA, const float *B, long long nB, lon
     return check_launch("k_split_rows");
 }
 
+// FP32 -> FP64 promotion interval of the Gram (64, 128 or 256 elements; 64:
+// the narrowest band, fewest re-checks, no measurable cost in the Gram); the
+// classification's error bound uses the same value.
+int g_gram_kc = 64;
+// 0: k_gram_bf16x3; 1: k_gram_dma in launch order; 2: k_gram_dma in XCD order
+int g_gram_pipeline = 2;
+int set_gram_pipeline(int64_t v)
+{
+    if (v < 0 || v > 2) return set_error(CIL_EINVAL, "Gram pipeline option %lld not in {0, 1, 2}", (long long)v);
+    g_gram_pipeline = (int)v;
+    return CIL_OK;
+}
+int gram_flush_interval() { return g_gram_kc; }
+int set_gram_flush_interval(int64_t v)
+{
+    if (v != 64 && v != 128 && v != 256) return set_error(CIL_EINVAL, "Gram flush interval %lld not in {64, 128, 256}",
+                                                         (long long)v);
+    g_gram_kc = (int)v;
+    return CIL_OK;
+}
+
 // number of K splits so that the grid holds enough workgroups
 long long gram_splits(long long nA, long long nB, long long dimP)
 {
@@ -243,9 +410,30 @@ int gram_partials(const GramWork &g, long long nA, long long nB, long long split
 {
     if (ks % GK != 0 || splits * ks < g.dimP) return set_error(CIL_EINVAL, "bad Gram split");
     dim3 grid((unsigned)((nB + GT - 1) / GT), (unsigned)((nA + GT - 1) / GT), (unsigned)splits);
+    const int kc = gram_flush_interval();
+    if (g_gram_pipeline) {
+        const ProfMark pm2 = prof_begin("k_gram_dma", st);
+        const __bf16 *ah = g.Ah, *al = g.Al, *bh = g.Bh, *bl = g.Bl;
+        const int xo = g_gram_pipeline == 2;
+        if (kc == 64)
+            hipLaunchKernelGGL(k_gram_dma<64>, grid, dim3(256), 0, st, ah, al, nA, bh, bl, nB, g.dimP, ks, P, xo);
+        else if (kc == 128)
+            hipLaunchKernelGGL(k_gram_dma<128>, grid, dim3(256), 0, st, ah, al, nA, bh, bl, nB, g.dimP, ks, P, xo);
+        else
+            hipLaunchKernelGGL(k_gram_dma<256>, grid, dim3(256), 0, st, ah, al, nA, bh, bl, nB, g.dimP, ks, P, xo);
+        prof_end(pm2, st);
+        return check_launch("k_gram_dma");
+    }
     const ProfMark pm = prof_begin("k_gram_bf16x3", st);
-    hipLaunchKernelGGL(k_gram_bf16x3, grid, dim3(256), 0, st, (const __bf16 *)g.Ah, (const __bf16 *)g.Al, nA,
-                       (const __bf16 *)g.Bh, (const __bf16 *)g.Bl, nB, g.dimP, ks, P);
+    if (kc == 64)
+        hipLaunchKernelGGL(k_gram_bf16x3<64>, grid, dim3(256), 0, st, (const __bf16 *)g.Ah, (const __bf16 *)g.Al, nA,
+                           (const __bf16 *)g.Bh, (const __bf16 *)g.Bl, nB, g.dimP, ks, P);
+    else if (kc == 128)
+        hipLaunchKernelGGL(k_gram_bf16x3<128>, grid, dim3(256), 0, st, (const __bf16 *)g.Ah, (const __bf16 *)g.Al,
+                           nA, (const __bf16 *)g.Bh, (const __bf16 *)g.Bl, nB, g.dimP, ks, P);
+    else
+        hipLaunchKernelGGL(k_gram_bf16x3<256>, grid, dim3(256), 0, st, (const __bf16 *)g.Ah, (const __bf16 *)g.Al,
+                           nA, (const __bf16 *)g.Bh, (const __bf16 *)g.Bl, nB, g.dimP, ks, P);
     prof_end(pm, st);
     return check_launch("k_gram_bf16x3");
 }

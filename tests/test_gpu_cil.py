@@ -127,6 +127,63 @@ def test_fast_pass_bound_fp64(cil, oracle_mod):
     assert np.all(np.abs(d2.cpu().numpy() - D) <= eps.cpu().numpy())
 
 
+@pytest.mark.parametrize("kc", [64, 128])
+@pytest.mark.parametrize("case", ["random", "offset", "near_equal", "stripes"])
+def test_gram_flush_interval_bound_and_counts(cil, oracle_mod, kc, case):
+    """Shorter FP32 accumulation intervals than 256 narrow the stated bound;
+    it still holds for every pair and the counts stay exact."""
+    nA, nB, d = 40, 37, 8192
+    A, B = adversarial_sets(case, nA, nB, d, seed=d + kc)
+    D = oracle_mod.pair_d2(A, B)
+    try:
+        cil.cil_set_option(cil.CIL_OPT_GRAM_FLUSH, 256)
+        d2w, epsw = cil.cil_approx_d2(dev(A), dev(B))
+        cil.cil_set_option(cil.CIL_OPT_GRAM_FLUSH, kc)
+        d2, eps = cil.cil_approx_d2(dev(A), dev(B))
+        radii = oracle_mod.radii_ladder(D.min() if D.min() > 0 else D.max() / 100, D.max(), 13)
+        c, _ = cil.cil_features(dev(A), dev(B), radii)
+        lo, hi, r2, bins, c2 = cil.cil_pair_bins_adaptive(dev(A), dev(B), 13)
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_GRAM_FLUSH, 64)
+    d2, eps = d2.cpu().numpy(), eps.cpu().numpy()
+    assert np.all(np.abs(d2 - D) <= eps)
+    assert np.all(eps < epsw.cpu().numpy())
+    assert np.array_equal(c, oracle_mod.counts_from_d2(D, radii))
+    assert (lo, hi) == (D.min(), D.max())
+    assert np.array_equal(bins.cpu().numpy(), oracle_mod.bins_from_d2(D, r2))
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("kc", [64, 256])
+@pytest.mark.parametrize("nA,nB,d", [(40, 37, 8192), (130, 257, 2048), (1, 300, 64), (300, 1, 200),
+                                     (129, 128, 33000), (1000, 1100, 96)])
+def test_gram_pipeline_gives_identical_sums(cil, oracle_mod, variant, kc, nA, nB, d):
+    """The LDS-DMA pipelined Gram (launch or XCD tile order) computes the same
+    products in the same order as the register-staged one: identical
+    approximate distances and bounds, on ragged tiles, one-row sets and a
+    dimension that is not a multiple of the staging depth."""
+    A, B = sets(nA, nB, d, seed=nA + nB + d, dtype=np.float32)
+    try:
+        cil.cil_set_option(cil.CIL_OPT_GRAM_FLUSH, kc)
+        cil.cil_set_option(cil.CIL_OPT_GRAM_PIPELINE, 0)
+        d2a, epsa = cil.cil_approx_d2(dev(A), dev(B))
+        cil.cil_set_option(cil.CIL_OPT_GRAM_PIPELINE, variant)
+        d2b, epsb = cil.cil_approx_d2(dev(A), dev(B))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_GRAM_PIPELINE, 2)
+        cil.cil_set_option(cil.CIL_OPT_GRAM_FLUSH, 64)
+    assert torch.equal(d2a, d2b) and torch.equal(epsa, epsb)
+    D = oracle_mod.pair_d2(A, B)
+    assert np.all(np.abs(d2b.cpu().numpy() - D) <= epsb.cpu().numpy())
+
+
+def test_gram_options_reject_other_values(cil):
+    for opt, v in ((cil.CIL_OPT_GRAM_FLUSH, 96), (cil.CIL_OPT_GRAM_PIPELINE, 3), (cil.CIL_OPT_GRAM_PIPELINE, -1)):
+        with pytest.raises(cil.CilError) as e:
+            cil.cil_set_option(opt, v)
+        assert e.value.code == cil.CIL_EINVAL
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nA,nB,d,M", [(1, 1, 8, 3), (67, 131, 50, 13), (64, 64, 2048, 16), (130, 70, 333, 32),
                                        (20, 30, 100, 100)])
