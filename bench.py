@@ -111,7 +111,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32-stepping", action="store_true")
     ap.add_argument("--cpu-sample-solves", type=int, default=96)
-    ap.add_argument("--gram-flush", type=int, default=64, choices=[64, 128, 256],
+    ap.add_argument("--gram-flush", type=int, default=64, choices=[32, 64, 128, 256],
                     help="features4096: FP32 -> FP64 promotion interval of the Gram")
     ap.add_argument("--gram-pipeline", type=int, default=2, choices=[0, 1, 2],
                     help="features4096: Gram staging variant (CIL_OPT_GRAM_PIPELINE)")

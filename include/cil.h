@@ -305,9 +305,9 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   per-resample gather kernel; 0 (default) = on the matrix cores when
  *   M <= 32 and no pattern occurs more than 256 times in a resample (the
  *   gather kernel otherwise).  Both give the same exact counts.
- * CIL_OPT_GRAM_FLUSH (value 64 (default), 128 or 256): number of elements
- *   the split-bf16x3 Gram accumulates in FP32 before adding into its FP64
- *   accumulator.  Smaller values narrow the error band (fewer canonical
+ * CIL_OPT_GRAM_FLUSH (value 32, 64 (default), 128 or 256): number of
+ *   elements the split-bf16x3 Gram accumulates in FP32 before adding into its
+ *   FP64 accumulator (at least 64 with CIL_OPT_GRAM_PIPELINE = 0).  Smaller values narrow the error band (fewer canonical
  *   re-checks) and cost more accumulator additions; counts are exact either
  *   way.  CIL_EINVAL for other values.
  * CIL_OPT_GRAM_PIPELINE (value 0, 1 or 2 (default)): how the Gram stages its

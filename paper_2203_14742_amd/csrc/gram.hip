@@ -386,11 +386,12 @@ int set_gram_pipeline(int64_t v)
     g_gram_pipeline = (int)v;
     return CIL_OK;
 }
-int gram_flush_interval() { return g_gram_kc; }
+// effective interval: the register-staged kernel promotes at multiples of its 64-k stage
+int gram_flush_interval() { return g_gram_pipeline ? g_gram_kc : std::max(g_gram_kc, GK); }
 int set_gram_flush_interval(int64_t v)
 {
-    if (v != 64 && v != 128 && v != 256) return set_error(CIL_EINVAL, "Gram flush interval %lld not in {64, 128, 256}",
-                                                         (long long)v);
+    if (v != 32 && v != 64 && v != 128 && v != 256)
+        return set_error(CIL_EINVAL, "Gram flush interval %lld not in {32, 64, 128, 256}", (long long)v);
     g_gram_kc = (int)v;
     return CIL_OK;
 }
@@ -415,7 +416,9 @@ int gram_partials(const GramWork &g, long long nA, long long nB, long long split
         const ProfMark pm2 = prof_begin("k_gram_dma", st);
         const __bf16 *ah = g.Ah, *al = g.Al, *bh = g.Bh, *bl = g.Bl;
         const int xo = g_gram_pipeline == 2;
-        if (kc == 64)
+        if (kc == 32)
+            hipLaunchKernelGGL(k_gram_dma<32>, grid, dim3(256), 0, st, ah, al, nA, bh, bl, nB, g.dimP, ks, P, xo);
+        else if (kc == 64)
             hipLaunchKernelGGL(k_gram_dma<64>, grid, dim3(256), 0, st, ah, al, nA, bh, bl, nB, g.dimP, ks, P, xo);
         else if (kc == 128)
             hipLaunchKernelGGL(k_gram_dma<128>, grid, dim3(256), 0, st, ah, al, nA, bh, bl, nB, g.dimP, ks, P, xo);
@@ -425,7 +428,7 @@ int gram_partials(const GramWork &g, long long nA, long long nB, long long split
         return check_launch("k_gram_dma");
     }
     const ProfMark pm = prof_begin("k_gram_bf16x3", st);
-    if (kc == 64)
+    if (kc <= 64)
         hipLaunchKernelGGL(k_gram_bf16x3<64>, grid, dim3(256), 0, st, (const __bf16 *)g.Ah, (const __bf16 *)g.Al, nA,
                            (const __bf16 *)g.Bh, (const __bf16 *)g.Bl, nB, g.dimP, ks, P);
     else if (kc == 128)

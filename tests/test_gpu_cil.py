@@ -127,7 +127,7 @@ def test_fast_pass_bound_fp64(cil, oracle_mod):
     assert np.all(np.abs(d2.cpu().numpy() - D) <= eps.cpu().numpy())
 
 
-@pytest.mark.parametrize("kc", [64, 128])
+@pytest.mark.parametrize("kc", [32, 64, 128])
 @pytest.mark.parametrize("case", ["random", "offset", "near_equal", "stripes"])
 def test_gram_flush_interval_bound_and_counts(cil, oracle_mod, kc, case):
     """Shorter FP32 accumulation intervals than 256 narrow the stated bound;
