@@ -21,7 +21,8 @@
  *     synchronises that stream before it returns; a call whose outputs are
  *     all device memory returns without synchronising.
  *   - The library keeps internal device workspaces, DCT tables, auxiliary
- *     streams and tuning state per device; cil_shutdown() frees them.  A
+ *     streams, a pool of the device buffers simulate calls used (reused by
+ *     later calls) and tuning state per device; cil_shutdown() frees them.  A
  *     simulate call with several grid sides runs each side's persistent
  *     kernel on an auxiliary stream forked from, and joined back into, the
  *     caller's stream.

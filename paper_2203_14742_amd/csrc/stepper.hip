@@ -28,6 +28,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -476,8 +477,25 @@ int quad_shape(bool f32, int n)
 
 }  // namespace
 
+// Device blocks reused across simulate calls, per device: a call's buffers go
+// back to this pool instead of hipFree, so repeated calls of similar size
+// allocate nothing.  Freed by cil_shutdown.
+std::mutex g_pool_mu;
+std::map<int, std::multimap<size_t, void *>> g_pool;     // device -> (capacity, block)
+
+size_t pool_capacity(size_t bytes)
+{
+    if (bytes <= ((size_t)1 << 20)) {
+        size_t c = 256;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    return (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+}
+
 // Library-owned stepper resources (cached DCT matrices of the plain path,
-// auxiliary streams and events), freed by cil_shutdown.
+// auxiliary streams and events, the pool of call buffers), freed by
+// cil_shutdown.
 int stepper_release()
 {
     int cur = 0;
@@ -496,6 +514,14 @@ int stepper_release()
         for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
     }
     g_aux.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (auto &kv : g_pool) {
+            (void)hipSetDevice(kv.first);
+            for (auto &b : kv.second) (void)hipFree(b.second);
+        }
+        g_pool.clear();
+    }
     (void)hipSetDevice(cur);
     return CIL_OK;
 }
@@ -575,21 +601,45 @@ int launch_plain(PlainGroup &g, const DevSolve *S, T *u, int nl, int model, doub
 
 }  // namespace
 
-// Device buffers owned by one simulate call (released at its end).
+// Device buffers owned by one simulate call (returned to the pool at its end;
+// a call that did not reach its final synchronisation first waits for the
+// device, so no block goes back while queued work may still use it).
 struct CallBuffers {
-    std::vector<void *> ptrs;
+    struct Block {
+        void *p;
+        size_t cap;
+        int dev;
+    };
+    std::vector<Block> blocks;
+    bool done = false;
     ~CallBuffers()
     {
-        for (void *p : ptrs) (void)hipFree(p);
+        if (blocks.empty()) return;
+        if (!done) (void)hipDeviceSynchronize();
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (const Block &b : blocks) g_pool[b.dev].emplace(b.cap, b.p);
     }
     int alloc(void **p, size_t bytes)
     {
-        if (bytes == 0) bytes = 16;
-        if (hipMalloc(p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(CIL_ENOMEM, "device allocation of %zu bytes failed", bytes);
+        int dev;
+        CIL_TRY(current_device(&dev));
+        const size_t cap = pool_capacity(bytes == 0 ? 16 : bytes);
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            auto &m = g_pool[dev];
+            auto it = m.lower_bound(cap);
+            if (it != m.end() && it->first <= 2 * cap) {
+                *p = it->second;
+                blocks.push_back(Block{it->second, it->first, dev});
+                m.erase(it);
+                return CIL_OK;
+            }
         }
-        ptrs.push_back(*p);
+        if (hipMalloc(p, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(CIL_ENOMEM, "device allocation of %zu bytes failed", cap);
+        }
+        blocks.push_back(Block{*p, cap, dev});
         return CIL_OK;
     }
 };
@@ -926,6 +976,7 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         CIL_TRY(check_launch("k_convert_solves"));
     }
     CIL_HIP(hipStreamSynchronize(st));
+    cb.done = true;
 
     int rc = CIL_OK;
     for (int b = 0; b < B; ++b) {
@@ -1182,6 +1233,7 @@ int plan_tune(SimPlan *p, int64_t steps, hipStream_t st)
     (void)hipEventDestroy(b);
     CIL_TRY(rc);
     CIL_HIP(hipStreamSynchronize(st));
+    tb.done = true;
     return plan_build_graph(*p);
 }
 
@@ -1231,6 +1283,7 @@ void plan_destroy(SimPlan *p)
     if (!p) return;
     (void)hipSetDevice(p->dev);
     (void)hipDeviceSynchronize();
+    p->bufs.done = true;
     delete p;
 }
 
