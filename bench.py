@@ -102,7 +102,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "features4096", "bz_uneven2048", "fhn128_mcmc"],
+                    choices=[WORKLOAD, "fhn32_fixed5000", "features4096", "bz_uneven2048", "fhn128_mcmc"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -144,6 +144,9 @@ def main():
         return
     if args.workload == "bz_uneven2048":
         uneven_main(args)
+        return
+    if args.workload == "fhn32_fixed5000":
+        fhn32_main(args)
         return
     if args.workload == "fhn128_mcmc":
         mcmc_main(args)
@@ -476,6 +479,103 @@ def uneven_main(args):
         "all_ok": bool(np.all(rep["status"] == 0) and np.all(rep["steps_taken"] == w["max_steps"])),
         "roofline": roof,
         "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def fhn32_main(args):
+    """The plain FP64 method's configuration: 128 FitzHugh-Nagumo solves on
+    32x32 (two 64-pattern sets), 5000 fixed steps of dt = 0.01, then the
+    correlation integral counts of the 64 x 64 cross pairs under 16 radii
+    R_0 1.2^-m (R_0 = the largest distance).  Timed twice on the same inputs:
+    the batched path (FP32 persistent fused stepper, split-bf16x3 Gram with
+    canonical re-check) and the plain FP64 GPU path (one kernel per stage and
+    step, direct FP64 distances).  `value` is the batched path's stationary
+    patterns/s."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS["fhn32_fixed5000"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics_host = np.concatenate([cs.initial_conditions(base, w["n"], w["count"], seed=s, law=w["ic_law"])
+                               for s in w["seeds"]])
+    B, half, M = ics_host.shape[0], w["count"], w["M"]
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=B)
+
+    def run(dtype, path):
+        ics = torch.tensor(ics_host, dtype=dtype, device=dev)
+        st = torch.empty_like(ics)
+
+        def one_step():
+            st.copy_(ics)
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"],
+                                            check_every=w["check_every"], path=path)
+            P = st.reshape(B, -1)
+            _, hi = cil.cil_distance_range(P[:half], P[half:])
+            radii = [math.sqrt(hi) * w["radii_base"] ** -(m + 1) for m in range(M)]
+            counts, _ = cil.cil_features(P[:half], P[half:], radii)
+            return rep, counts
+
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        cil.cil_profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rep, counts = one_step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
+        cil.cil_profile(False)
+        return el / args.steps, rep, counts, prof
+
+    t_fast, rep, counts, prof = run(torch.float32, cil.CIL_PATH_FUSED)
+    t_plain, rep64, counts64, prof64 = run(torch.float64, cil.CIL_PATH_PLAIN)
+    kname = "k_fused_q_f32_n32"
+    cnt, tot_ms = prof[kname]
+    flops = B * w["max_steps"] * fused_step_flops(w["n"], REACTION_FLOPS[w["model"]])
+    ach = flops / (tot_ms / cnt * 1e-3) / 1e12
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": VALU_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None, "launches": cnt,
+            "avg_launch_ms": round(tot_ms / cnt, 4),
+            "flops_per_solve_step": fused_step_flops(w["n"], REACTION_FLOPS[w["model"]])}
+    pairs = half * half
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
+        k = 16
+        t1 = time.perf_counter()
+        oracle.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], w["max_steps"], 0.0,
+                        w["check_every"], state=ics_host[:k].copy(), nthreads=threads)
+        tp = time.perf_counter() - t1
+        cpu = {"value": round(k / tp, 2), "unit": "patterns/s", "cores": threads, "kind": "oracle",
+               "sample": "%d solves x 5000 FP64 steps on the host (%.1f s)" % (k, tp)}
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(B / t_fast, 2), "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t_fast, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fhn32_fixed5000", "solves": B, "n": w["n"], "dt": w["dt"],
+                   "steps_per_solve": w["max_steps"], "pairs": pairs, "radii": M,
+                   "stepping": "fp32 fused persistent; statistic split-bf16x3 Gram + canonical re-check",
+                   "parallelism": "none (1 GPU)"},
+        "pairs_per_s": round(pairs / t_fast, 1),
+        "plain_fp64": {"patterns_per_s": round(B / t_plain, 2), "ms_per_step": round(1e3 * t_plain, 3),
+                       "speedup_patterns": round(t_plain / t_fast, 2),
+                       "what": "FP64, five kernels per time step (reaction, row and column transforms with the "
+                               "divide), direct FP64 distances"},
+        "counts_fp32_path": [int(c) for c in counts], "counts_fp64_path": [int(c) for c in counts64],
+        "all_ok": bool(np.all(rep["status"] == 0) and np.all(rep64["status"] == 0)),
+        "roofline": roof,
+        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

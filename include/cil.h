@@ -297,7 +297,8 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   the exact (slow) summation instead of the certified double-double one;
  *   for testing that path.
  * CIL_OPT_QUAD_SHAPE (value -1..3): code shape of the fused quad-lane stepper,
- *   -1 = chosen by precision (default); 0 = both species of a grid line in
+ *   -1 = chosen by grid side and precision (default: 1 for n = 32, else 2
+ *   in FP32 and 0 in FP64); 0 = both species of a grid line in
  *   one lane, 4n threads per solve; 1 = one species per lane, 8n threads;
  *   2, 3 = shapes 0, 1 with the column-pass divisor applied in the split
  *   step's complex form (fewer operations, a larger table).  Every shape

@@ -469,9 +469,14 @@ int g_quad_shape_option = -1;
 int quad_shape(bool f32, int n)
 {
     if (g_quad_shape_option >= 0) return g_quad_shape_option;
-    // measured on MI355X (GM 64^2, BZ 32^2 and 128^2 batches): both species
-    // per lane; the V-form divisor pays in FP32, not in FP64 (its third table
-    // plane costs more load latency than it saves operations)
+    // Measured on MI355X with the plans' autotuner (completion time of whole
+    // batches): 32^2 runs fastest with one species per lane (128 FHN solves:
+    // FP32 12.2 ms against 18.3 for both species per lane, FP64 16.2 against
+    // 24.6); 64^2 and 128^2 with both species per lane, where the V-form
+    // divisor pays in FP32 but not in FP64 (500 GM 64^2 solves in FP64: 30.4
+    // ms X-form, 33.6 V-form; its third table plane costs more load latency
+    // than it saves operations).
+    if (n == 32) return 1;
     return f32 ? 2 : 0;
 }
 
