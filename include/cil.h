@@ -317,9 +317,16 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   loads into two buffers, the next stage in flight while the matrix cores
  *   work; 2 = as 1 with tiles handed to the XCDs in contiguous ranges.  All
  *   compute the same products in the same order (identical results).
- *   CIL_EINVAL for other values. */
+ *   CIL_EINVAL for other values.
+ * CIL_OPT_WAVE_PRIORITY (value 0, or a base b in [2, 1e6]; default 100): in
+ *   residual-stopped fused runs (tol > 0) a solve sets its wavefronts' issue
+ *   priority at each evaluation from its residual r: 3, 2, 1 or 0 as r/tol
+ *   exceeds b^3, b^2, b or not, so that the solves with most steps to go,
+ *   which set the batch's time, win the SIMDs they share.  0 = off.  Results
+ *   are unchanged (priority changes timing only).  CIL_EINVAL for 1 or
+ *   values outside the range. */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
-       CIL_OPT_GRAM_PIPELINE = 5 };
+       CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

@@ -28,6 +28,7 @@ CIL_OPT_QUAD_SHAPE = 2
 CIL_OPT_BOOTSTRAP_GATHER = 3
 CIL_OPT_GRAM_FLUSH = 4
 CIL_OPT_GRAM_PIPELINE = 5
+CIL_OPT_WAVE_PRIORITY = 6
 CIL_QUAD_SHAPES = 4
 
 

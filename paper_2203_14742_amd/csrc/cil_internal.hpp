@@ -115,6 +115,7 @@ constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
 int gram_flush_interval();
 int set_gram_flush_interval(int64_t v);
 int set_gram_pipeline(int64_t v);
+int set_wave_priority(int64_t v);
 
 // Simulate plans (stepper.hip): a batch of fused solves bound to one graph.
 struct SimPlan;

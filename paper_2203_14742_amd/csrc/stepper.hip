@@ -465,6 +465,10 @@ int fused_supported(int n, bool f32)
 }
 
 int g_quad_shape_option = -1;
+// 0: off, else the base of the priority levels.  Measured on the 500-solve GM
+// batch (FP64, residual 1e-8): off 30.5 ms; base 3: 30.2; 10: 29.9; 100: 29.5;
+// 1000: 29.4.
+double g_wave_priority = 100.0;
 
 int quad_shape(bool f32, int n)
 {
@@ -528,6 +532,13 @@ int stepper_release()
         g_pool.clear();
     }
     (void)hipSetDevice(cur);
+    return CIL_OK;
+}
+
+int set_wave_priority(int64_t v)
+{
+    if (v < 0 || v == 1 || v > 1000000) return set_error(CIL_EINVAL, "wave priority option must be 0 or in [2, 1e6]");
+    g_wave_priority = (double)v;
     return CIL_OK;
 }
 
@@ -717,7 +728,7 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
     CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
     std::vector<long long> hsteps(c.steps.begin(), c.steps.end());
     CIL_HIP(hipMemcpyAsync(dsteps, hsteps.data(), sizeof(long long) * B, hipMemcpyHostToDevice, c.st));
-    PersistArgs pa{(long long)c.max_steps, c.tol, c.check, floor_coef, dsteps, dres, dstat};
+    PersistArgs pa{(long long)c.max_steps, c.tol, c.check, floor_coef, dsteps, dres, dstat, g_wave_priority};
     // Several grid sides: each side's persistent kernel on its own stream, the
     // most expensive (n^2 log n x solves) launched first, joined back into the
     // caller's stream, so the call stays ordered on it.
@@ -1159,7 +1170,8 @@ int plan_create(cil_model model, cil_precision prec, const cil_problem *probs, i
     const double floor_coef =
         (f32 && stp->tol > 0.0) ? (stp->fp32_floor_ulps > 0 ? stp->fp32_floor_ulps : 8) * std::ldexp(1.0, -24) / stp->dt
                                 : 0.0;
-    p->pa = PersistArgs{(long long)stp->max_steps, stp->tol, stp->check_every, floor_coef, dsteps, dres, dstat};
+    p->pa = PersistArgs{(long long)stp->max_steps, stp->tol, stp->check_every, floor_coef, dsteps, dres, dstat,
+                        g_wave_priority};
     CIL_HIP(hipMemcpyAsync(p->dS, p->hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
     for (auto &o : order) {
         SimPlan::Group g;
@@ -1204,7 +1216,7 @@ int plan_tune(SimPlan *p, int64_t steps, hipStream_t st)
     const PersistArgs pa = steps > 0 ? PersistArgs{(long long)steps, 0.0, (int)std::min<int64_t>(steps, 1 << 30), 0.0,
                                                    tsteps, tres, tstat}
                                      : PersistArgs{p->pa.max_steps, p->pa.tol, p->pa.check, p->pa.floor_coef, tsteps,
-                                                   tres, tstat};
+                                                   tres, tstat, p->pa.prio};
     hipEvent_t a, b;
     CIL_HIP(hipEventCreate(&a));
     CIL_HIP(hipEventCreate(&b));

@@ -102,7 +102,19 @@ struct PersistArgs {
     long long *steps;           // per solve: steps taken (in: start, out: end)
     double *resid;              // per solve: residual of the last evaluated step
     int *status;                // per solve: cil_solve_status
+    double prio;                // > 1: issue priority by distance from tol in powers of prio; 0: off
 };
+
+// A residual-stopped batch ends with its slowest solve.  With `prio`, a solve
+// far from its tolerance (many steps to go) takes issue priority on its SIMDs
+// over a co-resident solve that is nearly done (s_setprio, wave level).
+__device__ __forceinline__ void set_issue_priority(double ratio, double base)
+{
+    if (ratio > base * base * base) __builtin_amdgcn_s_setprio(3);
+    else if (ratio > base * base) __builtin_amdgcn_s_setprio(2);
+    else if (ratio > base) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
 
 // Quad-variant launch, one translation unit per precision (stepper_quad_*.hip).
 int launch_quad_f32(int n, int shape, int nl, const DevSolve *S, const int *list, float *state, const float *tables,

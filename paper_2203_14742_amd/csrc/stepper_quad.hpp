@@ -118,6 +118,7 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
                 if (st >= 0) pa.status[b] = st;
             }
             if (st >= 0) break;
+            if (pa.prio > 1.0 && pa.tol > 0.0) set_issue_priority(r / pa.tol, pa.prio);
         }
         if (step >= pa.max_steps) break;
         const long long next = step + 1;

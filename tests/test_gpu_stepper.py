@@ -263,3 +263,29 @@ def test_quad_shape_option_range(cil):
     with pytest.raises(cil.CilError) as e:
         cil.cil_set_option(cil.CIL_OPT_QUAD_SHAPE, 4)
     assert e.value.code == cil.CIL_EINVAL
+
+
+def test_wave_priority_changes_timing_only(cil):
+    """Residual-driven issue priority: identical states, steps and residuals
+    with it on (default) and off."""
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics = cs.initial_conditions(base, w["n"], 40, seed=41, law=w["ic_law"])
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=40)
+    out = []
+    try:
+        for prio in (0, 100):
+            cil.cil_set_option(cil.CIL_OPT_WAVE_PRIORITY, prio)
+            st = torch.tensor(ics, dtype=torch.float64, device="cuda")
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                            check_every=w["check_every"])
+            out.append((st, rep))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_WAVE_PRIORITY, 100)
+    assert torch.equal(out[0][0], out[1][0])
+    for k in ("steps_taken", "final_resid", "status"):
+        assert np.array_equal(out[0][1][k], out[1][1][k])
+    assert np.all(out[1][1]["status"] == 0)
+    for bad in (1, -1, 2000000):
+        with pytest.raises(cil.CilError):
+            cil.cil_set_option(cil.CIL_OPT_WAVE_PRIORITY, bad)
