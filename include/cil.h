@@ -324,9 +324,14 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   exceeds b^3, b^2, b or not, so that the solves with most steps to go,
  *   which set the batch's time, win the SIMDs they share.  0 = off.  Results
  *   are unchanged (priority changes timing only).  CIL_EINVAL for 1 or
- *   values outside the range. */
+ *   values outside the range.
+ * CIL_OPT_POLISH_SEPARATE (value 0/1): FP32 solves with polish = 1 on the
+ *   fused quad-lane path at n = 32 or 64 (default shapes) switch to FP64 at
+ *   their FP32 floor inside the same persistent launch (0, default); 1 = the
+ *   FP64 polish runs as a launch of its own after the whole FP32 phase.  Both
+ *   give identical results. */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
-       CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6 };
+       CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6, CIL_OPT_POLISH_SEPARATE = 7 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

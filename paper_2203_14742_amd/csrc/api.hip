@@ -591,6 +591,7 @@ int cil_set_option(int32_t option, int64_t value)
     if (option == CIL_OPT_GRAM_FLUSH) return set_gram_flush_interval(value);
     if (option == CIL_OPT_GRAM_PIPELINE) return set_gram_pipeline(value);
     if (option == CIL_OPT_WAVE_PRIORITY) return set_wave_priority(value);
+    if (option == CIL_OPT_POLISH_SEPARATE) return set_polish_separate(value);
     return set_error(CIL_EINVAL, "unknown option %d", option);
 }
 

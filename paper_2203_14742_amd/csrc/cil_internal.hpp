@@ -116,6 +116,7 @@ int gram_flush_interval();
 int set_gram_flush_interval(int64_t v);
 int set_gram_pipeline(int64_t v);
 int set_wave_priority(int64_t v);
+int set_polish_separate(int64_t v);
 
 // Simulate plans (stepper.hip): a batch of fused solves bound to one graph.
 struct SimPlan;

@@ -465,6 +465,7 @@ int fused_supported(int n, bool f32)
 }
 
 int g_quad_shape_option = -1;
+int g_polish_separate = 0;         // 1: FP64 polish always in a launch of its own
 // 0: off, else the base of the priority levels.  Measured on the 500-solve GM
 // batch (FP64, residual 1e-8): off 30.5 ms; base 3: 30.2; 10: 29.9; 100: 29.5;
 // 1000: 29.4.
@@ -532,6 +533,13 @@ int stepper_release()
         g_pool.clear();
     }
     (void)hipSetDevice(cur);
+    return CIL_OK;
+}
+
+int set_polish_separate(int64_t v)
+{
+    if (v != 0 && v != 1) return set_error(CIL_EINVAL, "polish option must be 0 or 1");
+    g_polish_separate = (int)v;
     return CIL_OK;
 }
 
@@ -673,7 +681,19 @@ struct SimCtx {
     std::vector<int64_t> steps;   // per solve (host)
     std::vector<double> fres;
     std::vector<int> status;
+    std::vector<int64_t> sw;      // mixed launches: step of the FP32 -> FP64 switch (-1: not a mixed solve)
 };
+
+// FP32 -> FP64 within one launch (k_fused_q_mixed) for these grid sides.
+struct MixedArgs {
+    double *state64;              // FP64 snapshots, same element layout as the FP32 state
+    long long *sw;                // per solve: switch step
+};
+
+bool mixed_supported(int n, bool quad)
+{
+    return quad && !g_polish_separate && g_quad_shape_option < 0 && (n == 32 || n == 64);
+}
 
 // Spectral tables for the solves in `ids` (side n): one per distinct (h, nu);
 // sets hs[b].tab.  Returns the device table buffer.
@@ -714,15 +734,18 @@ int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSo
 // device arrays; the host copies are refreshed after the launches.
 template <typename T>
 int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<DevSolve> &hs, DevSolve *dS, T *state,
-              bool quad, double floor_coef, long long *dsteps, double *dres, int *dstat)
+              bool quad, double floor_coef, long long *dsteps, double *dres, int *dstat, const MixedArgs *mx = nullptr)
 {
     if (byn.empty()) return CIL_OK;
-    std::vector<void *> tabs;
+    std::vector<void *> tabs, tabs64;
     for (auto &kv : byn) {
-        void *t;
+        void *t, *t64 = nullptr;
         CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &t,
                                quad && kQuadShape[quad_shape(std::is_same<T, float>::value, kv.first)].vform));
+        if (mx && mixed_supported(kv.first, quad))
+            CIL_TRY(make_tables<double>(c, kv.first, kv.second, hs, &t64, kQuadShape[quad_shape(false, kv.first)].vform));
         tabs.push_back(t);
+        tabs64.push_back(t64);
     }
     const int B = (int)hs.size();
     CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
@@ -765,6 +788,24 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
             CIL_HIP(hipStreamWaitEvent(gst, aux->ev[0], 0));
         }
         const int shape = quad_shape(std::is_same<T, float>::value, kv.first);
+        if constexpr (std::is_same<T, float>::value) {
+            if (tabs64[gi]) {
+                PersistArgs pa64 = pa;
+                pa64.floor_coef = 0.0;
+                const ProfMark pm = prof_begin(kv.first == 32 ? "k_fused_q_mixed_n32" : "k_fused_q_mixed_n64", gst);
+                const int rc = launch_quad_mixed(kv.first, (int)kv.second.size(), dS, dls[gi], state, mx->state64,
+                                                 (const float *)tabs[gi], (const double *)tabs64[gi], c.model, c.dt,
+                                                 pa, pa64, mx->sw, gst);
+                prof_end(pm, gst);
+                if (rc) return set_error(rc, "no mixed-precision kernel for n = %d", kv.first);
+                CIL_TRY(check_launch("k_fused_q_mixed"));
+                if (aux) {
+                    CIL_HIP(hipEventRecord(aux->ev[1 + gi], gst));
+                    CIL_HIP(hipStreamWaitEvent(c.st, aux->ev[1 + gi], 0));
+                }
+                continue;
+            }
+        }
         CIL_TRY(launch_persistent<T>(kv.first, quad, shape, (int)kv.second.size(), dS, dls[gi], state,
                                      (const T *)tabs[gi], c.model, c.dt, pa, gst));
         if (aux) {
@@ -777,12 +818,18 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
     CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
     CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
     CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
+    std::vector<long long> hsw;
+    if (mx) {
+        hsw.resize(B);
+        CIL_HIP(hipMemcpyAsync(hsw.data(), mx->sw, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
+    }
     CIL_HIP(hipStreamSynchronize(c.st));
-    for (auto &kv : byn)
-        for (int b : kv.second) {
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (int b : groups[gi]->second) {
             c.steps[b] = hsteps[b];
             c.fres[b] = hres[b];
             c.status[b] = hstat[b];
+            if (mx && tabs64[gi]) c.sw[b] = hsw[b];
         }
     return CIL_OK;
 }
@@ -930,7 +977,19 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     CIL_TRY(cb.alloc((void **)&R.maxabs, sizeof(unsigned long long) * B));
     CIL_TRY(cb.alloc((void **)&R.bad, sizeof(int) * B));
 
-    if (f32) CIL_TRY(run_fused<float>(c, fused_byn, hs, dS, (float *)state, quad, c.floor_coef32, dsteps, dres, dstat));
+    c.sw.assign(B, -1);
+    MixedArgs mx{nullptr, nullptr};
+    bool use_mixed = false;
+    if (polish)
+        for (auto &kv : fused_byn) use_mixed |= mixed_supported(kv.first, quad);
+    if (use_mixed) {
+        int64_t end = 0;
+        for (int b = 0; b < B; ++b) end = std::max<int64_t>(end, hs[b].off + elems[b]);
+        CIL_TRY(cb.alloc((void **)&mx.state64, sizeof(double) * (size_t)end));
+        CIL_TRY(cb.alloc((void **)&mx.sw, sizeof(long long) * B));
+    }
+    if (f32) CIL_TRY(run_fused<float>(c, fused_byn, hs, dS, (float *)state, quad, c.floor_coef32, dsteps, dres, dstat,
+                                      use_mixed ? &mx : nullptr));
     else CIL_TRY(run_fused<double>(c, fused_byn, hs, dS, (double *)state, quad, 0.0, dsteps, dres, dstat));
     if (!plain_byn.empty()) {
         CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
@@ -947,8 +1006,10 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     // phase 2: FP32 solves stopped at the FP32 floor continue in FP64
     std::vector<int64_t> steps64(B, 0);
     std::vector<int> promoted;
-    for (int b = 0; b < B; ++b)
+    for (int b = 0; b < B; ++b) {
+        if (c.sw[b] >= 0) steps64[b] = c.steps[b] - c.sw[b];     // polished inside the mixed launch
         if (polish && c.status[b] == CIL_SOLVE_FP32_FLOOR) promoted.push_back(b);
+    }
     if (!promoted.empty()) {
         std::vector<DevSolve> hs64 = hs;
         int64_t t = 0;

@@ -116,6 +116,12 @@ __device__ __forceinline__ void set_issue_priority(double ratio, double base)
     else __builtin_amdgcn_s_setprio(0);
 }
 
+// Mixed-precision quad launch (stepper_quad_mixed.hip): n = 32 and 64 with the
+// default shapes (FP32 shape 1 / FP64 shape 1 at n = 32, 2 / 0 at n = 64).
+int launch_quad_mixed(int n, int nl, const DevSolve *S, const int *list, float *state, double *state64,
+                      const float *tab32, const double *tab64, int model, double dt, const PersistArgs &pa32,
+                      const PersistArgs &pa64, long long *switch_step, hipStream_t st);
+
 // Quad-variant launch, one translation unit per precision (stepper_quad_*.hip).
 int launch_quad_f32(int n, int shape, int nl, const DevSolve *S, const int *list, float *state, const float *tables,
                     int model, double dt, const PersistArgs &pa, hipStream_t st);

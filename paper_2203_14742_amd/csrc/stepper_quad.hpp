@@ -12,9 +12,15 @@ namespace cil {
 // threads; group g of eight lanes owns row/column g, species s = (t / 4) & 1,
 // quad position q = t & 3 for v and 3 - (t & 3) for w, so that lane t ^ 7 -
 // the DPP half-row mirror - holds the other species at the same points).
-template <typename T, int N, int SPL, bool VF, typename MD>
-__device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, const DevSolve &s, int b, T *state,
-                                              const T *tables, double dt, const PersistArgs &pa)
+//
+// The lane's values of u live in ur/ui (caller's registers): loaded from
+// `state` first when LOAD, stored to `out` (element type TS, same layout) at
+// the end.  `step` enters as the first step and leaves as the last; the
+// return value is the status of the last evaluation (-1 if none ran).
+template <typename T, int N, int SPL, bool VF, typename MD, bool LOAD, typename TS>
+__device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, const DevSolve &s, int b, T *state,
+                                             TS *out, const T *tables, double dt, const PersistArgs &pa,
+                                             long long &step, T (&ur)[SPL][N / 8], T (&ui)[SPL][N / 8])
 {
     using Q = QuadLine<T, N>;
     constexpr int P = Q::P, M = N / 2;
@@ -54,7 +60,7 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
     const unsigned tko = (sp0 * VSP + kb * N + g) * sizeof(T), tmo = (sp0 * VSP + M * N + g) * sizeof(T);
     const unsigned tno = (sp0 * VSP + (N - kb - (P - 1)) * N + g) * sizeof(T);
 
-    T ur[SPL][P], ui[SPL][P];     // the lane's 2P values of each of its species along row g, natural order
+    // ur/ui: the lane's 2P values of each of its species along row g, natural order
     auto hbm_ld = [&](auto m1c, auto hc, int c) -> T {
         constexpr int m1 = decltype(m1c)::value;
         return buf_load<T>(ub, (m1 < P / 2 ? hu0 : hu1) + line_off(m1c, hc) * sizeof(T), c * NN * sizeof(T));
@@ -65,15 +71,17 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
-    static_for<0, P>([&](auto Mi) {
+    if constexpr (LOAD) {
+        static_for<0, P>([&](auto Mi) {
 #pragma unroll
-        for (int c = 0; c < SPL; ++c) {
-            ur[c][Mi] = hbm_ld(Mi, I0{}, c);
-            ui[c][Mi] = hbm_ld(Mi, I1{}, c);
-        }
-    });
-    const long long start = pa.steps[b];
-    long long step = start;
+            for (int c = 0; c < SPL; ++c) {
+                ur[c][Mi] = hbm_ld(Mi, I0{}, c);
+                ui[c][Mi] = hbm_ld(Mi, I1{}, c);
+            }
+        });
+    }
+    const long long start = step;
+    int fin = -1;
     while (true) {
         const bool eval_now = step > start && ((step % pa.check == 0) || step == pa.max_steps);
         if (eval_now) {       // stop rule on u^step against the snapshot of u^(step-1)
@@ -117,6 +125,7 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
                 pa.resid[b] = anybad ? (double)NAN : r;
                 if (st >= 0) pa.status[b] = st;
             }
+            fin = st;
             if (st >= 0) break;
             if (pa.prio > 1.0 && pa.tol > 0.0) set_issue_priority(r / pa.tol, pa.prio);
         }
@@ -221,14 +230,18 @@ __device__ __forceinline__ void fused_q_solve(T *sm, double *red, int *sbad, con
         }
         step = next;
     }
+    const auto ob = make_rsrc(out + s.off, 2 * NN * sizeof(TS));
     static_for<0, P>([&](auto Mi) {
 #pragma unroll
         for (int c = 0; c < SPL; ++c) {
-            hbm_st(ur[c][Mi], Mi, I0{}, c);
-            hbm_st(ui[c][Mi], Mi, I1{}, c);
+            buf_store<TS>(TS(ur[c][Mi]), ob, (Mi < P / 2 ? hu0 : hu1) / sizeof(T) * sizeof(TS) +
+                                                 line_off(Mi, I0{}) * sizeof(TS), c * NN * sizeof(TS));
+            buf_store<TS>(TS(ui[c][Mi]), ob, (Mi < P / 2 ? hu0 : hu1) / sizeof(T) * sizeof(TS) +
+                                                 line_off(Mi, I1{}) * sizeof(TS), c * NN * sizeof(TS));
         }
     });
     if (tid == 0) pa.steps[b] = step;
+    return fin;
 }
 
 // Quad variant: every line is transformed by a quad of lanes (dct_quad.hpp);
@@ -253,8 +266,53 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(W
     __shared__ int sbad[WAVES];
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
+    long long step = pa.steps[b];
     dispatch_model(model, [&](auto MD) {
-        fused_q_solve<T, N, SPL, VF, decltype(MD)>(sm, red, sbad, s, b, state, tables, dt, pa);
+        T ur[SPL][N / 8], ui[SPL][N / 8];
+        fused_q_solve<T, N, SPL, VF, decltype(MD), true, T>(sm, red, sbad, s, b, state, state, tables, dt, pa, step,
+                                                            ur, ui);
+    });
+}
+
+// FP32 stepping with the FP64 polish in one persistent launch.  A solve that
+// stops at the FP32 floor converts its registers to FP64 and continues with
+// the FP64 step (FP64 tables, FP64 snapshots for its stop rule in state64) to
+// the tolerance; its final state is stored as FP32.  Each phase is the
+// one-precision solve above, so the result equals that of the FP32 launch
+// followed by an FP64 launch over the promoted solves, without the second
+// launch waiting for the whole batch's FP32 phase.  switch_step[b]: the step
+// at which solve b changed precision (its last step if it did not).
+template <int N, int SPL, bool VF32, bool VF64>
+__global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_q_mixed(
+    const DevSolve *S, const int *list, float *state, double *state64, const float *tab32, const double *tab64,
+    int model, double dt, PersistArgs pa32, PersistArgs pa64, long long *switch_step)
+{
+    constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64, P = N / 8;
+    __shared__ double sm[2 * SP];
+    __shared__ double red[2 * WAVES];
+    __shared__ int sbad[WAVES];
+    const int b = list[blockIdx.x];
+    const DevSolve s = S[b];
+    long long step = pa32.steps[b];
+    dispatch_model(model, [&](auto MD) {
+        float ur[SPL][P], ui[SPL][P];
+        const int fin = fused_q_solve<float, N, SPL, VF32, decltype(MD), true, float>(
+            reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa32, step, ur, ui);
+        const long long sw = step;
+        if (fin == CIL_SOLVE_FP32_FLOOR) {         // uniform: every lane holds the same stop decision
+            double vr[SPL][P], vi[SPL][P];
+#pragma unroll
+            for (int c = 0; c < SPL; ++c)
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    vr[c][m] = (double)ur[c][m];
+                    vi[c][m] = (double)ui[c][m];
+                }
+            __syncthreads();                         // the LDS is reused at double width
+            fused_q_solve<double, N, SPL, VF64, decltype(MD), false, float>(sm, red, sbad, s, b, state64, state, tab64,
+                                                                            dt, pa64, step, vr, vi);
+        }
+        if (threadIdx.x == 0) switch_step[b] = sw;
     });
 }
 

@@ -3,10 +3,17 @@ times): 500 Gierer-Meinhardt (source form) solves on 64x64 grids to FP64
 residual < 1e-8, then the CIL statistic of the two 250-pattern halves stored
 as FP32 (d = 8192, 13 radii, 200 bootstrap resamples) and the likelihood.
 
-Sampled solves are re-run by the oracle (steps taken identical, patterns
-within 1e-8 of the oracle's); the statistic is checked in full: the oracle
-computes all 62 500 canonical distances, and range, radii, bins, counts,
-bootstrap counts (bit-exact) and the likelihood (1e-10) must agree.
+The benchmarked stepping is FP32 with each solve's FP64 polish (from its FP32
+floor to the tolerance) in the same launch.  Its patterns are checked by
+properties the oracle can verify one by one: every sampled stored pattern is
+stationary under the oracle's step (residual of one FP64 step within what
+FP32 storage rounding allows, tol + 4 x 2^-24 max|u| / dt), and the whole batch is
+bit-identical to the FP32 launch followed by a separate FP64 launch.  The
+FP64 fused stepping is checked against the oracle directly (sampled solves:
+step counts identical, patterns within 1e-8).  The statistic is checked in
+full on both pattern sets: the oracle computes all 62 500 canonical
+distances, and range, radii, bins, counts, bootstrap counts (bit-exact) and
+the likelihood (1e-10) must agree.
 """
 import numpy as np
 import pytest
@@ -38,6 +45,48 @@ def stepped(cil):
     return w, ics, st, rep
 
 
+@pytest.fixture(scope="module")
+def stepped32(cil):
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics = cs.initial_conditions(base, w["n"], w["count"], seed=w["seeds"][0], law=w["ic_law"])
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=w["count"])
+    out = []
+    try:
+        for sep in (0, 1):
+            cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
+            st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+            print("full-size GM-source run, FP32 + FP64 polish (separate launch: %d)" % sep, flush=True)
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                            check_every=w["check_every"], polish=1)
+            out.append((st, rep))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 0)
+    return w, ics, out
+
+
+def test_full_workload_fp32_polished_patterns(cil, oracle_mod, stepped32):
+    w, ics, out = stepped32
+    (st, rep), (st2, rep2) = out
+    assert torch.equal(st, st2)
+    for k in ("steps_taken", "steps_fp64", "final_resid", "status"):
+        assert np.array_equal(rep[k], rep2[k]), k
+    assert np.all(rep["status"] == 0) and np.all(rep["final_resid"] < w["tol"])
+    assert np.all(rep["steps_fp64"] > 0)
+    s = rep["steps_taken"]
+    sample = sorted({int(np.argmax(s)), int(np.argmin(s)), 0, 123, 249, 250, 377, 499})
+    g = st.double().cpu().numpy()[sample]
+    one, _, res, ostat = oracle_mod.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], 1, 0.0, 1,
+                                             state=g.copy(), nthreads=8)
+    r = np.abs(one - g).reshape(len(sample), -1).max(axis=1) / w["dt"]
+    # FP32 storage moves each value by at most 2^-24 max|u|; one step maps that
+    # perturbation to a residual of about that over dt (the diffusion solve
+    # damps it, the explicit reaction adds dt |f'|); a factor 4 of margin
+    bar = w["tol"] + 4.0 * 2.0 ** -24 * np.abs(g).reshape(len(sample), -1).max(axis=1) / w["dt"]
+    print("FP32-stored polished patterns: oracle one-step residual max %.3e (bar %.3e)" % (r.max(), bar.min()))
+    assert np.all(r < bar)
+
+
 def test_full_workload_stationary_patterns(cil, oracle_mod, stepped):
     w, ics, st, rep = stepped
     assert np.all(rep["status"] == 0) and np.all(rep["final_resid"] < w["tol"])
@@ -54,8 +103,13 @@ def test_full_workload_stationary_patterns(cil, oracle_mod, stepped):
     assert err <= 1e-8
 
 
-def test_full_workload_statistic(cil, oracle_mod, stepped):
-    w, ics, st, rep = stepped
+@pytest.mark.parametrize("stepping", ["fp32_polished", "fp64"])
+def test_full_workload_statistic(cil, oracle_mod, request, stepping):
+    if stepping == "fp64":
+        w, ics, st, rep = request.getfixturevalue("stepped")
+    else:
+        w, ics, out = request.getfixturevalue("stepped32")
+        st = out[0][0]
     B, half, d, M = w["count"], w["count"] // 2, 2 * w["n"] ** 2, w["M"]
     P = st.reshape(B, d).float().contiguous()
     A, Bs = P[:half], P[half:]

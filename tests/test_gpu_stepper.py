@@ -289,3 +289,62 @@ def test_wave_priority_changes_timing_only(cil):
     for bad in (1, -1, 2000000):
         with pytest.raises(cil.CilError):
             cil.cil_set_option(cil.CIL_OPT_WAVE_PRIORITY, bad)
+
+
+def _gm_batch(cil, n, count, seed, L):
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics = cs.initial_conditions(base, n, count, seed=seed, law=w["ic_law"])
+    return w, ics, cil.make_problems(n, L, w["nu"], w["params"], count=count)
+
+
+@pytest.mark.parametrize("n,L", [(64, 120.0), (32, 60.0)])
+def test_mixed_polish_equals_separate_launch(cil, n, L):
+    """FP32 stepping with the FP64 polish inside one persistent launch gives
+    the bits of the FP32 launch followed by an FP64 launch over the solves
+    promoted at the FP32 floor: states, step counts (total and FP64),
+    residuals and statuses."""
+    w, ics, probs = _gm_batch(cil, n, 24, seed=51 + n, L=L)
+    out = []
+    try:
+        for sep in (0, 1):
+            cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
+            st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+            print("polish separate=%d n=%d" % (sep, n), flush=True)
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                            check_every=w["check_every"], polish=1)
+            out.append((st, rep))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 0)
+    assert torch.equal(out[0][0], out[1][0])
+    for k in ("steps_taken", "steps_fp64", "final_resid", "status"):
+        assert np.array_equal(out[0][1][k], out[1][1][k]), k
+    assert np.any(out[0][1]["steps_fp64"] > 0)            # solves reached the FP32 floor and were polished
+    if n == 64:                                           # the benchmarked model and grid: all converge
+        assert np.all(out[0][1]["steps_fp64"] > 0)
+        assert np.all(out[0][1]["status"] == 0) and np.all(out[0][1]["final_resid"] < w["tol"])
+
+
+def test_mixed_polish_uneven_sides(cil):
+    """Sides 32, 64 (mixed launches) and 128 (FP32 launch + FP64 plain
+    polish) in one call: identical to the separate polish launches."""
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    ns = [32, 64, 128, 64, 32]
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    flat = np.concatenate([cs.initial_conditions(base, n, 1, seed=60 + i, law=w["ic_law"]).reshape(-1)
+                           for i, n in enumerate(ns)])
+    probs = cil.make_problems(ns, [60.0 if n == 32 else (120.0 if n == 64 else 240.0) for n in ns], w["nu"],
+                              w["params"])
+    out = []
+    try:
+        for sep in (0, 1):
+            cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
+            st = torch.tensor(flat, dtype=torch.float32, device="cuda")
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], 4000, tol=w["tol"],
+                                            check_every=w["check_every"], polish=1)
+            out.append((st, rep))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 0)
+    assert torch.equal(out[0][0], out[1][0])
+    for k in ("steps_taken", "steps_fp64", "final_resid", "status"):
+        assert np.array_equal(out[0][1][k], out[1][1][k]), k
