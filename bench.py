@@ -69,7 +69,7 @@ REACTION_FLOPS = {0: 12, 1: 13, 2: 13, 3: 13, 4: 4}   # kinetics + the explicit 
 
 # Sources that define the fused stepper kernels (device code, launch shape).
 STEPPER_SOURCES = ["stepper.hip", "stepper_common.hpp", "stepper_quad.hpp", "stepper_quad_f32.hip",
-                   "stepper_quad_f64.hip", "dct_quad.hpp", "cil_internal.hpp"]
+                   "stepper_quad_f64.hip", "stepper_quad_mixed.hip", "dct_quad.hpp", "cil_internal.hpp"]
 TRAFFIC_PROFILES = os.path.join(ROOT, "profiles", "*_hbm_bytes.md")
 
 
