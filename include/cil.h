@@ -100,7 +100,9 @@ typedef enum {
  * the FP32 floor fp32_floor_ulps * 2^-24 * max|u| / dt (the state can no
  * longer resolve the residual) and tol is below that floor, polish != 0
  * promotes the solve to FP64 stepping on the GPU until tol is met (the result
- * is rounded back to FP32); polish == 0 stops it there with status
+ * is rounded back to FP32; on the fused quad-lane path at n = 32 and 64 the
+ * switch happens inside the same persistent launch, see
+ * CIL_OPT_POLISH_SEPARATE); polish == 0 stops it there with status
  * CIL_SOLVE_FP32_FLOOR. */
 typedef struct {
     double dt;
