@@ -55,6 +55,17 @@ class SolveReport(ctypes.Structure):
                 ("final_resid", ctypes.c_double), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+# numpy view of a SolveReport array (same field order, sizes and offsets)
+_REPORT_DTYPE = np.dtype([("steps_taken", np.int64), ("steps_fp64", np.int64), ("final_resid", np.float64),
+                          ("status", np.int32), ("reserved", np.int32)])
+
+
+def _reports(reps, B: int):
+    a = np.frombuffer(reps, dtype=_REPORT_DTYPE, count=B) if B else np.zeros(0, dtype=_REPORT_DTYPE)
+    return dict(steps_taken=a["steps_taken"].copy(), steps_fp64=a["steps_fp64"].copy(),
+                final_resid=a["final_resid"].copy(), status=a["status"].copy())
+
+
 _lib = None
 
 
@@ -195,10 +206,7 @@ def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int
     rc = lib().cil_simulate_patterns(model, _prec(state), ctypes.cast(problems, ctypes.c_void_p), B,
                                      _dev(state, "state"), None if offs is None else offs.ctypes.data,
                                      ctypes.byref(st), ctypes.cast(reps, ctypes.c_void_p), _stream(state))
-    out = dict(steps_taken=np.array([r.steps_taken for r in reps[:B]], dtype=np.int64),
-               steps_fp64=np.array([r.steps_fp64 for r in reps[:B]], dtype=np.int64),
-               final_resid=np.array([r.final_resid for r in reps[:B]]),
-               status=np.array([r.status for r in reps[:B]], dtype=np.int32))
+    out = _reports(reps, B)
     if rc == CIL_ENONFINITE and not raise_on_nonfinite:
         return out
     _check(rc)
@@ -252,9 +260,8 @@ class SimPlan:
     def report(self, raise_on_nonfinite: bool = True):
         reps = (SolveReport * self.B)()
         rc = lib().cil_sim_plan_report(self._h, ctypes.cast(reps, ctypes.c_void_p), _stream(self.state))
-        out = dict(steps_taken=np.array([r.steps_taken for r in reps], dtype=np.int64),
-                   final_resid=np.array([r.final_resid for r in reps]),
-                   status=np.array([r.status for r in reps], dtype=np.int32))
+        out = _reports(reps, self.B)
+        del out["steps_fp64"]
         if rc == CIL_ENONFINITE and not raise_on_nonfinite:
             return out
         _check(rc)
