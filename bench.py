@@ -106,7 +106,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "fhn32_fixed5000", "features4096", "bz_uneven2048", "fhn128_mcmc"],
+                    choices=[WORKLOAD, "fhn32_fixed5000", "features4096", "mcil_stripes64", "bz_uneven2048",
+                             "fhn128_mcmc"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -120,6 +121,7 @@ def parse():
                     help="features4096: FP32 -> FP64 promotion interval of the Gram")
     ap.add_argument("--gram-pipeline", type=int, default=2, choices=[0, 1, 2],
                     help="features4096: Gram staging variant (CIL_OPT_GRAM_PIPELINE)")
+    ap.add_argument("--scaled", action="store_true", help="mcil_stripes64: min-max scale the patterns first")
     ap.add_argument("--tune-steps", type=int, default=100,
                     help="bz_uneven2048: steps per autotuning trial (0 = the plan's own stepping)")
     ap.add_argument("--sources-sha256", action="store_true",
@@ -149,6 +151,9 @@ def main():
         return
     if args.workload == "bz_uneven2048":
         uneven_main(args)
+        return
+    if args.workload == "mcil_stripes64":
+        mcil_main(args)
         return
     if args.workload == "fhn32_fixed5000":
         fhn32_main(args)
@@ -590,6 +595,87 @@ def fhn32_main(args):
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def mcil_main(args):
+    """Multi-feature CIL statistic (Sec. 3.1) on 500 stand-in patterns of side
+    64 (halves of 250): derivative augmentation, then per norm the adaptive
+    radii, bins and 200 bootstrap vectors -- L2 and W^{1,2} through the
+    split-bf16x3 Gram path (patterns / augmented vectors), L-inf, W^{1,inf} and
+    its sum variant from the per-segment max-abs distances of the augmented
+    vectors -- and the likelihood of the concatenated 60-entry vector.  With
+    --scaled the patterns are min-max scaled first (Sec. 5).  `value` is
+    distance pairs/s (pairs of patterns, all five norms)."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS["mcil_stripes64"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    count, n, M, n_boot, L = w["count"], w["n"], w["M"], w["n_boot"], w["L"]
+    half = count // 2
+    raw = torch.from_numpy(cs.stripe_patterns(count, n, seed=w["seed"]).astype(np.float32)).to(dev)
+    ia, ib = cs.resample_halves(half, half, half, half, n_boot, seed=w["boot_seed"])
+    idxA = torch.from_numpy(ia).to(dev)
+    idxB = torch.from_numpy(ib).to(dev)
+    nn2, ne2 = 2 * n * n, 2 * n * (n - 1)
+    ends = [nn2, nn2 + ne2, nn2 + 2 * ne2]
+    pairs = half * half
+
+    def one_step():
+        P = cil.cil_minmax_scale(raw, n) if args.scaled else raw
+        Aug = cil.cil_augment_patterns(P, n, L)
+        Ys = []
+        for X in (P.reshape(count, -1), Aug):
+            _, _, _, bins, _ = cil.cil_pair_bins_adaptive(X[:half], X[half:], M)
+            Ys.append(cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)[1])
+        D = cil.cil_pair_maxabs(Aug[:half], Aug[half:], ends)
+        for V in (D[..., 0].contiguous(), cil.cil_combine_segments(D, 0), cil.cil_combine_segments(D, 1)):
+            lo, hi = cil.cil_value_range(V)
+            bins, _ = cil.cil_bin_values(V, cil.cil_radii(lo * lo, hi * hi, M))
+            Ys.append(cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)[1])
+        Y = torch.cat(Ys, dim=1).contiguous()
+        return cil.cil_gaussian_loglik(Y, Y[0].contiguous()), Y
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    cil.cil_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, Y = one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
+    cil.cil_profile(False)
+    K = args.steps
+    daug = ends[-1]
+    roof = None
+    if "k_pair_maxabs" in prof:
+        cnt, tot_ms = prof["k_pair_maxabs"]
+        ops = 2.0 * daug * pairs               # one FP64 subtract and one max per element pair
+        ach = ops * cnt / (tot_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_pair_maxabs", "bound": "alu", "achieved": round(ach, 3),
+                "peak": VALU_FP64_PEAK_TFLOPS / 2, "unit": "TOP/s (FP64 VALU instructions x lanes)",
+                "frac": round(ach / (VALU_FP64_PEAK_TFLOPS / 2), 4), "traffic": None, "launches": cnt,
+                "avg_launch_ms": round(tot_ms / cnt, 4), "ops_per_pair": 2 * daug}
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(pairs * K / el, 1), "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mcil_stripes64", "patterns": count, "n": n, "dim": nn2, "augmented_dim": daug,
+                   "pairs_per_step": pairs, "norms": ["L2", "Linf", "W12", "W1inf", "W1inf_sum"], "radii": M,
+                   "bootstrap": n_boot, "scaled": bool(args.scaled), "parallelism": "none (1 GPU)"},
+        "features": int(Y.shape[1]), "m_eff": int(out[2].cpu()[0]), "loglik_status": int(out[3].cpu()[0]),
+        "roofline": roof,
+        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

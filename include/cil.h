@@ -270,6 +270,51 @@ int cil_pair_bins_adaptive(const void *setA, int64_t nA, const void *setB, int64
  * (slow) summation.  Host only. */
 int cil_last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact_fallbacks);
 
+/* ------------------------------------------- further features (Sec. 3.1) */
+/* Min-max scaling of Sec. 5 (scaled pattern data): for each pattern and
+ * species, s~ = (s - min) / (max - min) over the species' n x n values,
+ * evaluated in FP64 and rounded once to the element type; a constant species
+ * becomes 0.  patterns, out: device [count][2][n][n] of prec (may alias).
+ * CIL_EINVAL for count < 0, n < 1, count > 65535. */
+int cil_minmax_scale(const void *patterns, int64_t count, int32_t n, cil_precision prec, void *out,
+                     void *hip_stream);
+
+/* Derivative augmentation for the Sobolev norms of Sec. 3.1 (derivatives by
+ * forward differences, h = L / (n - 1) as the grid): pattern p ([2][n][n])
+ * becomes [s (2 n^2) | D_x s (2 n (n-1)) | D_y s (2 n (n-1))] with
+ * D_x s[c][i][j] = (s[c][i][j+1] - s[c][i][j]) / h (j < n - 1) and
+ * D_y s[c][i][j] = (s[c][i+1][j] - s[c][i][j]) / h (i < n - 1), each evaluated
+ * in FP64 and rounded once to the element type.  The W^{1,2} distance of two
+ * patterns is the L2 distance of their augmented vectors (the counting calls
+ * above take them as pattern sets of dimension 2 n^2 + 4 n (n-1)).
+ * out: device [count][2 n^2 + 4 n (n-1)].  CIL_EINVAL for n < 2, L <= 0. */
+int cil_augment_patterns(const void *patterns, int64_t count, int32_t n, double L, cil_precision prec, void *out,
+                         void *hip_stream);
+
+/* Max-abs distances per segment (the L-infinity norms of Sec. 3.1): for each
+ * pair and segment s = [seg_end[s-1], seg_end[s]) (seg_end[-1] = 0),
+ * D[(i nB + j) nseg + s] = max_k |A_ik - B_jk| over the segment, taken over
+ * fl64(|A_ik - B_jk|) -- which is the exact maximum rounded once to double
+ * (rounding is monotone); 0 for an empty segment.  seg_end host[nseg],
+ * non-decreasing, <= dim, 1 <= nseg <= 8.  D device double[nA][nB][nseg]. */
+int cil_pair_maxabs(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                    const int64_t *seg_end, int32_t nseg, double *D, void *hip_stream);
+
+/* out[p] = max (mode 0) or left-to-right FP64 sum (mode 1) of D[p][0..nseg-1]:
+ * W^{1,inf} and the sum variant of Sec. 3.1 from the per-segment maxima. */
+int cil_combine_segments(const double *D, int64_t n, int32_t nseg, int32_t mode, double *out, void *hip_stream);
+
+/* Smallest and largest of n >= 1 non-negative finite distances V (device);
+ * host outputs; synchronises. */
+int cil_value_range(const double *V, int64_t n, double *vmin, double *vmax, void *hip_stream);
+
+/* Correlation sums of distances (not squared): bins[p] = #{m : V[p] <
+ * radii[m]} (device uint8[n] or NULL), counts[m] = #{p : bins[p] >= m + 1}
+ * (host int64[M]).  radii host[M], > 0, strictly decreasing, M <= 255
+ * (a ladder for distances: cil_radii(vmin^2, vmax^2, M, law)). */
+int cil_bin_values(const double *V, int64_t n, const double *radii, int32_t M, uint8_t *bins, int64_t *counts,
+                   void *hip_stream);
+
 /* Bootstrap correlation integral vectors (Alg. 2bst / Alg. 3bst step 2):
  * resample r pairs the kA rows idxA[r][*] with the kB columns idxB[r][*]
  * (repeats allowed) and counts Ycount[r][m] = #{(a,b) : bins[idxA][idxB] > m},

@@ -361,3 +361,89 @@ def gaussian_cost(Y: np.ndarray, y_obs: np.ndarray):
     loglik = -0.5 * f - logdet_half - 0.5 * idx.size * math.log(2.0 * math.pi)
     out.update(f=f, loglik=loglik, ok=True)
     return out
+
+
+# --------------------------------------------------------------------------
+# Further pattern features: the multi-feature CIL of Sec. 3.1 (norms
+# eqs. norm:L2 ... norm:W1infprime) and the min-max scaling of Sec. 5.
+
+def minmax_scale(patterns: np.ndarray) -> np.ndarray:
+    """Sec. 5 min-max normalisation, per pattern and per species:
+    (s - min) / (max - min) over the species' grid, evaluated in FP64 and
+    rounded once to the input's type.  Reading: a constant species (max ==
+    min, the paper divides by zero) becomes 0."""
+    X = np.asarray(patterns)          # [count][2][n][n] or [count][2 n^2]
+    out = np.empty_like(X)
+    flat = X.reshape(X.shape[0], 2, -1)
+    res = out.reshape(flat.shape)
+    for p in range(flat.shape[0]):
+        for c in range(2):
+            v = flat[p, c].astype(np.float64)
+            lo, hi = v.min(), v.max()
+            span = hi - lo
+            res[p, c] = ((v - lo) / span).astype(X.dtype) if span > 0.0 else np.zeros(v.shape, dtype=X.dtype)
+    return out
+
+
+def augment(patterns: np.ndarray, n: int, L: float) -> np.ndarray:
+    """Sec. 3.1: the Sobolev norms use finite-difference derivatives.  Reading:
+    forward differences on the grid of the discretisation (h = L / (n - 1)),
+    per species, along x (within a row) and y (across rows), appended to the
+    pattern: [s | D_x s | D_y s], each value formed in FP64 and rounded once to
+    the input's type.  Then the W^{1,2} distance of two patterns (eq.
+    norm:W12) is the L2 distance of their augmented vectors."""
+    X = np.asarray(patterns)
+    S = X.reshape(-1, 2, n, n)
+    h = L / (n - 1)
+    s64 = S.astype(np.float64)
+    dx = (s64[:, :, :, 1:] - s64[:, :, :, :-1]) / h
+    dy = (s64[:, :, 1:, :] - s64[:, :, :-1, :]) / h
+    parts = [S.reshape(S.shape[0], -1), dx.astype(X.dtype).reshape(S.shape[0], -1),
+             dy.astype(X.dtype).reshape(S.shape[0], -1)]
+    return np.concatenate(parts, axis=1)
+
+
+def pair_maxabs(A, B, seg_end) -> np.ndarray:
+    """Eqs. norm:Linf, norm:W1inf, norm:W1infprime: the L-infinity norm of a
+    difference, per segment [seg_end[s-1], seg_end[s]) of the vectors:
+    D[i, j, s] = max_k |a_k - b_k| with the difference formed in FP64 (0 for an
+    empty segment)."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    ends = [int(e) for e in seg_end]
+    out = np.zeros((A.shape[0], B.shape[0], len(ends)))
+    for i in range(A.shape[0]):
+        prev = 0
+        for s, e in enumerate(ends):
+            if e > prev:
+                out[i, :, s] = np.abs(B[:, prev:e] - A[i, prev:e]).max(axis=1)
+            prev = e
+    return out
+
+
+def combine_segments(D: np.ndarray, mode: int) -> np.ndarray:
+    """W^{1,inf} (eq. norm:W1inf: the largest of the per-derivative maxima,
+    mode 0) and its variant with a sum (eq. norm:W1infprime, mode 1, summed
+    left to right in FP64)."""
+    D = np.asarray(D, dtype=np.float64)
+    v = D[..., 0].copy()
+    for s in range(1, D.shape[-1]):
+        v = np.maximum(v, D[..., s]) if mode == 0 else v + D[..., s]
+    return v
+
+
+def bins_from_values(V: np.ndarray, radii) -> np.ndarray:
+    """Eq. eCDF for distances that are not squared: per pair the number of
+    radii it lies under, #{m : V < R_m}."""
+    V = np.asarray(V, dtype=np.float64)
+    r = np.asarray(radii, dtype=np.float64)
+    out = np.zeros(V.shape, dtype=np.uint8)
+    for m in range(r.size):
+        out += (V < r[m]).astype(np.uint8)
+    return out
+
+
+def counts_from_values(V: np.ndarray, radii) -> np.ndarray:
+    """C(R_m) numerators of eq. eCDF for distances: #{pairs : V < R_m}."""
+    V = np.asarray(V, dtype=np.float64)
+    return np.array([int((V < float(r)).sum()) for r in np.asarray(radii, dtype=np.float64)], dtype=np.int64)

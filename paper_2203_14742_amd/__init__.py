@@ -98,6 +98,12 @@ def lib() -> ctypes.CDLL:
         L.cil_profile.argtypes = [i32]
         L.cil_profile_read.argtypes = [ctypes.c_char_p, vp, vp]
         L.cil_profile_names.argtypes = [vp, i64]
+        L.cil_minmax_scale.argtypes = [vp, i64, i32, ctypes.c_int, vp, vp]
+        L.cil_augment_patterns.argtypes = [vp, i64, i32, dbl, ctypes.c_int, vp, vp]
+        L.cil_pair_maxabs.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, i32, vp, vp]
+        L.cil_combine_segments.argtypes = [vp, i64, i32, i32, vp, vp]
+        L.cil_value_range.argtypes = [vp, i64, vp, vp, vp]
+        L.cil_bin_values.argtypes = [vp, i64, vp, i32, vp, vp, vp]
         L.cil_sim_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, vp, vp]
         L.cil_sim_plan_tune.argtypes = [vp, i64, vp]
         L.cil_sim_plan_launch.argtypes = [vp, vp]
@@ -110,7 +116,8 @@ def lib() -> ctypes.CDLL:
                      "cil_bootstrap_features", "cil_gaussian_loglik", "cil_set_option", "cil_shutdown",
                      "cil_profile", "cil_profile_read", "cil_profile_names", "cil_sim_plan_create",
                      "cil_sim_plan_tune", "cil_sim_plan_launch", "cil_sim_plan_report", "cil_sim_plan_groups",
-                     "cil_sim_plan_group_info", "cil_sim_plan_destroy"):
+                     "cil_sim_plan_group_info", "cil_sim_plan_destroy", "cil_minmax_scale", "cil_augment_patterns",
+                     "cil_pair_maxabs", "cil_combine_segments", "cil_value_range", "cil_bin_values"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -417,6 +424,70 @@ def cil_gaussian_loglik(Y, y_obs):
     _check(lib().cil_gaussian_loglik(_dev(Y, "Y"), P, n, M, _dev(y_obs, "y_obs"), _dev(f, "f"), _dev(ll, "loglik"),
                                      _dev(me, "m_eff"), _dev(stt, "status"), _stream(Y)))
     return f, ll, me, stt
+
+
+# ------------------------------------------------ further features (Sec. 3.1)
+
+def cil_minmax_scale(patterns, n: int, out=None):
+    """Per pattern and species: (s - min) / (max - min) (FP64, rounded once)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(patterns)
+    count = patterns.numel() // (2 * n * n)
+    _check(lib().cil_minmax_scale(_dev(patterns, "patterns"), count, n, _prec(patterns), _dev(out, "out"),
+                                  _stream(patterns)))
+    return out
+
+
+def augmented_dim(n: int) -> int:
+    return 2 * n * n + 4 * n * (n - 1)
+
+
+def cil_augment_patterns(patterns, n: int, L: float):
+    """[s | D_x s | D_y s] per pattern (forward differences, h = L / (n - 1))."""
+    import torch
+    count = patterns.numel() // (2 * n * n)
+    out = torch.empty((count, augmented_dim(n)), dtype=patterns.dtype, device=patterns.device)
+    _check(lib().cil_augment_patterns(_dev(patterns, "patterns"), count, n, float(L), _prec(patterns),
+                                      _dev(out, "out"), _stream(patterns)))
+    return out
+
+
+def cil_pair_maxabs(A, B, seg_end):
+    """D[i, j, s] = max over segment s of |A_ik - B_jk| (FP64, exact max rounded once)."""
+    import torch
+    A2, B2 = _sets(A, B)
+    se = _arr(seg_end, np.int64)
+    D = torch.empty((A2.shape[0], B2.shape[0], se.size), dtype=torch.float64, device=A2.device)
+    _check(lib().cil_pair_maxabs(_dev(A2, "A"), A2.shape[0], _dev(B2, "B"), B2.shape[0], A2.shape[1], _prec(A2),
+                                 se.ctypes.data, se.size, _dev(D, "D"), _stream(A2)))
+    return D
+
+
+def cil_combine_segments(D, mode: int):
+    """max (mode 0) or left-to-right sum (mode 1) over the last axis of D."""
+    import torch
+    nseg = D.shape[-1]
+    out = torch.empty(D.shape[:-1], dtype=torch.float64, device=D.device)
+    _check(lib().cil_combine_segments(_dev(D, "D"), out.numel(), nseg, int(mode), _dev(out, "out"), _stream(D)))
+    return out
+
+
+def cil_value_range(V):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().cil_value_range(_dev(V, "V"), V.numel(), ctypes.byref(lo), ctypes.byref(hi), _stream(V)))
+    return lo.value, hi.value
+
+
+def cil_bin_values(V, radii, want_bins: bool = True):
+    """bins = #{m : V < R_m} (uint8, V's shape), counts[m] = #{bins >= m + 1}."""
+    import torch
+    r = _arr(radii, np.float64)
+    bins = torch.empty(V.shape, dtype=torch.uint8, device=V.device) if want_bins else None
+    counts = np.zeros(r.size, dtype=np.int64)
+    _check(lib().cil_bin_values(_dev(V, "V"), V.numel(), r.ctypes.data, r.size,
+                                None if bins is None else _dev(bins, "bins"), counts.ctypes.data, _stream(V)))
+    return bins, counts
 
 
 def cil_set_option(option: int, value: int):

@@ -576,6 +576,70 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M, c
     return loglik_impl(Y, P, n_boot, M, y_obs, f, loglik, m_eff, status, (hipStream_t)hip_stream);
 }
 
+int cil_minmax_scale(const void *patterns, int64_t count, int32_t n, cil_precision prec, void *out, void *hip_stream)
+{
+    API_BEGIN();
+    if (count < 0 || n < 1) return set_error(CIL_EINVAL, "need count >= 0, n >= 1");
+    if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
+    if (count > 0 && (!patterns || !out)) return set_error(CIL_EINVAL, "null pointer");
+    if (count > 65535) return set_error(CIL_EINVAL, "count > 65535");
+    CIL_TRY(check_device());
+    return minmax_scale_impl(patterns, count, n, prec, out, (hipStream_t)hip_stream);
+}
+
+int cil_augment_patterns(const void *patterns, int64_t count, int32_t n, double L, cil_precision prec, void *out,
+                         void *hip_stream)
+{
+    API_BEGIN();
+    if (count < 0 || n < 2) return set_error(CIL_EINVAL, "need count >= 0, n >= 2");
+    if (!(L > 0.0) || !std::isfinite(L)) return set_error(CIL_EINVAL, "L must be > 0");
+    if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
+    if (count > 0 && (!patterns || !out)) return set_error(CIL_EINVAL, "null pointer");
+    if (count > 65535) return set_error(CIL_EINVAL, "count > 65535");
+    CIL_TRY(check_device());
+    return augment_impl(patterns, count, n, L, prec, out, (hipStream_t)hip_stream);
+}
+
+int cil_pair_maxabs(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
+                    const int64_t *seg_end, int32_t nseg, double *D, void *hip_stream)
+{
+    API_BEGIN();
+    if (nA < 0 || nB < 0 || dim < 0) return set_error(CIL_EINVAL, "negative size");
+    if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
+    if (!seg_end) return set_error(CIL_EINVAL, "null segment ends");
+    if (nA * nB > 0 && (!setA || !setB || !D)) return set_error(CIL_EINVAL, "null pointer");
+    if ((nA + 63) / 64 > 65535) return set_error(CIL_EINVAL, "nA too large");
+    CIL_TRY(check_device());
+    return pair_maxabs_impl(setA, nA, setB, nB, dim, prec, seg_end, nseg, D, (hipStream_t)hip_stream);
+}
+
+int cil_combine_segments(const double *D, int64_t n, int32_t nseg, int32_t mode, double *out, void *hip_stream)
+{
+    API_BEGIN();
+    if (n < 0 || nseg < 1 || (mode != 0 && mode != 1)) return set_error(CIL_EINVAL, "need n >= 0, nseg >= 1, mode 0/1");
+    if (n > 0 && (!D || !out)) return set_error(CIL_EINVAL, "null pointer");
+    CIL_TRY(check_device());
+    return combine_segments_impl(D, n, nseg, mode, out, (hipStream_t)hip_stream);
+}
+
+int cil_value_range(const double *V, int64_t n, double *vmin, double *vmax, void *hip_stream)
+{
+    API_BEGIN();
+    if (n < 1 || !V || !vmin || !vmax) return set_error(CIL_EINVAL, "need n >= 1 and non-null pointers");
+    CIL_TRY(check_device());
+    return value_range_impl(V, n, vmin, vmax, (hipStream_t)hip_stream);
+}
+
+int cil_bin_values(const double *V, int64_t n, const double *radii, int32_t M, uint8_t *bins, int64_t *counts,
+                   void *hip_stream)
+{
+    API_BEGIN();
+    if (n < 0 || (n > 0 && !V) || !counts) return set_error(CIL_EINVAL, "bad arguments");
+    if (!radii_ok(radii, M, 255)) return set_error(CIL_EINVAL, "radii must be > 0, finite, strictly decreasing, M <= 255");
+    CIL_TRY(check_device());
+    return bin_values_impl(V, n, radii, M, bins, counts, (hipStream_t)hip_stream);
+}
+
 int cil_set_option(int32_t option, int64_t value)
 {
     API_BEGIN();

@@ -38,7 +38,7 @@ enum WsSlot {
     WS_STEP_SOLVES = 0, WS_STEP_LIST, WS_STEP_RESID, WS_STEP_TABLES, WS_STEP_WORK_A,
     WS_STEP_WORK_B, WS_STEP_STATE64, WS_STEP_LIST64, WS_STEP_DCT,
     WS_DIST_NORMS, WS_DIST_SPLIT_A, WS_DIST_SPLIT_B, WS_DIST_RECHECK, WS_DIST_COUNTS,
-    WS_DIST_MISC, WS_DIST_SAMPLE, WS_BOOT_MISC, WS_BOOT_MULT, WS_STATS_MISC,
+    WS_DIST_MISC, WS_DIST_SAMPLE, WS_BOOT_MISC, WS_BOOT_MULT, WS_STATS_MISC, WS_FEAT_MISC, WS_FEAT_SEG,
     WS_NUM_SLOTS
 };
 int ws_get(int slot, size_t bytes, void **ptr);
@@ -110,6 +110,16 @@ constexpr double ce_cospi(long p, long q)
 }
 
 constexpr double ce_sinpi(long p, long q) { return ce_cospi(q - 2 * p, 2 * q); }
+
+// Pattern features beyond L2 (features.hip).
+int minmax_scale_impl(const void *X, long long count, int n, cil_precision prec, void *Y, hipStream_t st);
+int augment_impl(const void *X, long long count, int n, double L, cil_precision prec, void *Y, hipStream_t st);
+int pair_maxabs_impl(const void *A, long long nA, const void *B, long long nB, long long dim, cil_precision prec,
+                     const int64_t *seg_end, int nseg, double *D, hipStream_t st);
+int combine_segments_impl(const double *D, long long n, int nseg, int mode, double *out, hipStream_t st);
+int value_range_impl(const double *V, long long n, double *vmin, double *vmax, hipStream_t st);
+int bin_values_impl(const double *V, long long n, const double *radii, int M, uint8_t *bins, int64_t *counts,
+                    hipStream_t st);
 
 // Gram FP32 -> FP64 promotion interval (gram.hip), shared with the error bound.
 int gram_flush_interval();

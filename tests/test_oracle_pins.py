@@ -424,3 +424,104 @@ def test_nonspd_covariance_reports_failure(oracle_mod):
         assert not r["ok"] and math.isnan(r["f"])
     with pytest.raises(np.linalg.LinAlgError):
         o.cholesky(np.array([[1.0, 2.0], [2.0, 1.0]]))          # indefinite
+
+
+# ------------------------------------------------ further features (Sec. 3.1, Sec. 5)
+
+def test_minmax_scale_pins(oracle_mod):
+    """Sec. 5 normalisation: a hand example, invariance under a positive affine
+    map of the data, the constant-species reading, range [0, 1] attained."""
+    o = oracle_mod
+    x = np.array([[[[2.0, 4.0], [6.0, 10.0]], [[-1.0, -1.0], [-1.0, -1.0]]]])
+    y = o.minmax_scale(x)
+    assert np.array_equal(y[0, 0], np.array([[0.0, 0.25], [0.5, 1.0]]))
+    assert np.array_equal(y[0, 1], np.zeros((2, 2)))
+    g = np.random.default_rng(3)
+    z = g.integers(-50, 50, size=(3, 2, 5, 5)).astype(np.float64)
+    assert np.array_equal(o.minmax_scale(z), o.minmax_scale(4.0 * z + 8.0))   # exact: integer data, power-of-2 scale
+    s = o.minmax_scale(z)
+    for p in range(3):
+        for c in range(2):
+            assert s[p, c].min() == 0.0 and s[p, c].max() == 1.0
+    assert o.minmax_scale(z.astype(np.float32)).dtype == np.float32
+
+
+def test_augment_pins(oracle_mod):
+    """Forward differences are exact on linear data and give 2j + 1 on j^2
+    (h = 1); layout [s | D_x | D_y] with the stated sizes."""
+    o = oracle_mod
+    n = 5
+    j = np.arange(n, dtype=np.float64)
+    ramp_x = np.broadcast_to(j, (n, n))                     # s[i][j] = j
+    ramp_y = ramp_x.T.copy()                                # s[i][j] = i
+    a = o.augment(np.stack([ramp_x, ramp_y])[None], n, L=n - 1.0)
+    ne = n * (n - 1)
+    assert a.shape == (1, 2 * n * n + 4 * ne)
+    dx, dy = a[0, 2 * n * n: 2 * n * n + 2 * ne], a[0, 2 * n * n + 2 * ne:]
+    assert np.array_equal(dx[:ne], np.ones(ne)) and np.array_equal(dx[ne:], np.zeros(ne))
+    assert np.array_equal(dy[:ne], np.zeros(ne)) and np.array_equal(dy[ne:], np.ones(ne))
+    q = np.broadcast_to(j * j, (n, n))
+    a = o.augment(np.stack([q, q])[None], n, L=n - 1.0)
+    assert np.array_equal(a[0, 2 * n * n: 2 * n * n + n - 1], 2 * j[:-1] + 1)
+    # h = L / (n - 1): doubling L halves the differences exactly
+    a2 = o.augment(np.stack([q, q])[None], n, L=2 * (n - 1.0))
+    assert np.array_equal(a2[0, 2 * n * n:], a[0, 2 * n * n:] / 2)
+
+
+def test_w12_is_the_l2_distance_of_augmented_vectors(oracle_mod):
+    """Eq. norm:W12: ||u||^2 + ||D_x u||^2 + ||D_y u||^2 computed part by part
+    equals the squared L2 distance of the augmented vectors."""
+    o = oracle_mod
+    g = np.random.default_rng(4)
+    n = 6
+    A = g.standard_normal((3, 2, n, n))
+    B = g.standard_normal((2, 2, n, n))
+    Aa, Ba = o.augment(A, n, 1.0), o.augment(B, n, 1.0)
+    D = o.pair_d2(Aa, Ba)
+    h = 1.0 / (n - 1)
+    for i in range(3):
+        for k in range(2):
+            u = A[i] - B[k]
+            parts = (u ** 2).sum() + (((u[:, :, 1:] - u[:, :, :-1]) / h) ** 2).sum() + \
+                (((u[:, 1:, :] - u[:, :-1, :]) / h) ** 2).sum()
+            assert D[i, k] == pytest.approx(parts, rel=1e-12)
+
+
+def test_pair_maxabs_brute_force(oracle_mod):
+    """Eqs. norm:Linf / norm:W1inf / norm:W1infprime on tiny sets, against
+    pure-Python loops; identical vectors give 0, one changed element gives
+    its change; an empty segment gives 0."""
+    o = oracle_mod
+    g = np.random.default_rng(5)
+    A = g.standard_normal((3, 11))
+    B = g.standard_normal((4, 11))
+    ends = [4, 4, 9, 11]
+    D = o.pair_maxabs(A, B, ends)
+    for i in range(3):
+        for j in range(4):
+            prev = 0
+            for s, e in enumerate(ends):
+                want = max((abs(float(A[i, k]) - float(B[j, k])) for k in range(prev, e)), default=0.0)
+                assert D[i, j, s] == want
+                prev = e
+    C = A.copy()
+    C[1, 7] += 0.5
+    D2 = o.pair_maxabs(A, C, [11])
+    assert D2[0, 0, 0] == 0.0 and D2[1, 1, 0] == abs((A[1, 7] + 0.5) - A[1, 7])
+    W = o.combine_segments(D, 0)
+    S = o.combine_segments(D, 1)
+    assert np.array_equal(W, np.max(D, axis=2))
+    assert np.array_equal(S, ((D[..., 0] + D[..., 1]) + D[..., 2]) + D[..., 3])
+
+
+def test_bins_from_values_brute_force(oracle_mod):
+    o = oracle_mod
+    g = np.random.default_rng(6)
+    V = g.random(200)
+    r = np.array([0.9, 0.5, 0.25, 0.1])
+    V[:4] = r                                       # ties: strict, a value at R_m is not under it
+    b = o.bins_from_values(V, r)
+    for p in range(V.size):
+        assert b[p] == sum(1 for m in range(r.size) if V[p] < r[m])
+    c = o.counts_from_values(V, r)
+    assert np.array_equal(c, np.array([(b >= m + 1).sum() for m in range(r.size)]))
