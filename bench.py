@@ -605,9 +605,10 @@ def mcil_main(args):
     radii, bins and 200 bootstrap vectors -- L2 and W^{1,2} through the
     split-bf16x3 Gram path (patterns / augmented vectors), L-inf, W^{1,inf} and
     its sum variant from the per-segment max-abs distances of the augmented
-    vectors -- and the likelihood of the concatenated 60-entry vector.  With
-    --scaled the patterns are min-max scaled first (Sec. 5).  `value` is
-    distance pairs/s (pairs of patterns, all five norms)."""
+    vectors, the sum-of-L2 W^{1,2} variant from per-part canonical squared
+    distances of all pairs -- and the likelihood of the concatenated 60-entry
+    vector.  With --scaled the patterns are min-max scaled first (Sec. 5).
+    `value` is distance pairs/s (pairs of patterns, all six norms)."""
     import numpy as np
     import torch
 
@@ -626,6 +627,8 @@ def mcil_main(args):
     nn2, ne2 = 2 * n * n, 2 * n * (n - 1)
     ends = [nn2, nn2 + ne2, nn2 + 2 * ne2]
     pairs = half * half
+    ii = torch.arange(half, device=dev).repeat_interleave(half)
+    jj = torch.arange(half, device=dev).repeat(half)
 
     def one_step():
         P = cil.cil_minmax_scale(raw, n) if args.scaled else raw
@@ -635,7 +638,12 @@ def mcil_main(args):
             _, _, _, bins, _ = cil.cil_pair_bins_adaptive(X[:half], X[half:], M)
             Ys.append(cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)[1])
         D = cil.cil_pair_maxabs(Aug[:half], Aug[half:], ends)
-        for V in (D[..., 0].contiguous(), cil.cil_combine_segments(D, 0), cil.cil_combine_segments(D, 1)):
+        parts = []
+        for a, b in zip([0] + ends[:-1], ends):
+            Xs = Aug[:, a:b].contiguous()
+            parts.append(cil.cil_canonical_d2(Xs[:half], Xs[half:], ii, jj).reshape(half, half))
+        Wsum = cil.cil_combine_segments(torch.stack(parts, dim=-1).contiguous(), 2)
+        for V in (D[..., 0].contiguous(), cil.cil_combine_segments(D, 0), cil.cil_combine_segments(D, 1), Wsum):
             lo, hi = cil.cil_value_range(V)
             bins, _ = cil.cil_bin_values(V, cil.cil_radii(lo * lo, hi * hi, M))
             Ys.append(cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)[1])
@@ -670,7 +678,8 @@ def mcil_main(args):
         "ms_per_step": round(1e3 * el / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "mcil_stripes64", "patterns": count, "n": n, "dim": nn2, "augmented_dim": daug,
-                   "pairs_per_step": pairs, "norms": ["L2", "Linf", "W12", "W1inf", "W1inf_sum"], "radii": M,
+                   "pairs_per_step": pairs, "norms": ["L2", "W12", "Linf", "W1inf", "W1inf_sum", "W12_sum"],
+                   "radii": M,
                    "bootstrap": n_boot, "scaled": bool(args.scaled), "parallelism": "none (1 GPU)"},
         "features": int(Y.shape[1]), "m_eff": int(out[2].cpu()[0]), "loglik_status": int(out[3].cpu()[0]),
         "roofline": roof,

@@ -178,9 +178,9 @@ WORKLOADS = {
     # halves of 2048, 32 power-law radii, 200 bootstrap resamples of the halves.
     "features4096": dict(count=4096, n=128, M=32, n_boot=200, seeds=(5,), boot_seed=6),
     # Multi-feature CIL (Sec. 3.1): 500 stand-in patterns of side 64, halves of
-    # 250, five norms (L2, L-inf, W^{1,2}, W^{1,inf}, its sum variant) with 12
-    # radii each, 200 bootstrap resamples; optionally min-max scaled (Sec. 5).
-    "mcil_stripes64": dict(count=500, n=64, L=1.0, M=12, n_boot=200, seed=23, boot_seed=24),
+    # 250, the six norms of Sec. 3.1 with 10 radii each (a 60-entry vector), 200
+    # bootstrap resamples; optionally min-max scaled (Sec. 5).
+    "mcil_stripes64": dict(count=500, n=64, L=1.0, M=10, n_boot=200, seed=23, boot_seed=24),
     # Uneven batch: 2048 Brusselator solves, sides 32/64/128 in turn, each with
     # its own (A, B, Du, Dv) around Table exp1's point, FP32, T = 100 at dt = 0.05.
     "bz_uneven2048": dict(model=BRUSSELATOR, count=2048, sides=(32, 64, 128), L=1.0, dt=0.05, max_steps=2000,

@@ -300,8 +300,11 @@ int cil_augment_patterns(const void *patterns, int64_t count, int32_t n, double 
 int cil_pair_maxabs(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim, cil_precision prec,
                     const int64_t *seg_end, int32_t nseg, double *D, void *hip_stream);
 
-/* out[p] = max (mode 0) or left-to-right FP64 sum (mode 1) of D[p][0..nseg-1]:
- * W^{1,inf} and the sum variant of Sec. 3.1 from the per-segment maxima. */
+/* out[p] over D[p][0..nseg-1]: max (mode 0), left-to-right FP64 sum (mode 1),
+ * or left-to-right sum of the correctly rounded square roots (mode 2):
+ * W^{1,inf} and its sum variant from per-segment maxima (eqs. norm:W1inf,
+ * norm:W1infprime), and the sum-of-L2 W^{1,2} variant (eq. norm:W12prime)
+ * from per-segment canonical squared distances (cil_canonical_d2). */
 int cil_combine_segments(const double *D, int64_t n, int32_t nseg, int32_t mode, double *out, void *hip_stream);
 
 /* Smallest and largest of n >= 1 non-negative finite distances V (device);

@@ -423,12 +423,15 @@ def pair_maxabs(A, B, seg_end) -> np.ndarray:
 
 def combine_segments(D: np.ndarray, mode: int) -> np.ndarray:
     """W^{1,inf} (eq. norm:W1inf: the largest of the per-derivative maxima,
-    mode 0) and its variant with a sum (eq. norm:W1infprime, mode 1, summed
-    left to right in FP64)."""
+    mode 0), its variant with a sum (eq. norm:W1infprime, mode 1, summed left
+    to right in FP64), and the sum-of-L2 W^{1,2} variant (eq. norm:W12prime,
+    mode 2: from per-part squared distances, the sum of their square roots,
+    left to right)."""
     D = np.asarray(D, dtype=np.float64)
-    v = D[..., 0].copy()
+    f = np.sqrt if mode == 2 else (lambda x: x)
+    v = f(D[..., 0]).copy()
     for s in range(1, D.shape[-1]):
-        v = np.maximum(v, D[..., s]) if mode == 0 else v + D[..., s]
+        v = np.maximum(v, D[..., s]) if mode == 0 else v + f(D[..., s])
     return v
 
 

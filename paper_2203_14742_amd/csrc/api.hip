@@ -616,7 +616,7 @@ int cil_pair_maxabs(const void *setA, int64_t nA, const void *setB, int64_t nB, 
 int cil_combine_segments(const double *D, int64_t n, int32_t nseg, int32_t mode, double *out, void *hip_stream)
 {
     API_BEGIN();
-    if (n < 0 || nseg < 1 || (mode != 0 && mode != 1)) return set_error(CIL_EINVAL, "need n >= 0, nseg >= 1, mode 0/1");
+    if (n < 0 || nseg < 1 || mode < 0 || mode > 2) return set_error(CIL_EINVAL, "need n >= 0, nseg >= 1, mode 0..2");
     if (n > 0 && (!D || !out)) return set_error(CIL_EINVAL, "null pointer");
     CIL_TRY(check_device());
     return combine_segments_impl(D, n, nseg, mode, out, (hipStream_t)hip_stream);

@@ -159,14 +159,15 @@ __global__ __launch_bounds__(256) void k_pair_maxabs(const T *A, long long nA, c
     }
 }
 
-// out[p] = max or left-to-right sum of D[p][0..nseg-1]
+// out[p] over D[p][0..nseg-1]: mode 0 max, 1 left-to-right sum, 2 left-to-right
+// sum of the (correctly rounded) square roots
 __global__ void k_combine(const double *D, long long n, int nseg, int mode, double *out)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const double *d = D + p * nseg;
-    double v = d[0];
-    for (int s = 1; s < nseg; ++s) v = mode == 0 ? fmax(v, d[s]) : v + d[s];
+    double v = mode == 2 ? sqrt(d[0]) : d[0];
+    for (int s = 1; s < nseg; ++s) v = mode == 0 ? fmax(v, d[s]) : v + (mode == 2 ? sqrt(d[s]) : d[s]);
     out[p] = v;
 }
 

@@ -2,8 +2,9 @@
 against the oracle: min-max scaling, derivative augmentation, per-segment
 max-abs distances and their combinations, distance ranges and bins, all
 bit-exact; W^{1,2} counts through the Gram path on augmented vectors,
-bit-exact; the concatenated five-norm bootstrap vectors bit-exact and their
-likelihood within 1e-10.
+bit-exact; the sum-of-L2 W^{1,2} variant from per-part canonical squared
+distances, bit-exact; the concatenated six-norm bootstrap vectors bit-exact
+and their likelihood within 1e-10.
 """
 import numpy as np
 import pytest
@@ -56,7 +57,7 @@ def test_pair_maxabs_bit_exact(cil, oracle_mod, dtype, nA, nB, ends):
     D = cil.cil_pair_maxabs(dev(A), dev(B), ends)
     want = oracle_mod.pair_maxabs(A, B, ends)
     assert np.array_equal(D.cpu().numpy(), want)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         assert np.array_equal(cil.cil_combine_segments(D, mode).cpu().numpy(), oracle_mod.combine_segments(want, mode))
 
 
@@ -87,14 +88,23 @@ def test_feature_argument_errors(cil):
 
 
 def mcil_features(cil, P, n, L, M, ia, ib):
-    """Five-norm bootstrap vectors on the GPU: L2, L-inf, W^{1,2}, W^{1,inf} and
-    its sum variant, each with its own adaptive radii (Sec. 3.2)."""
+    """Six-norm bootstrap vectors on the GPU: L2, L-inf, W^{1,2}, W^{1,inf}, its
+    sum variant and the sum-of-L2 W^{1,2} variant, each with its own adaptive
+    radii (Sec. 3.2)."""
     half = P.shape[0] // 2
     nn2 = 2 * n * n
     ne2 = 2 * n * (n - 1)
     Aug = cil.cil_augment_patterns(P, n, L)
     Ys, radii_all = [], []
     tA, tB = torch.from_numpy(ia), torch.from_numpy(ib)
+    # per-part canonical squared distances of all pairs, for the sum-of-L2 variant
+    ii = torch.arange(half, device="cuda").repeat_interleave(half)
+    jj = torch.arange(half, device="cuda").repeat(half)
+    parts = []
+    for a, b in ((0, nn2), (nn2, nn2 + ne2), (nn2 + ne2, nn2 + 2 * ne2)):
+        Xs = Aug[:, a:b].contiguous()
+        parts.append(cil.cil_canonical_d2(Xs[:half], Xs[half:], ii, jj).reshape(half, half))
+    Wsum = cil.cil_combine_segments(torch.stack(parts, dim=-1).contiguous(), 2)
     # L2 and W^{1,2}: squared distances through the counting path
     for X in (P.reshape(P.shape[0], -1), Aug):
         _, _, radii, bins, _ = cil.cil_pair_bins_adaptive(X[:half], X[half:], M)
@@ -103,7 +113,7 @@ def mcil_features(cil, P, n, L, M, ia, ib):
         radii_all.append(radii)
     # the max-abs family from per-segment maxima of the augmented vectors
     D = cil.cil_pair_maxabs(Aug[:half], Aug[half:], [nn2, nn2 + ne2, nn2 + 2 * ne2])
-    for V in (D[..., 0].contiguous(), cil.cil_combine_segments(D, 0), cil.cil_combine_segments(D, 1)):
+    for V in (D[..., 0].contiguous(), cil.cil_combine_segments(D, 0), cil.cil_combine_segments(D, 1), Wsum):
         lo, hi = cil.cil_value_range(V)
         radii = cil.cil_radii(lo * lo, hi * hi, M)
         bins, _ = cil.cil_bin_values(V, radii)
@@ -126,7 +136,9 @@ def oracle_mcil(o, Pn, n, L, M, ia, ib):
         Ys.append(Y)
         radii_all.append(radii)
     Dm = o.pair_maxabs(Aug[:half], Aug[half:], [nn2, nn2 + ne2, nn2 + 2 * ne2])
-    for V in (Dm[..., 0], o.combine_segments(Dm, 0), o.combine_segments(Dm, 1)):
+    parts = np.stack([o.pair_d2(Aug[:half, a:b], Aug[half:, a:b], nthreads=8)
+                      for a, b in ((0, nn2), (nn2, nn2 + ne2), (nn2 + ne2, nn2 + 2 * ne2))], axis=-1)
+    for V in (Dm[..., 0], o.combine_segments(Dm, 0), o.combine_segments(Dm, 1), o.combine_segments(parts, 2)):
         radii = o.radii_ladder(V.min() ** 2, V.max() ** 2, M)
         # bootstrap on distances: the squared values keep the order and the
         # radii ladder's squares decide the same bins
@@ -142,7 +154,7 @@ def oracle_mcil(o, Pn, n, L, M, ia, ib):
 
 @pytest.mark.parametrize("scaled", [False, True])
 def test_multi_feature_vectors_and_likelihood(cil, oracle_mod, scaled):
-    n, L, M, count, n_boot = 32, 1.0, 12, 64, 60
+    n, L, M, count, n_boot = 32, 1.0, 10, 64, 60
     P = cs.stripe_patterns(count, n, seed=21).astype(np.float32)
     if scaled:
         P = oracle_mod.minmax_scale(P)

@@ -510,8 +510,13 @@ def test_pair_maxabs_brute_force(oracle_mod):
     assert D2[0, 0, 0] == 0.0 and D2[1, 1, 0] == abs((A[1, 7] + 0.5) - A[1, 7])
     W = o.combine_segments(D, 0)
     S = o.combine_segments(D, 1)
+    R = o.combine_segments(D, 2)
     assert np.array_equal(W, np.max(D, axis=2))
     assert np.array_equal(S, ((D[..., 0] + D[..., 1]) + D[..., 2]) + D[..., 3])
+    for i in range(3):
+        for j in range(4):
+            want = ((math.sqrt(D[i, j, 0]) + math.sqrt(D[i, j, 1])) + math.sqrt(D[i, j, 2])) + math.sqrt(D[i, j, 3])
+            assert R[i, j] == want
 
 
 def test_bins_from_values_brute_force(oracle_mod):
@@ -525,3 +530,24 @@ def test_bins_from_values_brute_force(oracle_mod):
         assert b[p] == sum(1 for m in range(r.size) if V[p] < r[m])
     c = o.counts_from_values(V, r)
     assert np.array_equal(c, np.array([(b >= m + 1).sum() for m in range(r.size)]))
+
+
+def test_w12_sum_variant_from_part_distances(oracle_mod):
+    """Eq. norm:W12prime: ||u|| + ||D_x u|| + ||D_y u|| equals the sum of the
+    square roots of the per-part squared distances of augmented vectors."""
+    o = oracle_mod
+    g = np.random.default_rng(7)
+    n = 5
+    A = g.standard_normal((2, 2, n, n))
+    B = g.standard_normal((3, 2, n, n))
+    Aa, Ba = o.augment(A, n, 2.0), o.augment(B, n, 2.0)
+    e = [2 * n * n, 2 * n * n + 2 * n * (n - 1), 2 * n * n + 4 * n * (n - 1)]
+    parts = np.stack([o.pair_d2(Aa[:, a:b], Ba[:, a:b]) for a, b in zip([0] + e[:-1], e)], axis=-1)
+    W = o.combine_segments(parts, 2)
+    h = 2.0 / (n - 1)
+    for i in range(2):
+        for k in range(3):
+            u = A[i] - B[k]
+            want = np.sqrt((u ** 2).sum()) + np.sqrt((((u[:, :, 1:] - u[:, :, :-1]) / h) ** 2).sum()) + \
+                np.sqrt((((u[:, 1:, :] - u[:, :-1, :]) / h) ** 2).sum())
+            assert W[i, k] == pytest.approx(want, rel=1e-12)
