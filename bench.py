@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "fhn32_fixed5000", "features4096", "mcil_stripes64", "bz_uneven2048",
-                             "fhn128_mcmc"],
+                             "fhn128_mcmc", "fhn128_de"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -160,6 +160,9 @@ def main():
         return
     if args.workload == "fhn128_mcmc":
         mcmc_main(args)
+        return
+    if args.workload == "fhn128_de":
+        de_main(args)
         return
 
     import cil_synth as cs
@@ -779,6 +782,62 @@ def mcmc_main(args):
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def de_main(args):
+    """Differential evolution on the synthetic likelihood (Sec. 5's
+    pre-optimisation): 20 candidates per generation, each generation one
+    batched cost evaluation of 20 proposals x 64 synthetic FitzHugh-Nagumo
+    patterns (128 x 128, 2000 FP32 steps) through `inference.SyntheticCIL`.
+    The timed region is one DE run of `--steps` generations (plus its initial
+    population); `value` is synthetic patterns/s."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+    from paper_2203_14742_amd.inference import SyntheticCIL, differential_evolution
+
+    w = cs.WORKLOADS["fhn128_mcmc"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pop, nsyn, nset, nboot, M, n = w["window"], w["n_syn"], w["n_set"], w["n_boot"], w["M"], w["n"]
+    p0 = (w["theta0"][0], w["theta0"][1], w["alpha"])
+    base = cil.cil_homogeneous_state(w["model"], p0)
+    data = torch.tensor(cs.initial_conditions(base, n, nset, seed=w["data_seed"]), dtype=torch.float32, device=dev)
+    cil.cil_simulate_patterns(w["model"], data, cil.make_problems(n, w["L"], w["nu"], p0, count=nset), w["dt"],
+                              w["max_steps"], check_every=w["max_steps"])
+    scil = SyntheticCIL(w["model"], n, w["L"], w["nu"], lambda t: (t[0], t[1], w["alpha"]), data.reshape(nset, -1),
+                        nsyn, nboot, M, w["dt"], w["max_steps"],
+                        cs.initial_conditions(base, n, nsyn, seed=w["ic_seed"]),
+                        cs.resample_synthetic(nsyn, nset, nboot, seed=w["boot_seed"]))
+    t0v = np.asarray(w["theta0"], dtype=np.float64)
+    bounds = [(0.8 * t0v[0], 1.2 * t0v[0]), (0.8 * t0v[1], 1.2 * t0v[1])]
+    cost = lambda X: scil.costs(X)[0]
+    if args.warmup > 0:
+        differential_evolution(cost, bounds, pop=pop, generations=args.warmup - 1, seed=99)
+    torch.cuda.synchronize()
+    K = args.steps
+    t0 = time.perf_counter()
+    r = differential_evolution(cost, bounds, pop=pop, generations=K, seed=w["proposal_seed"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    evals = K + 1
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(pop * nsyn * evals / el, 2), "unit": "patterns/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el / evals, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fhn128_de", "candidates": pop, "generations_timed": K,
+                   "batched_evaluations_timed": evals, "synthetic_per_proposal": nsyn, "data_patterns": nset,
+                   "grid": n, "steps_per_solve": w["max_steps"], "bootstrap": nboot, "radii": M,
+                   "parallelism": "none (1 GPU)"},
+        "generations_per_s": round(evals / el, 4),
+        "best_cost_history": [round(h, 6) for h in r["history"]],
+        "best_theta": [round(float(v), 6) for v in r["x"]],
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -1,0 +1,108 @@
+"""Host side of the inference driver: the DE/rand/1/bin optimiser (Sec. 5's
+pre-optimisation) on closed-form costs, no GPU."""
+import numpy as np
+import pytest
+
+from paper_2203_14742_amd.inference import differential_evolution
+
+
+def test_de_finds_the_minimum_of_a_shifted_sphere():
+    c = np.array([0.3, -1.2, 2.0])
+    calls = []
+
+    def cost(X):
+        calls.append(X.shape[0])
+        return ((X - c) ** 2).sum(axis=1)
+
+    r = differential_evolution(cost, [(-3.0, 3.0)] * 3, pop=20, generations=50, seed=1)
+    assert calls == [20] * 51                     # one batched evaluation per generation
+    assert np.all(np.diff(r["history"]) <= 0.0)
+    assert np.abs(r["x"] - c).max() < 1e-2 and r["f"] < 1e-4
+
+
+def test_de_keeps_points_in_bounds_and_is_deterministic():
+    bounds = [(0.0, 1.0), (5.0, 6.0)]
+
+    def cost(X):                                  # minimum outside the box: pulls at the bounds
+        return (X[:, 0] + 4.0) ** 2 + (X[:, 1] - 9.0) ** 2
+
+    a = differential_evolution(cost, bounds, pop=8, generations=30, seed=3)
+    b = differential_evolution(cost, bounds, pop=8, generations=30, seed=3)
+    lo, hi = np.array(bounds).T
+    assert np.all(a["population"] >= lo) and np.all(a["population"] <= hi)
+    assert np.array_equal(a["population"], b["population"]) and a["history"] == b["history"]
+    assert a["x"][0] < 0.05 and a["x"][1] > 5.95
+
+
+def test_de_infinite_costs_are_never_selected_over_finite_ones():
+    def cost(X):
+        return np.where(X[:, 0] > 0.5, np.inf, X[:, 0])
+
+    r = differential_evolution(cost, [(0.0, 1.0)], pop=6, generations=20, seed=0)
+    assert np.isfinite(r["f"]) and r["x"][0] <= 0.5
+
+
+def test_de_rejects_a_population_below_four():
+    with pytest.raises(ValueError):
+        differential_evolution(lambda X: np.zeros(len(X)), [(0.0, 1.0)], pop=3)
+
+
+# ---- adaptive Metropolis / DRAM on a closed-form Gaussian target
+
+MU = np.array([1.0, -2.0])
+SIG = np.array([[1.0, 0.8], [0.8, 2.0]])
+SIG_INV = np.linalg.inv(SIG)
+
+
+def gauss_loglik(X):
+    d = X - MU
+    return -0.5 * np.einsum("ki,ij,kj->k", d, SIG_INV, d)
+
+
+def pooled(r, burn):
+    S = r["chains"][:, burn:].reshape(-1, 2)
+    return S.mean(axis=0), np.cov(S.T)
+
+
+def test_am_samples_the_target_gaussian():
+    from paper_2203_14742_amd.inference import adaptive_metropolis
+    x0 = np.zeros((8, 2))
+    r = adaptive_metropolis(gauss_loglik, x0, 6000, 0.01 * np.eye(2), seed=2, adapt_start=200)
+    m, C = pooled(r, 1000)
+    assert np.abs(m - MU).max() < 0.1
+    assert np.abs(C - SIG).max() < 0.15
+    rate = r["accepted"].sum() / (8 * 6000)
+    assert 0.15 < rate < 0.6                      # the adapted 2.4^2/d scale
+    assert r["evaluations"] == 6001
+
+
+def test_dram_second_stage_keeps_the_target():
+    """Adaptation off, a first stage twice the target's width and a second
+    stage half of it: a third of the moves come from the delayed-rejection
+    stage.  Dropping the kernel ratio q(y2 -> y1) / q(x -> y1), dropping the
+    (1 - a) factors, or swapping the kernel ratio's centres moves the sampled
+    covariance by 0.05 to 0.2 here (64 chains, checked on planted copies);
+    the correct ratio stays within 0.015."""
+    from paper_2203_14742_amd.inference import adaptive_metropolis
+    x0 = np.tile(MU, (64, 1))
+    r = adaptive_metropolis(gauss_loglik, x0, 8000, 4.0 * SIG, seed=1, adapt_start=10 ** 9, dr_scale=0.5)
+    assert r["accepted_dr"].sum() > 0.3 * (r["accepted"].sum() + r["accepted_dr"].sum())
+    m, C = pooled(r, 500)
+    assert np.abs(m - MU).max() < 0.05
+    assert np.abs(C - SIG).max() < 0.03
+
+
+def test_chain_records_are_consistent():
+    from paper_2203_14742_amd.inference import adaptive_metropolis
+    bounds = [(0.0, 2.0), (-3.0, -1.0)]
+    r = adaptive_metropolis(gauss_loglik, np.tile(MU, (3, 1)), 300, 0.5 * np.eye(2), bounds=bounds, seed=7,
+                            adapt_start=50, dr_scale=0.3)
+    ch = r["chains"]
+    lo, hi = np.array(bounds).T
+    assert np.all(ch >= lo) and np.all(ch <= hi)
+    np.testing.assert_array_equal(r["loglik"], gauss_loglik(ch.reshape(-1, 2)).reshape(3, -1))
+    moved = np.any(ch[:, 1:] != ch[:, :-1], axis=2).sum(axis=1)
+    np.testing.assert_array_equal(moved, r["accepted"] + r["accepted_dr"])
+    again = adaptive_metropolis(gauss_loglik, np.tile(MU, (3, 1)), 300, 0.5 * np.eye(2), bounds=bounds, seed=7,
+                                adapt_start=50, dr_scale=0.3)
+    np.testing.assert_array_equal(again["chains"], ch)
