@@ -115,8 +115,10 @@ def implicit_diffusion(n: int, L: float, dt: float, nu: float, b: np.ndarray) ->
 
 
 def imex_run(model: int, params, nu, n, L, dt: float, max_steps: int, tol: float = 0.0,
-             check_every: int = 1, state: np.ndarray | None = None, nthreads: int = 0):
-    """IMEX-Euler runs of a batch of solves, one grid side per solve allowed.
+             check_every: int = 1, state: np.ndarray | None = None, nthreads: int = 0, scheme: str = "euler"):
+    """IMEX-Euler runs of a batch of solves, one grid side per solve allowed
+    (scheme "sbdf2": the second-order IMEX stepper, semi-implicit BDF2 with
+    an IMEX-Euler first step).
 
     ``params``: [B, <=4]; ``nu``: [B, 2]; ``n``, ``L``: scalars or [B];
     ``state``: list of [2, n_b, n_b] arrays or an array [B, 2, n, n] (FP64).
@@ -142,10 +144,12 @@ def imex_run(model: int, params, nu, n, L, dt: float, max_steps: int, tol: float
     steps = np.zeros(B, dtype=np.int64)
     resid = np.zeros(B, dtype=np.float64)
     status = np.zeros(B, dtype=np.int32)
-    rc = lib().oracle_imex_batch(ctypes.c_int(model), ctypes.c_int(B), _ptr(nn), _ptr(LL), _ptr(nus),
-                                 _ptr(pp), ctypes.c_double(dt), ctypes.c_long(max_steps),
-                                 ctypes.c_double(tol), ctypes.c_int(check_every), _ptr(buf), _ptr(off),
-                                 _ptr(steps), _ptr(resid), _ptr(status), ctypes.c_int(nthreads))
+    if scheme not in ("euler", "sbdf2"):
+        raise ValueError(scheme)
+    run = lib().oracle_imex_batch if scheme == "euler" else lib().oracle_sbdf2_batch
+    rc = run(ctypes.c_int(model), ctypes.c_int(B), _ptr(nn), _ptr(LL), _ptr(nus), _ptr(pp), ctypes.c_double(dt),
+             ctypes.c_long(max_steps), ctypes.c_double(tol), ctypes.c_int(check_every), _ptr(buf), _ptr(off),
+             _ptr(steps), _ptr(resid), _ptr(status), ctypes.c_int(nthreads))
     if rc:
         raise RuntimeError("oracle IMEX run failed")
     outs = [buf[off[b]: off[b] + sizes[b]].reshape(2, nn[b], nn[b]) for b in range(B)]

@@ -10,7 +10,9 @@ grids, 16 synthetic patterns per proposal, a data set of 4 patterns.
 - the whole cost of a batch equals the two stages chained;
 - differential evolution: every point inside the bounds, the best cost never
   rises, the same seed gives the same run;
-- DRAM chains: the recorded log-likelihoods are those of the chain states.
+- DRAM chains: the recorded log-likelihoods are those of the chain states;
+- the single-pattern variant (Sec. 5: a data set of one pattern, FHN
+  diffusion scaled by 0.35) through both stages against the oracle.
 """
 import numpy as np
 import pytest
@@ -136,3 +138,44 @@ def test_dram_chains_on_the_synthetic_likelihood(problem):
     np.testing.assert_allclose(r["loglik"].reshape(-1), scil.costs(states)[1], rtol=1e-9)
     assert r["evaluations"] <= 1 + 2 * 6
     print("DRAM: accepted %s, second stage %s" % (r["accepted"], r["accepted_dr"]))
+
+
+def test_single_pattern_scil_matches_oracle(cil, oracle_mod):
+    """N_set = 1: s1 is one synthetic pattern per resample, the observed
+    vector compares the one data pattern with n_syn - 1 synthetic ones."""
+    from paper_2203_14742_amd.inference import SyntheticCIL
+    w = cs.WORKLOADS["fhn128_mcmc"]
+    nu = (0.35 * w["nu"][0], 0.35 * w["nu"][1])
+    alpha, nset = w["alpha"], 1
+    base0 = (w["theta0"][0], w["theta0"][1], alpha)
+    base = oracle_mod.homogeneous_state(w["model"], base0)
+    ics = cs.initial_conditions(base, N, NSYN, seed=w["ic_seed"] + 50)
+    data, _, _, _ = oracle_mod.imex_run(w["model"], base0, nu, N, w["L"], w["dt"], STEPS, 0.0, STEPS,
+                                        state=cs.initial_conditions(base, N, nset, seed=w["data_seed"] + 50),
+                                        nthreads=8)
+    lists = cs.resample_synthetic(NSYN, nset, NBOOT, seed=w["boot_seed"] + 50)
+    assert lists[0].shape == (NBOOT, 1) and lists[1].shape == (NBOOT, NSYN - 1)
+    scil = SyntheticCIL(w["model"], N, w["L"], nu, lambda t: (t[0], t[1], alpha),
+                        torch.tensor(data.reshape(nset, -1), device="cuda"), NSYN, NBOOT, M, w["dt"], STEPS, ics,
+                        lists)
+    thetas = np.asarray(cs.relative_draws(w["theta0"], 2, w["rel"], seed=w["proposal_seed"] + 50))
+    params = [(t[0], t[1], alpha) for t in thetas for _ in range(NSYN)]
+    want_S, _, _, _ = oracle_mod.imex_run(w["model"], params, nu, N, w["L"], w["dt"], STEPS, 0.0, STEPS,
+                                          state=np.concatenate([ics] * len(thetas)), nthreads=8)
+    want_S = want_S.reshape(len(thetas) * NSYN, -1)
+    S = scil.simulate(thetas)
+    assert np.abs(S.cpu().numpy() - want_S).max() / np.abs(want_S).max() <= 1e-9
+    f, ll = scil.costs_from_patterns(torch.tensor(want_S, device="cuda"))
+    i1, i2, sub = lists
+    for p in range(len(thetas)):
+        Sp = want_S[p * NSYN:(p + 1) * NSYN]
+        lo, hi = oracle_mod.distance_range(Sp, Sp, exclude_diagonal=True)
+        radii = oracle_mod.radii_ladder(lo, hi, M)
+        _, Y = oracle_mod.bootstrap_vectors(oracle_mod.pair_d2(Sp, Sp), i1, i2, radii)
+        _, yo = oracle_mod.bootstrap_vectors(oracle_mod.pair_d2(data.reshape(nset, -1), Sp),
+                                             np.zeros((1, 1), dtype=np.int32), sub[None, :], radii)
+        r = oracle_mod.gaussian_cost(Y, yo[0])
+        if r["ok"]:
+            assert f[p] == pytest.approx(r["f"], rel=1e-10) and ll[p] == pytest.approx(r["loglik"], rel=1e-10)
+        else:
+            assert f[p] == np.inf and ll[p] == -np.inf

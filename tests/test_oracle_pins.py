@@ -551,3 +551,90 @@ def test_w12_sum_variant_from_part_distances(oracle_mod):
             want = np.sqrt((u ** 2).sum()) + np.sqrt((((u[:, :, 1:] - u[:, :, :-1]) / h) ** 2).sum()) + \
                 np.sqrt((((u[:, 1:, :] - u[:, :-1, :]) / h) ** 2).sum())
             assert W[i, k] == pytest.approx(want, rel=1e-12)
+
+
+# ---- second-order IMEX stepper (semi-implicit BDF2)
+
+def _heat_modes(n, L, nu):
+    h = L / (n - 1)
+    i = np.arange(n)
+    mode = lambda k: np.cos(np.pi * k * (i + 0.5) / n)
+    lam = lambda k: (4.0 / h ** 2) * np.sin(np.pi * k / (2 * n)) ** 2
+    shapes = [np.outer(mode(2), mode(3)), np.outer(mode(5), mode(1))]
+    mu = np.array([nu[0] * (lam(2) + lam(3)), nu[1] * (lam(5) + lam(1))])
+    return shapes, mu
+
+
+@pytest.mark.parametrize("dt,S", [(1e-3, 1), (1e-3, 2), (1e-3, 50), (2e-2, 40)])
+def test_sbdf2_heat_mode_closed_form(oracle_mod, dt, S):
+    """Pure diffusion of one cosine mode per species (an eigenvector of the
+    ghost-copy Laplacian, eigenvalue -mu/nu): the amplitude follows the linear
+    recurrence a_1 = a_0 / (1 + dt mu), (3 + 2 dt mu) a_s = 4 a_{s-1} - a_{s-2},
+    solved in closed form from the roots of its characteristic polynomial
+    (complex for 2 dt mu > 1, the last case)."""
+    n, L, nu = 16, 1.0, (0.3, 0.7)
+    shapes, mu = _heat_modes(n, L, nu)
+    a0 = np.array([1.0, 0.5])
+    st = np.stack([a0[0] * shapes[0], a0[1] * shapes[1]])[None]
+    out, steps, _, _ = oracle_mod.imex_run(oracle_mod.HEAT, (0.0, 0.0), nu, n, L, dt, S, state=st.copy(),
+                                           scheme="sbdf2")
+    c = 3.0 + 2.0 * dt * mu
+    disc = np.sqrt((1.0 - 2.0 * dt * mu).astype(complex))
+    zp, zm = (2.0 + disc) / c, (2.0 - disc) / c
+    a1 = a0 / (1.0 + dt * mu)
+    cp = (a1 - a0 * zm) / (zp - zm)
+    a = (cp * zp ** S + (a0 - cp) * zm ** S).real
+    want = np.stack([a[0] * shapes[0], a[1] * shapes[1]])
+    assert steps[0] == S
+    assert np.abs(out[0] - want).max() <= 1e-13
+
+
+def test_sbdf2_is_second_order_against_the_exact_heat_solution(oracle_mod):
+    """Error at T = 0.1 against exp(-mu t) of each mode: halving dt divides it
+    by 4 for the second-order stepper and by 2 for IMEX Euler."""
+    n, L, nu, T = 16, 1.0, (0.3, 0.7), 0.1
+    shapes, mu = _heat_modes(n, L, nu)
+    st = np.stack([shapes[0], 0.5 * shapes[1]])[None]
+    a = np.array([1.0, 0.5]) * np.exp(-mu * T)
+    want = np.stack([a[0] * shapes[0], a[1] * shapes[1]])
+    for scheme, lo, hi in (("sbdf2", 3.7, 4.6), ("euler", 1.9, 2.1)):
+        e = []
+        for m in (20, 40, 80):
+            out, _, _, _ = oracle_mod.imex_run(oracle_mod.HEAT, (0.0, 0.0), nu, n, L, T / m, m, state=st.copy(),
+                                               scheme=scheme)
+            e.append(np.abs(out[0] - want).max())
+        assert lo < e[0] / e[1] < hi and lo < e[1] / e[2] < hi, (scheme, e)
+
+
+def test_sbdf2_reaction_extrapolation_is_second_order(oracle_mod):
+    """FitzHugh-Nagumo (nonlinear reaction) to T = 0.5: differences of runs
+    at dt, dt/2, dt/4, dt/8 shrink 4-fold (2-fold for IMEX Euler), which a
+    reaction taken at the old level only, or a wrong extrapolation weight,
+    would not give."""
+    n, L = 16, 1.0
+    x = np.linspace(0.0, 1.0, n)
+    ic = np.stack([0.1 * np.outer(np.cos(np.pi * x), np.cos(2 * np.pi * x)),
+                   0.1 * np.outer(np.sin(np.pi * x), np.cos(np.pi * x))])[None]
+    T = 0.5
+    for scheme, lo, hi in (("sbdf2", 3.6, 4.4), ("euler", 1.8, 2.2)):
+        us = [oracle_mod.imex_run(oracle_mod.FHN, (1.0, 10.0, 1.0), (0.05, 0.00028), n, L, T / m, m,
+                                  state=ic.copy(), scheme=scheme)[0][0] for m in (50, 100, 200, 400)]
+        e = [np.abs(us[j] - us[j + 1]).max() for j in range(3)]
+        assert lo < e[0] / e[1] < hi and lo < e[1] / e[2] < hi, (scheme, e)
+
+
+def test_sbdf2_keeps_a_stationary_state(oracle_mod):
+    """A stationary state of the method-of-lines system is a fixed point of
+    both steppers: started at IMEX Euler's converged Gierer-Meinhardt pattern
+    (residual < 1e-11), 200 second-order steps move it by less than 1e-9."""
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    n = 16
+    base = oracle_mod.homogeneous_state(w["model"], w["params"])
+    ic = cs.initial_conditions(base, n, 1, seed=5, law=w["ic_law"])
+    L = w["L"] * n / w["n"]
+    st, _, res, stat = oracle_mod.imex_run(w["model"], w["params"], w["nu"], n, L, w["dt"], 50000, 1e-11, 25,
+                                           state=ic.copy())
+    assert stat[0] == 0 and res[0] < 1e-11
+    out, _, res2, _ = oracle_mod.imex_run(w["model"], w["params"], w["nu"], n, L, w["dt"], 200, state=st.copy(),
+                                          scheme="sbdf2")
+    assert np.abs(out - st).max() < 1e-9 and res2[0] < 1e-10
