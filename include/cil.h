@@ -151,6 +151,25 @@ int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem
                           void *state, const int64_t *elem_offsets, const cil_stepping *stepping,
                           cil_solve_report *reports, void *hip_stream);
 
+/* The same solves with a second-order IMEX stepper (semi-implicit BDF2; the
+ * paper's integrators, Sec. 5.1 and App. B.2, are first order in time or
+ * explicit).  Step 1 of every call is the IMEX-Euler step above; step s >= 2:
+ *   r_s = (4 u^{s-1} - u^{s-2}) / 3 + (2 dt / 3) (2 F(u^{s-1}) - F(u^{s-2}))
+ *   u^s = (I - (2 dt / 3) nu_s Lap_h)^{-1} r_s    (cosine-basis solve)
+ * Its fixed points are the stationary solutions nu Lap_h u + F(u) = 0, as
+ * for IMEX Euler.  Residual, stop rule, reports and errors as for
+ * cil_simulate_patterns.  The history (u^{s-2}, F(u^{s-2})) lives for one
+ * call only: a call that continues from a state the previous one left starts
+ * again with an Euler step, so it is not the same as one uninterrupted run.
+ * Runs on the plain back-end (path AUTO or PLAIN; FUSED paths:
+ * CIL_EUNSUPPORTED).  FP32: polish must be 0 (no FP64 continuation; a solve
+ * that reaches the FP32 floor ends with status FP32_FLOOR); polish != 0 with
+ * tol > 0 is CIL_EUNSUPPORTED.  Two device buffers of the state's size hold
+ * the history (from the library's buffer pool). */
+int cil_simulate_patterns_sbdf2(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B,
+                                void *state, const int64_t *elem_offsets, const cil_stepping *stepping,
+                                cil_solve_report *reports, void *hip_stream);
+
 /* Simulate plans.  The paper's experiments draw every statistic from large
  * batches of independent solves of one model (Sec. 4, many initial states per
  * parameter value).  A plan binds such a batch -- problems, layout, stepping

@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         L.cil_last_error.restype = ctypes.c_char_p
         L.cil_homogeneous_state.argtypes = [ctypes.c_int, vp, vp]
         L.cil_simulate_patterns.argtypes = [ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, vp, vp]
+        L.cil_simulate_patterns_sbdf2.argtypes = [ctypes.c_int, ctypes.c_int, vp, i32, vp, vp, vp, vp, vp]
         L.cil_features.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, i32, vp, vp, vp]
         L.cil_pair_bins.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, vp, i32, vp, vp, vp]
         L.cil_distance_range.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, vp, vp, vp]
@@ -194,9 +195,15 @@ def make_problems(n, L, nu, p, count: int | None = None):
 
 def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int, tol: float = 0.0,
                           check_every: int = 1, path: int = CIL_PATH_AUTO, polish: int = 1,
-                          fp32_floor_ulps: int = 0, offsets=None, raise_on_nonfinite: bool = True):
+                          fp32_floor_ulps: int = 0, offsets=None, raise_on_nonfinite: bool = True,
+                          scheme: str = "euler"):
     """Run the solves in place on ``state`` (float32/float64 device tensor).
+    scheme "euler": IMEX Euler (cil_simulate_patterns); "sbdf2": the
+    second-order IMEX stepper (cil_simulate_patterns_sbdf2, plain back-end,
+    FP32 with polish=0 only).
     Returns a dict of numpy arrays: steps_taken, steps_fp64, final_resid, status."""
+    if scheme not in ("euler", "sbdf2"):
+        raise ValueError("unknown scheme %r" % (scheme,))
     B = len(problems)
     st = Stepping(dt=dt, max_steps=int(max_steps), tol=tol, check_every=int(check_every), path=int(path),
                   polish=int(polish), fp32_floor_ulps=int(fp32_floor_ulps))
@@ -210,9 +217,10 @@ def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int
         need = int(sizes.sum())
     if state.numel() < need:
         raise ValueError("state holds %d elements, the solves need %d" % (state.numel(), need))
-    rc = lib().cil_simulate_patterns(model, _prec(state), ctypes.cast(problems, ctypes.c_void_p), B,
-                                     _dev(state, "state"), None if offs is None else offs.ctypes.data,
-                                     ctypes.byref(st), ctypes.cast(reps, ctypes.c_void_p), _stream(state))
+    fn = lib().cil_simulate_patterns if scheme == "euler" else lib().cil_simulate_patterns_sbdf2
+    rc = fn(model, _prec(state), ctypes.cast(problems, ctypes.c_void_p), B, _dev(state, "state"),
+            None if offs is None else offs.ctypes.data, ctypes.byref(st), ctypes.cast(reps, ctypes.c_void_p),
+            _stream(state))
     out = _reports(reps, B)
     if rc == CIL_ENONFINITE and not raise_on_nonfinite:
         return out

@@ -17,7 +17,7 @@ namespace cil {
 
 // implemented in the other translation units
 int simulate_impl(cil_model, cil_precision, const cil_problem *, int, void *, const int64_t *,
-                  const cil_stepping *, cil_solve_report *, hipStream_t);
+                  const cil_stepping *, cil_solve_report *, hipStream_t, int scheme);
 template <typename T>
 int pair_bins_impl(const T *, long long, const T *, long long, long long, const double *, int, uint8_t *,
                    std::vector<unsigned long long> &, hipStream_t);
@@ -310,11 +310,10 @@ int cil_homogeneous_state(cil_model model, const double *p, double *v0w0)
     }
 }
 
-int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B, void *state,
-                          const int64_t *elem_offsets, const cil_stepping *stepping, cil_solve_report *reports,
-                          void *hip_stream)
+static int simulate_checked(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B, void *state,
+                            const int64_t *elem_offsets, const cil_stepping *stepping, cil_solve_report *reports,
+                            void *hip_stream, int scheme)
 {
-    API_BEGIN();
     if ((int)model < CIL_FHN || (int)model > CIL_HEAT) return set_error(CIL_EINVAL, "unknown model %d", (int)model);
     if (prec != CIL_FP32 && prec != CIL_FP64) return set_error(CIL_EINVAL, "unknown precision");
     if (B < 0) return set_error(CIL_EINVAL, "B < 0");
@@ -338,7 +337,24 @@ int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem
             for (int b = 0; b < B; ++b) reports[b] = cil_solve_report{0, 0, 0.0, CIL_SOLVE_OK, 0};
         return CIL_OK;
     }
-    return simulate_impl(model, prec, probs, B, state, elem_offsets, stepping, reports, (hipStream_t)hip_stream);
+    return simulate_impl(model, prec, probs, B, state, elem_offsets, stepping, reports, (hipStream_t)hip_stream,
+                         scheme);
+}
+
+int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B, void *state,
+                          const int64_t *elem_offsets, const cil_stepping *stepping, cil_solve_report *reports,
+                          void *hip_stream)
+{
+    API_BEGIN();
+    return simulate_checked(model, prec, probs, B, state, elem_offsets, stepping, reports, hip_stream, 0);
+}
+
+int cil_simulate_patterns_sbdf2(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B,
+                                void *state, const int64_t *elem_offsets, const cil_stepping *stepping,
+                                cil_solve_report *reports, void *hip_stream)
+{
+    API_BEGIN();
+    return simulate_checked(model, prec, probs, B, state, elem_offsets, stepping, reports, hip_stream, 1);
 }
 
 // plan handles are cil::SimPlan objects behind the opaque C type

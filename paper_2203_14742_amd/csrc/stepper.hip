@@ -75,6 +75,44 @@ __global__ void k_plain_reaction(const DevSolve *S, const int *list, const T *st
     });
 }
 
+// Second-order IMEX reaction stage (semi-implicit BDF2): with the history
+// uh = u^{s-2}, fh = F(u^{s-2}) (same layout as the state),
+//   r = (4 u^{s-1} - u^{s-2}) / 3 + (2 dt / 3) (2 F(u^{s-1}) - F(u^{s-2})),
+// followed by the diffusion solve with 2 dt / 3 in place of dt.  The first
+// step of a call is the IMEX-Euler stage (no history yet).  Either way the
+// history moves on to u^{s-1}, F(u^{s-1}).
+template <typename T>
+__global__ void k_plain_reaction_sbdf2(const DevSolve *S, const int *list, const T *state, T *R, T *uh, T *fh,
+                                       int n, int model, double dt, int first)
+{
+    const int slot = blockIdx.y;
+    const DevSolve s = S[list[slot]];
+    const int N2 = n * n;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N2) return;
+    const T *u = state + s.off;
+    T *up = uh + s.off, *fp = fh + s.off;
+    T *r = R + (size_t)slot * 2 * N2;
+    T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
+    const T v = u[q], w = u[N2 + q];
+    dispatch_model(model, [&](auto MD) {
+        T f, g;
+        kinetics<MD>(p, v, w, f, g);
+        if (first) {
+            r[q] = v + T(dt) * f;
+            r[N2 + q] = w + T(dt) * g;
+        } else {
+            const T c = T(2.0 * dt / 3.0);
+            r[q] = (T(4) * v - up[q]) / T(3) + c * (T(2) * f - fp[q]);
+            r[N2 + q] = (T(4) * w - up[N2 + q]) / T(3) + c * (T(2) * g - fp[N2 + q]);
+        }
+        up[q] = v;
+        up[N2 + q] = w;
+        fp[q] = f;
+        fp[N2 + q] = g;
+    });
+}
+
 // out[i][l] = sum_j in[i][j] C[l][j]   (row forward)
 template <typename T>
 __global__ void k_plain_rows_fwd(const int *list, const T *in, T *out, const T *Ct, int n)
@@ -598,9 +636,17 @@ struct PlainGroup {
     size_t work_cap = 0;
 };
 
+// History of the second-order stepper for one plain launch: u^{s-2} and
+// F(u^{s-2}) in the state's layout, and the step index the launch starts at.
+template <typename T>
+struct Sbdf2Args {
+    T *uh, *fh;
+    int64_t step0;
+};
+
 template <typename T>
 int launch_plain(PlainGroup &g, const DevSolve *S, T *u, int nl, int model, double dt, int K, StepResults R,
-                 hipStream_t st)
+                 hipStream_t st, const Sbdf2Args<T> *bdf = nullptr)
 {
     PlainTables tb;
     CIL_TRY(plain_tables<T>(g.n, &tb));
@@ -609,13 +655,23 @@ int launch_plain(PlainGroup &g, const DevSolve *S, T *u, int nl, int model, doub
     T *Bw = A + g.work_cap * 2 * N2;
     const dim3 blk(256);
     const dim3 grid1((N2 + 255) / 256, nl), grid2((2 * N2 + 255) / 256, nl);
-    const ProfMark pm = prof_begin(std::is_same<T, float>::value ? "plain_step_f32" : "plain_step_f64", st);
+    const bool f32 = std::is_same<T, float>::value;
+    const ProfMark pm = prof_begin(bdf ? (f32 ? "plain_step_sbdf2_f32" : "plain_step_sbdf2_f64")
+                                       : (f32 ? "plain_step_f32" : "plain_step_f64"), st);
     for (int k = 0; k < K; ++k) {
         const int check = (k == K - 1);
-        hipLaunchKernelGGL(k_plain_reaction<T>, grid1, blk, 0, st, S, g.dlist, u, A, n, model, dt);
+        double dts = dt;                   // the diffusion solve's step
+        if (bdf) {
+            const int first = (bdf->step0 + k == 0);
+            if (!first) dts = 2.0 * dt / 3.0;
+            hipLaunchKernelGGL(k_plain_reaction_sbdf2<T>, grid1, blk, 0, st, S, g.dlist, u, A, bdf->uh, bdf->fh, n,
+                               model, dt, first);
+        } else {
+            hipLaunchKernelGGL(k_plain_reaction<T>, grid1, blk, 0, st, S, g.dlist, u, A, n, model, dt);
+        }
         hipLaunchKernelGGL(k_plain_rows_fwd<T>, grid2, blk, 0, st, g.dlist, A, Bw, (const T *)tb.Ct, n);
         hipLaunchKernelGGL(k_plain_cols_fwd_div<T>, grid2, blk, 0, st, S, g.dlist, Bw, A, (const T *)tb.C, tb.lam, n,
-                           dt);
+                           dts);
         hipLaunchKernelGGL(k_plain_cols_inv<T>, grid2, blk, 0, st, g.dlist, A, Bw, (const T *)tb.Cw, n);
         hipLaunchKernelGGL(k_plain_rows_inv<T>, grid2, blk, 0, st, S, g.dlist, Bw, u, (const T *)tb.Cw, n, check, R);
     }
@@ -682,6 +738,8 @@ struct SimCtx {
     std::vector<double> fres;
     std::vector<int> status;
     std::vector<int64_t> sw;      // mixed launches: step of the FP32 -> FP64 switch (-1: not a mixed solve)
+    int scheme = 0;               // 0 IMEX Euler, 1 second-order IMEX (plain back-end)
+    void *uh = nullptr, *fh = nullptr;   // second-order history, state layout
 };
 
 // FP32 -> FP64 within one launch (k_fused_q_mixed) for these grid sides.
@@ -856,7 +914,8 @@ int run_plain(SimCtx &c, std::vector<PlainGroup> &groups, const DevSolve *dS, T 
             const int nl = (int)g.active.size();
             CIL_HIP(hipMemcpyAsync(g.dlist, g.active.data(), sizeof(int) * nl, hipMemcpyHostToDevice, c.st));
             hipLaunchKernelGGL(k_clear_results, dim3((nl + 255) / 256), dim3(256), 0, c.st, g.dlist, nl, R);
-            CIL_TRY(launch_plain<T>(g, dS, state, nl, c.model, c.dt, K, R, c.st));
+            const Sbdf2Args<T> bdf{(T *)c.uh, (T *)c.fh, step};
+            CIL_TRY(launch_plain<T>(g, dS, state, nl, c.model, c.dt, K, R, c.st, c.scheme ? &bdf : nullptr));
         }
         CIL_HIP(hipMemcpyAsync(h_resid.data(), R.resid, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, c.st));
         CIL_HIP(hipMemcpyAsync(h_maxabs.data(), R.maxabs, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost, c.st));
@@ -915,7 +974,7 @@ int make_plain_groups(SimCtx &c, const std::map<int, std::vector<int>> &byn, std
 }  // namespace
 
 int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs, int B, void *state,
-                  const int64_t *offs, const cil_stepping *stp, cil_solve_report *reports, hipStream_t st)
+                  const int64_t *offs, const cil_stepping *stp, cil_solve_report *reports, hipStream_t st, int scheme)
 {
     const bool f32 = (prec == CIL_FP32);
     const int floor_ulps = stp->fp32_floor_ulps > 0 ? stp->fp32_floor_ulps : 8;
@@ -934,6 +993,13 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     c.status.assign(B, CIL_SOLVE_OK);
     const bool polish = f32 && stp->polish && stp->tol > 0.0;
     const bool quad = stp->path != CIL_PATH_FUSED_LINE;
+    if (scheme) {
+        if (stp->path != CIL_PATH_AUTO && stp->path != CIL_PATH_PLAIN)
+            return set_error(CIL_EUNSUPPORTED, "the second-order stepper runs on the plain back-end only");
+        if (polish)
+            return set_error(CIL_EUNSUPPORTED, "the second-order stepper has no FP64 polish: set polish = 0");
+    }
+    c.scheme = scheme;
 
     std::vector<DevSolve> hs(B);
     std::vector<int64_t> elems(B);
@@ -960,8 +1026,15 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         const bool fs = fused_supported(n, f32);
         if (stp->path >= CIL_PATH_FUSED && !fs)
             return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", n, f32 ? "FP32" : "FP64");
-        if (fs && stp->path != CIL_PATH_PLAIN) fused_byn[n].push_back(b);
+        if (fs && stp->path != CIL_PATH_PLAIN && !scheme) fused_byn[n].push_back(b);
         else plain_byn[n].push_back(b);
+    }
+    if (scheme) {
+        int64_t end = 0;
+        for (int b = 0; b < B; ++b) end = std::max<int64_t>(end, hs[b].off + elems[b]);
+        const size_t es = f32 ? sizeof(float) : sizeof(double);
+        CIL_TRY(cb.alloc(&c.uh, es * (size_t)end));
+        CIL_TRY(cb.alloc(&c.fh, es * (size_t)end));
     }
     DevSolve *dS;
     long long *dsteps;
