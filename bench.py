@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "fhn32_fixed5000", "features4096", "mcil_stripes64", "bz_uneven2048",
-                             "fhn128_mcmc", "fhn128_de"],
+                             "fhn128_mcmc", "fhn128_de", "fhn32_sbdf2"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -163,6 +163,9 @@ def main():
         return
     if args.workload == "fhn128_de":
         de_main(args)
+        return
+    if args.workload == "fhn32_sbdf2":
+        sbdf2_main(args)
         return
 
     import cil_synth as cs
@@ -598,6 +601,89 @@ def fhn32_main(args):
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def sbdf2_main(args):
+    """The second-order IMEX stepper (semi-implicit BDF2) on the plain FP64
+    method's configuration: 128 FitzHugh-Nagumo solves on 32x32, 5000 fixed
+    steps of dt = 0.01, then the correlation integral counts of the 64 x 64
+    cross pairs under 16 radii R_0 1.2^-m.  Both steppers run on the plain
+    back-end in FP64 (five kernels per time step); `value` is the
+    second-order path's patterns/s, the IMEX-Euler plain path is timed beside
+    it.  Roofline: the plain step's executed flops (dense cosine transforms,
+    16 n^3 per solve and step, plus the reaction) against the FP64 vector
+    peak."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS["fhn32_fixed5000"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics_host = np.concatenate([cs.initial_conditions(base, w["n"], w["count"], seed=s, law=w["ic_law"])
+                               for s in w["seeds"]])
+    B, half, M, n = ics_host.shape[0], w["count"], w["M"], w["n"]
+    probs = cil.make_problems(n, w["L"], w["nu"], w["params"], count=B)
+
+    def run(scheme):
+        ics = torch.tensor(ics_host, dtype=torch.float64, device=dev)
+        st = torch.empty_like(ics)
+
+        def one_step():
+            st.copy_(ics)
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"],
+                                            check_every=w["check_every"], path=cil.CIL_PATH_PLAIN, scheme=scheme)
+            P = st.reshape(B, -1)
+            _, hi = cil.cil_distance_range(P[:half], P[half:])
+            radii = [math.sqrt(hi) * w["radii_base"] ** -(m + 1) for m in range(M)]
+            counts, _ = cil.cil_features(P[:half], P[half:], radii)
+            return rep, counts
+
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        cil.cil_profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rep, counts = one_step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = {k: cil.cil_profile_read(k) for k in cil.cil_profile_names()}
+        cil.cil_profile(False)
+        return el / args.steps, rep, counts, prof
+
+    t2, rep2, counts2, prof2 = run("sbdf2")
+    t1, rep1, counts1, _ = run("euler")
+    kname = "plain_step_sbdf2_f64"
+    cnt, tot_ms = prof2[kname]
+    # per solve and step: four dense transform passes over both species
+    # (2 n^2 outputs x n multiply-adds each) plus the pointwise stage
+    step_flops = 16 * n ** 3 + n * n * (REACTION_FLOPS[w["model"]] + 10)
+    flops = B * w["max_steps"] * step_flops              # one profiled range = one whole 5000-step run
+    ach = flops / (tot_ms / cnt * 1e-3) / 1e12
+    roof = {"kernel": "plain second-order step (reaction + four transform kernels, 5000 steps)", "bound": "alu",
+            "achieved": round(ach, 4), "peak": VALU_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / VALU_FP64_PEAK_TFLOPS, 5), "traffic": None, "launch_groups": cnt,
+            "ms_per_run": round(tot_ms / cnt, 3), "flops_per_solve_step": step_flops}
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(B / t2, 2), "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t2, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "fhn32_sbdf2", "solves": B, "n": n, "dt": w["dt"], "steps_per_solve": w["max_steps"],
+                   "pairs": half * half, "radii": M, "stepping": "second-order IMEX (semi-implicit BDF2), plain FP64",
+                   "parallelism": "none (1 GPU)"},
+        "imex_euler_plain_fp64": {"patterns_per_s": round(B / t1, 2), "ms_per_step": round(1e3 * t1, 3)},
+        "counts_sbdf2": [int(c) for c in counts2], "counts_euler": [int(c) for c in counts1],
+        "all_ok": bool(np.all(rep2["status"] == 0) and np.all(rep1["status"] == 0)),
+        "roofline": roof,
+        "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof2.items())},
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
