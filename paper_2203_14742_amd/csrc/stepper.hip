@@ -125,6 +125,7 @@ __global__ void k_plain_rows_fwd(const int *list, const T *in, T *out, const T *
     const int sp = e / N2, i = (e / n) % n, l = e % n;
     const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2 + (size_t)i * n;
     T acc = T(0);
+    #pragma unroll 8
     for (int j = 0; j < n; ++j) acc += x[j] * Ct[j * n + l];
     out[(size_t)slot * 2 * N2 + e] = acc;
 }
@@ -142,8 +143,10 @@ __global__ void k_plain_cols_fwd_div(const DevSolve *S, const int *list, const T
     const int sp = e / N2, k = (e / n) % n, l = e % n;
     const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2;
     T acc = T(0);
+    #pragma unroll 8
     for (int i = 0; i < n; ++i) acc += C[k * n + i] * x[i * n + l];
-    const double fac = 1.0 / (1.0 + dt * s.nu[sp] * (lam[k] + lam[l]) * s.inv_h2);
+    const double nu = sp ? s.nu[1] : s.nu[0];     // a select: an indexed read would place s in memory
+    const double fac = 1.0 / (1.0 + dt * nu * (lam[k] + lam[l]) * s.inv_h2);
     out[(size_t)slot * 2 * N2 + e] = acc * T(fac);
 }
 
@@ -159,6 +162,7 @@ __global__ void k_plain_cols_inv(const int *list, const T *in, T *out, const T *
     const int sp = e / N2, i = (e / n) % n, l = e % n;
     const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2;
     T acc = T(0);
+    #pragma unroll 8
     for (int k = 0; k < n; ++k) acc += Cw[k * n + i] * x[k * n + l];
     out[(size_t)slot * 2 * N2 + e] = acc;
 }
@@ -180,6 +184,7 @@ __global__ void k_plain_rows_inv(const DevSolve *S, const int *list, const T *in
         const int sp = e / N2, i = (e / n) % n, j = e % n;
         const T *x = in + (size_t)slot * 2 * N2 + (size_t)sp * N2 + (size_t)i * n;
         T acc = T(0);
+        #pragma unroll 8
         for (int l = 0; l < n; ++l) acc += x[l] * Cw[l * n + j];
         T *u = state + s.off;
         if (check) {
