@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
 and by the CPU-baseline leg of ``bench.py``; never by the product package.  It
-shares no code with the HIP path.  Heavy loops (IMEX stepping with a banded
-Cholesky diffusion solve, canonical distances, counts, bootstrap counts) live
+shares no code with the HIP path.  Heavy loops (IMEX-Euler and second-order
+IMEX stepping with a banded Cholesky diffusion solve, canonical distances,
+counts, bootstrap counts) live
 in ``cil_oracle.c``; the small statistics (radii ladder, mean/covariance,
 Cholesky, cost) are written out here with plain loops.
 
