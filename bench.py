@@ -116,7 +116,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64-fused", "--no-fp32-stepping", dest="no_secondary", action="store_true",
                     help="skip the secondary leg (the same step with FP64 fused stepping throughout)")
-    ap.add_argument("--cpu-sample-solves", type=int, default=96)
+    ap.add_argument("--cpu-sample-solves", type=int, default=384,
+                    help="solves the CPU oracle runs to stationarity for the cpu_baseline leg (about 10 s on 16 "
+                         "threads at the default)")
     ap.add_argument("--gram-flush", type=int, default=64, choices=[32, 64, 128, 256],
                     help="features4096: FP32 -> FP64 promotion interval of the Gram")
     ap.add_argument("--gram-pipeline", type=int, default=2, choices=[0, 1, 2],
@@ -409,7 +411,7 @@ def features_main(args):
         import oracle
         oracle.build()
         threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
-        k = 256
+        k = 768                                          # about 10 s on 16 threads
         t1 = time.perf_counter()
         D = oracle.pair_d2(host[:k], host[half:half + k], nthreads=threads)
         tp = time.perf_counter() - t1
@@ -575,7 +577,7 @@ def fhn32_main(args):
         import oracle
         oracle.build()
         threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
-        k = 16
+        k = B                                            # the whole batch: a few seconds
         t1 = time.perf_counter()
         oracle.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], w["max_steps"], 0.0,
                         w["check_every"], state=ics_host[:k].copy(), nthreads=threads)
@@ -945,7 +947,7 @@ def cpu_baseline(w, ics_host, base, n_solves, half, d):
                                               w["max_steps"], w["tol"], w["check_every"], state=ics,
                                               nthreads=threads)
     t_sim = time.perf_counter() - t0
-    k = min(64, n_solves // 2)
+    k = n_solves // 2
     A = out[:k].reshape(k, -1).astype(np.float32)
     Bm = out[k:2 * k].reshape(k, -1).astype(np.float32)
     t1 = time.perf_counter()
