@@ -128,7 +128,7 @@ def adaptive_metropolis(loglik_batch, x0, n_steps: int, C0, bounds=None, seed: i
     """K chains of adaptive Metropolis, started at the rows of x0 [K, dim].
 
     Step t of each chain proposes y = x + L_t z, z ~ N(0, I), C_t = L_t L_t^T:
-    C_t = C0 while t <= adapt_start, afterwards sd (Cov(x_0 .. x_{t-1}) + eps I)
+    C_t = C0 while t <= max(adapt_start, 1), afterwards sd (Cov(x_0 .. x_{t-1}) + eps I)
     with sd = 2.4^2 / dim by default (the chain's own history, updated
     recursively).  Accept with probability min(1, pi(y) / pi(x)) under a flat
     prior inside `bounds` (a proposal outside has pi = 0 and is not
@@ -174,7 +174,7 @@ def adaptive_metropolis(loglik_batch, x0, n_steps: int, C0, bounds=None, seed: i
 
     for t in range(1, n_steps + 1):
         x, lx = chains[:, t - 1], ll[:, t - 1]
-        if t <= adapt_start:
+        if t <= max(adapt_start, 1):                  # a covariance needs two history points
             Ls = np.broadcast_to(L0, (K, dim, dim))
         else:
             Ls = np.linalg.cholesky(sd * (M2 / (t - 1) + eps * np.eye(dim)))

@@ -106,3 +106,11 @@ def test_chain_records_are_consistent():
     again = adaptive_metropolis(gauss_loglik, np.tile(MU, (3, 1)), 300, 0.5 * np.eye(2), bounds=bounds, seed=7,
                                 adapt_start=50, dr_scale=0.3)
     np.testing.assert_array_equal(again["chains"], ch)
+
+
+def test_am_adapts_from_the_second_step_when_asked():
+    from paper_2203_14742_amd.inference import adaptive_metropolis
+    r = adaptive_metropolis(gauss_loglik, np.zeros((4, 2)), 2000, 0.1 * np.eye(2), seed=8, adapt_start=0)
+    assert np.all(np.isfinite(r["chains"])) and r["accepted"].sum() > 0
+    m, C = pooled(r, 500)
+    assert np.abs(m - MU).max() < 0.3 and np.abs(C - SIG).max() < 0.5
