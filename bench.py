@@ -611,12 +611,12 @@ def sbdf2_main(args):
     """The second-order IMEX stepper (semi-implicit BDF2) on the plain FP64
     method's configuration: 128 FitzHugh-Nagumo solves on 32x32, 5000 fixed
     steps of dt = 0.01, then the correlation integral counts of the 64 x 64
-    cross pairs under 16 radii R_0 1.2^-m.  Both steppers run on the plain
-    back-end in FP64 (five kernels per time step); `value` is the
-    second-order path's patterns/s, the IMEX-Euler plain path is timed beside
-    it.  Roofline: the plain step's executed flops (dense cosine transforms,
-    16 n^3 per solve and step, plus the reaction) against the FP64 vector
-    peak."""
+    cross pairs under 16 radii R_0 1.2^-m, all in FP64.  `value` is the
+    fused second-order kernel's patterns/s (one workgroup per solve, history
+    in LDS); beside it the same step on the plain back-end and IMEX Euler's
+    fused FP64 step.  Roofline: the fused kernel's algorithmic flops (the
+    transform count of the Euler step plus the second-order pointwise terms)
+    against the FP64 vector peak."""
     import numpy as np
     import torch
 
@@ -632,14 +632,14 @@ def sbdf2_main(args):
     B, half, M, n = ics_host.shape[0], w["count"], w["M"], w["n"]
     probs = cil.make_problems(n, w["L"], w["nu"], w["params"], count=B)
 
-    def run(scheme):
+    def run(scheme, path):
         ics = torch.tensor(ics_host, dtype=torch.float64, device=dev)
         st = torch.empty_like(ics)
 
         def one_step():
             st.copy_(ics)
             rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"],
-                                            check_every=w["check_every"], path=cil.CIL_PATH_PLAIN, scheme=scheme)
+                                            check_every=w["check_every"], path=path, scheme=scheme)
             P = st.reshape(B, -1)
             _, hi = cil.cil_distance_range(P[:half], P[half:])
             radii = [math.sqrt(hi) * w["radii_base"] ** -(m + 1) for m in range(M)]
@@ -659,30 +659,31 @@ def sbdf2_main(args):
         cil.cil_profile(False)
         return el / args.steps, rep, counts, prof
 
-    t2, rep2, counts2, prof2 = run("sbdf2")
-    t1, rep1, counts1, _ = run("euler")
-    kname = "plain_step_sbdf2_f64"
+    t2, rep2, counts2, prof2 = run("sbdf2", cil.CIL_PATH_AUTO)
+    tp, repp, countsp, _ = run("sbdf2", cil.CIL_PATH_PLAIN)
+    t1, rep1, counts1, _ = run("euler", cil.CIL_PATH_AUTO)
+    kname = "k_fused_sbdf2_f64_n32"
     cnt, tot_ms = prof2[kname]
-    # per solve and step: four dense transform passes over both species
-    # (2 n^2 outputs x n multiply-adds each) plus the pointwise stage
-    step_flops = 16 * n ** 3 + n * n * (REACTION_FLOPS[w["model"]] + 10)
-    flops = B * w["max_steps"] * step_flops              # one profiled range = one whole 5000-step run
+    step_flops = fused_step_flops(n, REACTION_FLOPS[w["model"]]) + 2 * n * n * 6
+    flops = B * w["max_steps"] * step_flops                  # one launch = the whole 5000-step run
     ach = flops / (tot_ms / cnt * 1e-3) / 1e12
-    roof = {"kernel": "plain second-order step (reaction + four transform kernels, 5000 steps)", "bound": "alu",
-            "achieved": round(ach, 4), "peak": VALU_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / VALU_FP64_PEAK_TFLOPS, 5), "traffic": None, "launch_groups": cnt,
-            "ms_per_run": round(tot_ms / cnt, 3), "flops_per_solve_step": step_flops}
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 4), "peak": VALU_FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / VALU_FP64_PEAK_TFLOPS, 5), "traffic": None, "launches": cnt,
+            "avg_launch_ms": round(tot_ms / cnt, 3), "flops_per_solve_step": step_flops}
     line = {
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
         "value": round(B / t2, 2), "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * t2, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "fhn32_sbdf2", "solves": B, "n": n, "dt": w["dt"], "steps_per_solve": w["max_steps"],
-                   "pairs": half * half, "radii": M, "stepping": "second-order IMEX (semi-implicit BDF2), plain FP64",
+                   "pairs": half * half, "radii": M,
+                   "stepping": "second-order IMEX (semi-implicit BDF2), fused FP64 line kernel",
                    "parallelism": "none (1 GPU)"},
-        "imex_euler_plain_fp64": {"patterns_per_s": round(B / t1, 2), "ms_per_step": round(1e3 * t1, 3)},
-        "counts_sbdf2": [int(c) for c in counts2], "counts_euler": [int(c) for c in counts1],
-        "all_ok": bool(np.all(rep2["status"] == 0) and np.all(rep1["status"] == 0)),
+        "sbdf2_plain_fp64": {"patterns_per_s": round(B / tp, 2), "ms_per_step": round(1e3 * tp, 3)},
+        "imex_euler_fused_fp64": {"patterns_per_s": round(B / t1, 2), "ms_per_step": round(1e3 * t1, 3)},
+        "counts_sbdf2": [int(c) for c in counts2], "counts_sbdf2_plain": [int(c) for c in countsp],
+        "counts_euler": [int(c) for c in counts1],
+        "all_ok": bool(np.all(rep2["status"] == 0) and np.all(repp["status"] == 0) and np.all(rep1["status"] == 0)),
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof2.items())},
         "cpu_baseline": None,

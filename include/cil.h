@@ -161,11 +161,15 @@ int cil_simulate_patterns(cil_model model, cil_precision prec, const cil_problem
  * cil_simulate_patterns.  The history (u^{s-2}, F(u^{s-2})) lives for one
  * call only: a call that continues from a state the previous one left starts
  * again with an Euler step, so it is not the same as one uninterrupted run.
- * Runs on the plain back-end (path AUTO or PLAIN; FUSED paths:
- * CIL_EUNSUPPORTED).  FP32: polish must be 0 (no FP64 continuation; a solve
+ * Back-ends: a fused persistent kernel (one workgroup per solve, one lane
+ * per grid line, state and history resident in LDS) for n = 32 and, in FP32,
+ * n = 64; the plain back-end (history in two state-sized device buffers from
+ * the library's buffer pool) otherwise.  Path AUTO picks the fused kernel
+ * where it exists, PLAIN forces the plain back-end, FUSED and FUSED_LINE
+ * require the fused kernel (CIL_EUNSUPPORTED for other sides), FUSED_QUAD is
+ * CIL_EUNSUPPORTED.  FP32: polish must be 0 (no FP64 continuation; a solve
  * that reaches the FP32 floor ends with status FP32_FLOOR); polish != 0 with
- * tol > 0 is CIL_EUNSUPPORTED.  Two device buffers of the state's size hold
- * the history (from the library's buffer pool). */
+ * tol > 0 is CIL_EUNSUPPORTED. */
 int cil_simulate_patterns_sbdf2(cil_model model, cil_precision prec, const cil_problem *probs, int32_t B,
                                 void *state, const int64_t *elem_offsets, const cil_stepping *stepping,
                                 cil_solve_report *reports, void *hip_stream);

@@ -102,9 +102,9 @@ __global__ void k_plain_reaction_sbdf2(const DevSolve *S, const int *list, const
             r[q] = v + T(dt) * f;
             r[N2 + q] = w + T(dt) * g;
         } else {
-            const T c = T(2.0 * dt / 3.0);
-            r[q] = (T(4) * v - up[q]) / T(3) + c * (T(2) * f - fp[q]);
-            r[N2 + q] = (T(4) * w - up[N2 + q]) / T(3) + c * (T(2) * g - fp[N2 + q]);
+            const T c = T(2.0 * dt / 3.0), third = T(1.0 / 3.0);
+            r[q] = (T(4) * v - up[q]) * third + c * (T(2) * f - fp[q]);
+            r[N2 + q] = (T(4) * w - up[N2 + q]) * third + c * (T(2) * g - fp[N2 + q]);
         }
         up[q] = v;
         up[N2 + q] = w;
@@ -350,6 +350,85 @@ __global__ __launch_bounds__(2 * N) void k_fused(const DevSolve *S, const int *l
             for (int j = 0; j < N; ++j) ms[ln * LD + j] = x[j];
         }
         __syncthreads();
+    });
+}
+
+// Second-order line variant (semi-implicit BDF2): as k_fused, with the
+// history u^{s-2}, F(u^{s-2}) resident in LDS beside the state.  The first
+// step of the launch is the IMEX-Euler step (tables tabE, built with dt);
+// later steps take r = (4 u^{s-1} - u^{s-2}) / 3 + (2 dt / 3)(2 F(u^{s-1}) -
+// F(u^{s-2})) and the diffusion solve with 2 dt / 3 (tables tabB).
+template <typename T, int N>
+__global__ __launch_bounds__(2 * N) void k_fused_sbdf2(const DevSolve *S, const int *list, T *state, const T *tabE,
+                                                       const T *tabB, int model, double dt, PersistArgs pa)
+{
+    using D = DctLine<T, N>;
+    constexpr int LD = N + 1, SP = N * LD, THREADS = 2 * N;
+    __shared__ T sm[6 * SP];                       // state [2][N][N+1], then u^{s-2}, then F(u^{s-2})
+    T *uh = sm + 2 * SP, *fh = sm + 4 * SP;
+    const int b = list[blockIdx.x];
+    const DevSolve s = S[b];
+    T *u = state + s.off;
+    const size_t toff = (size_t)s.tab * 2 * N * N;
+    const int tid = threadIdx.x;
+    const int sp = tid / N, ln = tid % N;
+    T p[4] = {T(s.p[0]), T(s.p[1]), T(s.p[2]), T(s.p[3])};
+    const T tdt = T(dt), c23 = T(2.0 * dt / 3.0), third = T(1.0 / 3.0);   // a multiply, not a divide
+    T *ms = sm + sp * SP;
+    bool first = true;
+    run_solve<T, N, THREADS>(sm, u, b, dt, pa, [&]() {
+        dispatch_model(model, [&](auto MD) {        // reaction stage, pointwise
+            for (int q = tid; q < N * N; q += THREADS) {
+                const int a = (q / N) * LD + q % N;
+                const T v = sm[a], w = sm[SP + a];
+                T f, g;
+                kinetics<MD>(p, v, w, f, g);
+                if (first) {
+                    sm[a] = v + tdt * f;
+                    sm[SP + a] = w + tdt * g;
+                } else {
+                    sm[a] = (T(4) * v - uh[a]) * third + c23 * (T(2) * f - fh[a]);
+                    sm[SP + a] = (T(4) * w - uh[SP + a]) * third + c23 * (T(2) * g - fh[SP + a]);
+                }
+                uh[a] = v;
+                uh[SP + a] = w;
+                fh[a] = f;
+                fh[SP + a] = g;
+            }
+        });
+        __syncthreads();
+        {   // forward DCT along rows
+            T x[N], X[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) x[j] = ms[ln * LD + j];
+            D::forward(x, X);
+#pragma unroll
+            for (int j = 0; j < N; ++j) ms[ln * LD + j] = X[j];
+        }
+        __syncthreads();
+        {   // forward along columns, spectral divide, inverse along columns
+            T x[N], X[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[i] = ms[i * LD + ln];
+            D::forward(x, X);
+            const T *tb = (first ? tabE : tabB) + toff + (size_t)sp * N * N + ln;
+#pragma unroll
+            for (int k = 0; k < N; ++k) X[k] *= tb[k * N];
+            D::inverse(X, x);
+#pragma unroll
+            for (int i = 0; i < N; ++i) ms[i * LD + ln] = x[i];
+        }
+        __syncthreads();
+        {   // inverse along rows
+            T x[N], X[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) X[j] = ms[ln * LD + j];
+            D::inverse(X, x);
+#pragma unroll
+            for (int j = 0; j < N; ++j) ms[ln * LD + j] = x[j];
+        }
+        __syncthreads();
+        first = false;
     });
 }
 
@@ -761,8 +840,10 @@ bool mixed_supported(int n, bool quad)
 // Spectral tables for the solves in `ids` (side n): one per distinct (h, nu);
 // sets hs[b].tab.  Returns the device table buffer.
 template <typename T>
-int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSolve> &hs, void **tables, bool vform)
+int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSolve> &hs, void **tables, bool vform,
+                double dt_tab = 0.0)
 {
+    const double dtt = dt_tab > 0.0 ? dt_tab : c.dt;
     std::map<std::tuple<double, double, double>, int> uniq;
     std::vector<TabSpec> specs;
     for (int b : ids) {
@@ -782,12 +863,12 @@ int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSo
         CIL_TRY(c.cb->alloc(tables, sizeof(T) * per * specs.size()));
         dim3 grid((unsigned)((2 * (n / 2 + 1) * n + 255) / 256), (unsigned)specs.size());
         hipLaunchKernelGGL(k_make_vtables<T>, grid, dim3(256), 0, c.st, (const TabSpec *)dspecs, (int)specs.size(), n,
-                           c.dt, (T *)*tables);
+                           dtt, (T *)*tables);
         return check_launch("k_make_vtables");
     }
     CIL_TRY(c.cb->alloc(tables, sizeof(T) * (size_t)2 * n * n * specs.size()));
     dim3 grid((2 * n * n + 255) / 256, (unsigned)specs.size());
-    hipLaunchKernelGGL(k_make_tables<T>, grid, dim3(256), 0, c.st, (const TabSpec *)dspecs, (int)specs.size(), n, c.dt,
+    hipLaunchKernelGGL(k_make_tables<T>, grid, dim3(256), 0, c.st, (const TabSpec *)dspecs, (int)specs.size(), n, dtt,
                        (T *)*tables);
     return check_launch("k_make_tables");
 }
@@ -897,6 +978,66 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
     return CIL_OK;
 }
 
+// Second-order fused solves (line variant; n = 32, and n = 64 in FP32, where
+// state and history fit the LDS of one workgroup), one launch per grid side,
+// in order on the caller's stream.
+bool sbdf2_fused_supported(int n, bool f32) { return n == 32 || (n == 64 && f32); }
+
+template <typename T>
+int run_fused_sbdf2(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<DevSolve> &hs, DevSolve *dS,
+                    T *state, double floor_coef, long long *dsteps, double *dres, int *dstat)
+{
+    if (byn.empty()) return CIL_OK;
+    const bool f32 = std::is_same<T, float>::value;
+    std::vector<void *> tabE, tabB;
+    for (auto &kv : byn) {
+        void *te, *tb;
+        CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &te, false, c.dt));
+        CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &tb, false, 2.0 * c.dt / 3.0));
+        tabE.push_back(te);
+        tabB.push_back(tb);
+    }
+    const int B = (int)hs.size();
+    CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
+    std::vector<long long> hsteps(c.steps.begin(), c.steps.end());
+    CIL_HIP(hipMemcpyAsync(dsteps, hsteps.data(), sizeof(long long) * B, hipMemcpyHostToDevice, c.st));
+    PersistArgs pa{(long long)c.max_steps, c.tol, c.check, floor_coef, dsteps, dres, dstat, 0.0};
+    int gi = 0;
+    for (auto &kv : byn) {
+        const int n = kv.first, nl = (int)kv.second.size();
+        int *dl;
+        CIL_TRY(c.cb->alloc((void **)&dl, sizeof(int) * nl));
+        CIL_HIP(hipMemcpyAsync(dl, kv.second.data(), sizeof(int) * nl, hipMemcpyHostToDevice, c.st));
+        const T *te = (const T *)tabE[gi], *tb = (const T *)tabB[gi];
+        ++gi;
+        const char *name = n == 32 ? (f32 ? "k_fused_sbdf2_f32_n32" : "k_fused_sbdf2_f64_n32") : "k_fused_sbdf2_f32_n64";
+        const ProfMark pm = prof_begin(name, c.st);
+        if (n == 32)
+            hipLaunchKernelGGL((k_fused_sbdf2<T, 32>), dim3(nl), dim3(64), 0, c.st, dS, dl, state, te, tb, c.model,
+                               c.dt, pa);
+        else if constexpr (std::is_same<T, float>::value) {
+            if (n == 64)
+                hipLaunchKernelGGL((k_fused_sbdf2<T, 64>), dim3(nl), dim3(128), 0, c.st, dS, dl, state, te, tb,
+                                   c.model, c.dt, pa);
+        }
+        prof_end(pm, c.st);
+        CIL_TRY(check_launch(name));
+    }
+    std::vector<double> hres(B);
+    std::vector<int> hstat(B);
+    CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipStreamSynchronize(c.st));
+    for (auto &kv : byn)
+        for (int b : kv.second) {
+            c.steps[b] = hsteps[b];
+            c.fres[b] = hres[b];
+            c.status[b] = hstat[b];
+        }
+    return CIL_OK;
+}
+
 // Plain solves: host-driven lockstep loop from a common step `start`; a
 // launch per stage per step, the residual read back every check_every steps.
 template <typename T>
@@ -999,8 +1140,8 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     const bool polish = f32 && stp->polish && stp->tol > 0.0;
     const bool quad = stp->path != CIL_PATH_FUSED_LINE;
     if (scheme) {
-        if (stp->path != CIL_PATH_AUTO && stp->path != CIL_PATH_PLAIN)
-            return set_error(CIL_EUNSUPPORTED, "the second-order stepper runs on the plain back-end only");
+        if (stp->path == CIL_PATH_FUSED_QUAD)
+            return set_error(CIL_EUNSUPPORTED, "the second-order stepper has no quad-lane kernel");
         if (polish)
             return set_error(CIL_EUNSUPPORTED, "the second-order stepper has no FP64 polish: set polish = 0");
     }
@@ -1028,13 +1169,14 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     std::map<int, std::vector<int>> fused_byn, plain_byn;
     for (int b = 0; b < B; ++b) {
         const int n = hs[b].n;
-        const bool fs = fused_supported(n, f32);
+        const bool fs = scheme ? sbdf2_fused_supported(n, f32) : fused_supported(n, f32);
         if (stp->path >= CIL_PATH_FUSED && !fs)
-            return set_error(CIL_EUNSUPPORTED, "no fused stepper for n = %d in %s", n, f32 ? "FP32" : "FP64");
-        if (fs && stp->path != CIL_PATH_PLAIN && !scheme) fused_byn[n].push_back(b);
+            return set_error(CIL_EUNSUPPORTED, "no fused %sstepper for n = %d in %s", scheme ? "second-order " : "", n,
+                             f32 ? "FP32" : "FP64");
+        if (fs && stp->path != CIL_PATH_PLAIN) fused_byn[n].push_back(b);
         else plain_byn[n].push_back(b);
     }
-    if (scheme) {
+    if (scheme && !plain_byn.empty()) {              // the plain back-end keeps the history in HBM
         int64_t end = 0;
         for (int b = 0; b < B; ++b) end = std::max<int64_t>(end, hs[b].off + elems[b]);
         const size_t es = f32 ? sizeof(float) : sizeof(double);
@@ -1066,9 +1208,15 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         CIL_TRY(cb.alloc((void **)&mx.state64, sizeof(double) * (size_t)end));
         CIL_TRY(cb.alloc((void **)&mx.sw, sizeof(long long) * B));
     }
-    if (f32) CIL_TRY(run_fused<float>(c, fused_byn, hs, dS, (float *)state, quad, c.floor_coef32, dsteps, dres, dstat,
-                                      use_mixed ? &mx : nullptr));
-    else CIL_TRY(run_fused<double>(c, fused_byn, hs, dS, (double *)state, quad, 0.0, dsteps, dres, dstat));
+    if (scheme) {
+        if (f32) CIL_TRY(run_fused_sbdf2<float>(c, fused_byn, hs, dS, (float *)state, c.floor_coef32, dsteps, dres, dstat));
+        else CIL_TRY(run_fused_sbdf2<double>(c, fused_byn, hs, dS, (double *)state, 0.0, dsteps, dres, dstat));
+    } else if (f32) {
+        CIL_TRY(run_fused<float>(c, fused_byn, hs, dS, (float *)state, quad, c.floor_coef32, dsteps, dres, dstat,
+                                 use_mixed ? &mx : nullptr));
+    } else {
+        CIL_TRY(run_fused<double>(c, fused_byn, hs, dS, (double *)state, quad, 0.0, dsteps, dres, dstat));
+    }
     if (!plain_byn.empty()) {
         CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, st));
         std::vector<PlainGroup> pg;

@@ -1,5 +1,6 @@
 """GPU parity of the second-order IMEX stepper (semi-implicit BDF2,
-`cil_simulate_patterns_sbdf2`, plain back-end) against the FP64 oracle.
+`cil_simulate_patterns_sbdf2`; the fused line kernel at n = 32 and n = 64 in
+FP32, the plain back-end elsewhere or on request) against the FP64 oracle.
 
 Error measure and bars as for IMEX Euler: max |gpu - oracle| / max |oracle|;
 1e-10 for FP64 at fixed step counts, 1e-4 for FP32; residual-stopped FP64
@@ -32,17 +33,19 @@ def rel_err(a, b):
     return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+@pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("case,n,L,dt,steps", [(FHN, 32, 1.0, 0.01, 300), (GM, 17, 1.0, 0.05, 200),
                                                (GMS, 33, 60.0, 0.2, 150), (BZ, 64, 1.0, 0.05, 120),
-                                               (FHN, 2, 1.0, 0.01, 50)])
-def test_fp64_trajectory_parity(cil, oracle_mod, case, n, L, dt, steps):
+                                               (FHN, 2, 1.0, 0.01, 50), (GMS, 32, 60.0, 0.2, 150),
+                                               (BZ, 32, 1.0, 0.05, 200)])
+def test_fp64_trajectory_parity(cil, oracle_mod, path, case, n, L, dt, steps):
     model, p, nu = case
-    print("sbdf2 fp64 model=%d n=%d" % (model, n), flush=True)
+    print("sbdf2 fp64 model=%d n=%d path=%d" % (model, n, path), flush=True)
     base = oracle_mod.homogeneous_state(model, p)
     ics = cs.initial_conditions(base, n, 3, seed=60 + model, law="additive_pos")
     st = torch.tensor(ics, dtype=torch.float64, device="cuda")
     rep = cil.cil_simulate_patterns(model, st, cil.make_problems(n, L, nu, p, count=3), dt, steps,
-                                    check_every=steps, scheme="sbdf2")
+                                    check_every=steps, scheme="sbdf2", path=path)
     out, _, ores, _ = oracle_mod.imex_run(model, p, nu, n, L, dt, steps, 0.0, steps, state=ics.copy(), nthreads=8,
                                           scheme="sbdf2")
     assert rel_err(st.cpu().numpy(), out) <= 1e-10
@@ -75,9 +78,10 @@ def test_ragged_sides_and_offsets(cil, oracle_mod):
         assert np.all(g[o_ + x.size:o_ + x.size + 5] == 7.0)    # the gaps are untouched
 
 
-def test_residual_stopped_runs_take_the_oracles_steps(cil, oracle_mod):
+@pytest.mark.parametrize("n,L", [(16, 30.0), (32, 60.0)])
+def test_residual_stopped_runs_take_the_oracles_steps(cil, oracle_mod, n, L):
     model, p, nu = GMS
-    n, L, dt, tol, check = 16, 30.0, 0.2, 1e-8, 25
+    dt, tol, check = 0.2, 1e-8, 25
     base = oracle_mod.homogeneous_state(model, p)
     ics = cs.initial_conditions(base, n, 4, seed=81, law="multiplicative")
     st = torch.tensor(ics, device="cuda")
@@ -92,9 +96,10 @@ def test_residual_stopped_runs_take_the_oracles_steps(cil, oracle_mod):
     assert rel_err(st.cpu().numpy(), out) <= 1e-8
 
 
+@pytest.mark.parametrize("n", [16, 32])
 @pytest.mark.parametrize("dt,S", [(1e-3, 1), (1e-3, 50), (2e-2, 40)])
-def test_heat_mode_closed_form(cil, oracle_mod, dt, S):
-    n, L, nu = 16, 1.0, (0.3, 0.7)
+def test_heat_mode_closed_form(cil, oracle_mod, dt, S, n):
+    L, nu = 1.0, (0.3, 0.7)
     h = L / (n - 1)
     i = np.arange(n)
     mode = lambda k: np.cos(np.pi * k * (i + 0.5) / n)
@@ -114,22 +119,27 @@ def test_heat_mode_closed_form(cil, oracle_mod, dt, S):
     assert np.abs(st.cpu().numpy()[0] - want).max() <= 1e-13
 
 
-def test_fp32_trajectory_and_floor(cil, oracle_mod):
+@pytest.mark.parametrize("n,path", [(32, 0), (32, 1), (64, 0)])
+def test_fp32_trajectory(cil, oracle_mod, n, path):
     model, p, nu = FHN
-    n, L, dt = 32, 1.0, 0.01
+    L, dt = 1.0, 0.01
     base = oracle_mod.homogeneous_state(model, p)
     ics = cs.initial_conditions(base, n, 3, seed=90, law="additive_sym").astype(np.float32).astype(np.float64)
     st = torch.tensor(ics, dtype=torch.float32, device="cuda")
     cil.cil_simulate_patterns(model, st, cil.make_problems(n, L, nu, p, count=3), dt, 200, check_every=200,
-                              scheme="sbdf2", polish=0)
+                              scheme="sbdf2", polish=0, path=path)
     out, _, _, _ = oracle_mod.imex_run(model, p, nu, n, L, dt, 200, 0.0, 200, state=ics.copy(), scheme="sbdf2")
     assert rel_err(st.double().cpu().numpy(), out) <= 1e-4
-    # FP32 cannot certify 1e-12: the solves stop at the FP32 floor
+
+
+@pytest.mark.parametrize("n,L", [(16, 30.0), (32, 60.0)])
+def test_fp32_floor_status(cil, oracle_mod, n, L):
+    """FP32 cannot certify 1e-12: the solves stop at the FP32 floor."""
     model, p, nu = GMS
     base = oracle_mod.homogeneous_state(model, p)
-    st = torch.tensor(cs.initial_conditions(base, 16, 2, seed=91, law="multiplicative"), dtype=torch.float32,
+    st = torch.tensor(cs.initial_conditions(base, n, 2, seed=91, law="multiplicative"), dtype=torch.float32,
                       device="cuda")
-    rep = cil.cil_simulate_patterns(model, st, cil.make_problems(16, 30.0, nu, p, count=2), 0.2, 20000, tol=1e-12,
+    rep = cil.cil_simulate_patterns(model, st, cil.make_problems(n, L, nu, p, count=2), 0.2, 20000, tol=1e-12,
                                     check_every=25, scheme="sbdf2", polish=0, fp32_floor_ulps=32)
     assert np.all(rep["status"] == cil.CIL_SOLVE_FP32_FLOOR)
 
@@ -138,8 +148,16 @@ def test_sbdf2_argument_errors(cil):
     model, p, nu = FHN
     st = torch.zeros(1, 2, 32, 32, dtype=torch.float32, device="cuda")
     probs = cil.make_problems(32, 1.0, nu, p, count=1)
-    with pytest.raises(cil.CilError):                      # fused paths do not run this scheme
-        cil.cil_simulate_patterns(model, st, probs, 0.01, 10, path=cil.CIL_PATH_FUSED, scheme="sbdf2")
+    with pytest.raises(cil.CilError):                      # no quad-lane kernel for this scheme
+        cil.cil_simulate_patterns(model, st, probs, 0.01, 10, path=cil.CIL_PATH_FUSED_QUAD, scheme="sbdf2")
+    st17 = torch.zeros(1, 2, 17, 17, dtype=torch.float32, device="cuda")
+    with pytest.raises(cil.CilError):                      # no fused kernel for this side
+        cil.cil_simulate_patterns(model, st17, cil.make_problems(17, 1.0, nu, p, count=1), 0.01, 10,
+                                  path=cil.CIL_PATH_FUSED, scheme="sbdf2")
+    st64 = torch.zeros(1, 2, 64, 64, dtype=torch.float64, device="cuda")
+    with pytest.raises(cil.CilError):                      # FP64 history at n = 64 does not fit the LDS
+        cil.cil_simulate_patterns(model, st64, cil.make_problems(64, 1.0, nu, p, count=1), 0.01, 10,
+                                  path=cil.CIL_PATH_FUSED_LINE, scheme="sbdf2")
     with pytest.raises(cil.CilError):                      # no FP64 polish
         cil.cil_simulate_patterns(model, st, probs, 0.01, 10, tol=1e-8, polish=1, scheme="sbdf2")
     with pytest.raises(ValueError):
