@@ -72,11 +72,11 @@ def test_radii_rejects_degenerate_range():
         cil.cil_radii(0.0, 4.0, 5)
 
 
-def _simulate_raw(probs, stepping, B=None, state=1):
+def _simulate_raw(probs, stepping, B=None, state=1, entry="cil_simulate_patterns"):
     L = cil.lib()
     B = len(probs) if B is None else B
-    return L.cil_simulate_patterns(0, 0, ctypes.cast(probs, ctypes.c_void_p), B,
-                                   ctypes.c_void_p(state), None, ctypes.byref(stepping), None, None)
+    return getattr(L, entry)(0, 0, ctypes.cast(probs, ctypes.c_void_p), B,
+                             ctypes.c_void_p(state), None, ctypes.byref(stepping), None, None)
 
 
 def test_simulate_argument_validation_before_device():
@@ -94,6 +94,23 @@ def test_simulate_argument_validation_before_device():
     probs_badL = cil.make_problems(8, -1.0, (0.1, 0.1), (1.0, 1.0, 1.0))
     assert _simulate_raw(probs_badL, good) == cil.CIL_EINVAL
     assert _simulate_raw(probs, good, B=0) == cil.CIL_OK                          # empty batch
+
+
+def test_second_order_entry_validates_like_the_euler_one():
+    """The second-order entry point takes the same checks before any device
+    work; the binding rejects an unknown scheme before calling the library."""
+    good = cil.Stepping(dt=0.01, max_steps=10, tol=0.0, check_every=1, path=0, polish=0, fp32_floor_ulps=0)
+    e = "cil_simulate_patterns_sbdf2"
+    assert _simulate_raw(cil.make_problems(1, 1.0, (0.1, 0.1), (1.0, 1.0, 1.0)), good, entry=e) == cil.CIL_EINVAL
+    probs = cil.make_problems(8, 1.0, (0.1, 0.1), (1.0, 1.0, 1.0))
+    for field, val in (("dt", 0.0), ("max_steps", -1), ("check_every", 0), ("path", 7)):
+        st = cil.Stepping(dt=0.01, max_steps=10, tol=0.0, check_every=1, path=0, polish=0, fp32_floor_ulps=0)
+        setattr(st, field, val)
+        assert _simulate_raw(probs, st, entry=e) == cil.CIL_EINVAL, field
+    assert _simulate_raw(probs, good, state=0, entry=e) == cil.CIL_EINVAL
+    assert _simulate_raw(probs, good, B=0, entry=e) == cil.CIL_OK
+    with pytest.raises(ValueError):
+        cil.cil_simulate_patterns(0, None, probs, 0.01, 10, scheme="rk4")
 
 
 def test_statistic_argument_validation():
