@@ -51,6 +51,18 @@ __global__ void k_shift_vector(const float *A, long long nA, const float *B, lon
 
 // ------------------------------------------------------------------ split
 // One workgroup per row: hi/lo into [n][dimP] (zero padded), |x^|^2 in FP64.
+// Rows whose FP32 data (and the shift vector) are 16-byte aligned with
+// dim % 4 == 0 move four elements per lane (16-byte loads, 8-byte stores);
+// other rows go one element per lane.  The split of each element is the same
+// either way; only the order of the FP64 norm accumulation differs.
+__device__ __forceinline__ void split_one(float xs, __bf16 &bh, __bf16 &bl, double &s)
+{
+    bh = (__bf16)xs;
+    bl = (__bf16)(xs - (float)bh);
+    const double v = (double)(float)bh + (double)(float)bl;
+    s = fma(v, v, s);
+}
+
 __global__ __launch_bounds__(256) void k_split_rows(const float *X, long long dim, long long dimP, const float *c,
                                                     __bf16 *hi, __bf16 *lo, double *norm2)
 {
@@ -60,17 +72,34 @@ __global__ __launch_bounds__(256) void k_split_rows(const float *X, long long di
     __bf16 *h = hi + r * dimP;
     __bf16 *l = lo + r * dimP;
     double s = 0.0;
-    for (long long k = threadIdx.x; k < dimP; k += blockDim.x) {
-        __bf16 bh = (__bf16)0.0f, bl = (__bf16)0.0f;
-        if (k < dim) {
-            const float xs = x[k] - c[k];
-            bh = (__bf16)xs;
-            bl = (__bf16)(xs - (float)bh);
-            const double v = (double)(float)bh + (double)(float)bl;
-            s = fma(v, v, s);
+    const bool vec = (dim & 3) == 0 && (dimP & 3) == 0 && (((uintptr_t)x | (uintptr_t)c) & 15) == 0;
+    if (vec) {
+        for (long long k = 4 * (long long)threadIdx.x; k < dimP; k += 4 * (long long)blockDim.x) {
+            union {
+                __bf16 b[4];
+                uint2 u;
+            } ph, pl;
+            if (k < dim) {                          // dim % 4 == 0: all four elements are data
+                const float4 xv = *(const float4 *)(x + k);
+                const float4 cv = *(const float4 *)(c + k);
+                split_one(xv.x - cv.x, ph.b[0], pl.b[0], s);
+                split_one(xv.y - cv.y, ph.b[1], pl.b[1], s);
+                split_one(xv.z - cv.z, ph.b[2], pl.b[2], s);
+                split_one(xv.w - cv.w, ph.b[3], pl.b[3], s);
+            } else {
+                ph.u = make_uint2(0u, 0u);
+                pl.u = make_uint2(0u, 0u);
+            }
+            *(uint2 *)(h + k) = ph.u;
+            *(uint2 *)(l + k) = pl.u;
         }
-        h[k] = bh;
-        l[k] = bl;
+    } else {
+        for (long long k = threadIdx.x; k < dimP; k += blockDim.x) {
+            __bf16 bh = (__bf16)0.0f, bl = (__bf16)0.0f;
+            if (k < dim) split_one(x[k] - c[k], bh, bl, s);
+            h[k] = bh;
+            l[k] = bl;
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -356,7 +385,7 @@ int gram_prepare(const float *A, long long nA, const float *B, long long nB, lon
     CIL_TRY(ws_get(WS_DIST_COUNTS, sizeof(double) * (size_t)(nA + nB + 2) + sizeof(float) * (size_t)dimP + 64, &p));
     g->na = (double *)p;
     g->nb = g->na + nA + 1;
-    g->c = (float *)(g->nb + nB + 1);
+    g->c = (float *)(((uintptr_t)(g->nb + nB + 1) + 15) & ~(uintptr_t)15);   // 16-byte aligned (64 B of slack)
     g->dimP = dimP;
     if (dim > 0) {
         hipLaunchKernelGGL(k_shift_vector, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, st, A, nA, B, nB, dim,
