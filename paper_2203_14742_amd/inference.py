@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (cil_bootstrap_features, cil_gaussian_loglik, cil_pair_bins,
+from . import (CIL_SOLVE_NONFINITE, cil_bootstrap_features, cil_gaussian_loglik, cil_pair_bins,
                cil_pair_bins_adaptive, cil_simulate_patterns, make_problems)
 
 
@@ -53,13 +53,15 @@ class SyntheticCIL:
 
     def simulate(self, thetas):
         """The synthetic patterns of every proposal: device tensor
-        [P n_syn, 2 n^2], proposal-major, from one simulate call."""
+        [P n_syn, 2 n^2], proposal-major, from one simulate call.  Sets
+        `last_nonfinite` [P]: proposals with a solve that went non-finite."""
         thetas = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
         P, ns = thetas.shape[0], self.n_syn
         params = [self.params_of_theta(t) for t in thetas for _ in range(ns)]
         st = self.ic.repeat(P, 1, 1, 1).contiguous()
-        cil_simulate_patterns(self.model, st, make_problems(self.n, self.L, self.nu, params), self.dt, self.steps,
-                              check_every=self.steps)
+        rep = cil_simulate_patterns(self.model, st, make_problems(self.n, self.L, self.nu, params), self.dt,
+                                    self.steps, check_every=max(self.steps, 1), raise_on_nonfinite=False)
+        self.last_nonfinite = (rep["status"] == CIL_SOLVE_NONFINITE).reshape(P, ns).any(axis=1)
         return st.reshape(P * ns, 2 * self.n * self.n)
 
     def costs_from_patterns(self, S):
@@ -82,8 +84,21 @@ class SyntheticCIL:
         return np.where(status == 0, f, np.inf), np.where(status == 0, ll, -np.inf)
 
     def costs(self, thetas):
-        """f(theta) and the log-likelihoods of a batch of proposals."""
-        return self.costs_from_patterns(self.simulate(thetas))
+        """f(theta) and the log-likelihoods of a batch of proposals; a
+        proposal with a non-finite synthetic pattern gets f = inf and
+        loglik = -inf, the others are evaluated as usual."""
+        import torch
+        S = self.simulate(thetas)
+        bad = self.last_nonfinite
+        P = bad.size
+        f, ll = np.full(P, np.inf), np.full(P, -np.inf)
+        good = np.flatnonzero(~bad)
+        if good.size == P:
+            return self.costs_from_patterns(S)
+        if good.size:
+            rows = S.reshape(P, self.n_syn, -1)[torch.from_numpy(good).to(S.device)].reshape(good.size * self.n_syn, -1)
+            f[good], ll[good] = self.costs_from_patterns(rows.contiguous())
+        return f, ll
 
 
 def differential_evolution(cost_batch, bounds, pop: int = 20, generations: int = 50, F: float = 0.8,

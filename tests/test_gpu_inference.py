@@ -179,3 +179,18 @@ def test_single_pattern_scil_matches_oracle(cil, oracle_mod):
             assert f[p] == pytest.approx(r["f"], rel=1e-10) and ll[p] == pytest.approx(r["loglik"], rel=1e-10)
         else:
             assert f[p] == np.inf and ll[p] == -np.inf
+
+
+def test_nonfinite_proposal_costs_inf_and_spares_the_rest(problem):
+    """A proposal whose solves go non-finite (a NaN parameter here) gets
+    f = inf, loglik = -inf; the other proposals of the batch keep their
+    values."""
+    scil = problem["scil"]
+    t = problem["thetas"]
+    batch = np.stack([t[0], [np.nan, t[1][1]], t[2]])
+    f, ll = scil.costs(batch)
+    assert np.array_equal(scil.last_nonfinite, [False, True, False])
+    assert f[1] == np.inf and ll[1] == -np.inf
+    f2, ll2 = scil.costs(np.stack([t[0], t[2]]))
+    np.testing.assert_allclose(f[[0, 2]], f2, rtol=1e-9)
+    np.testing.assert_allclose(ll[[0, 2]], ll2, rtol=1e-9)
