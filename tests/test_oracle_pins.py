@@ -145,21 +145,29 @@ def _jacobian(model, p, v, w):
     if model == 1:
         mv, mw = p
         return np.array([[-mv + 2 * v / w, -v * v / (w * w)], [2 * v, -mw]])
+    if model == 2:
+        a, b = p
+        return np.array([[-b + 2 * v / w, -v * v / (w * w)], [2 * v, -1.0]])
     if model == 3:
         A, B = p
         return np.array([[-(B + 1) + 2 * v * w, v * v], [B - 2 * v * w, -v * v]])
     raise ValueError
 
 
-@pytest.mark.parametrize("model,p,nu,n,kl", [(0, FHN_P, FHN_NU, 32, (3, 8)),
-                                             (1, GM_P, GM_NU, 32, (2, 7)),
-                                             (3, BZ_P, BZ_NU, 32, (3, 10))])
-def test_P3_linear_single_mode_growth(oracle_mod, model, p, nu, n, kl):
+@pytest.mark.parametrize("model,p,nu,n,kl,L,dt,eps", [(0, FHN_P, FHN_NU, 32, (3, 8), 1.0, 0.01, 1e-6),
+                                                      (1, GM_P, GM_NU, 32, (2, 7), 1.0, 0.01, 1e-6),
+                                                      (2, GMS_P, GMS_NU, 64, (6, 11), 120.0, 0.2, 1e-7),
+                                                      (2, GMS_P, GMS_NU, 32, (3, 5), 60.0, 0.2, 1e-7),
+                                                      (3, BZ_P, BZ_NU, 32, (3, 10), 1.0, 0.01, 1e-6)])
+def test_P3_linear_single_mode_growth(oracle_mod, model, p, nu, n, kl, L, dt, eps):
     """A small perturbation along one cosine mode and one eigenvector of the
     per-step amplification matrix G = (I + dt Lambda diag nu)^-1 (I + dt J)
-    grows by exactly that eigenvalue per step (to first order)."""
+    grows by exactly that eigenvalue per step (to first order).  The
+    Gierer-Meinhardt source form runs on the stationarity workload's domain
+    (L = 120, dt = 0.2) and on a half-size one; it grows faster per step, so it
+    starts from a smaller perturbation eps."""
     o = oracle_mod
-    dt, steps, L = 0.01, 60, 1.0
+    steps = 60
     v0, w0 = o.homogeneous_state(model, p)
     J = _jacobian(model, p, v0, w0)
     Lam = lam_1d(n, L, kl[0]) + lam_1d(n, L, kl[1])
@@ -169,7 +177,17 @@ def test_P3_linear_single_mode_growth(oracle_mod, model, p, nu, n, kl):
     i = int(np.argmax(ev.real))
     rho, e = ev[i].real, V[:, i].real
     assert rho > 1.0                               # the mode is Turing-unstable
-    eps = 1e-6                                     # small: nonlinear terms O(eps)
+    # every Jacobian entry moves the predicted growth well past the bar, so a
+    # wrong partial derivative of the kinetics cannot pass
+    for (r, c) in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        Jw = J.copy()
+        Jw[r, c] *= 1.1
+        Gw = np.linalg.solve(np.eye(2) + dt * Lam * np.diag(nu), np.eye(2) + dt * Jw)
+        rw = np.abs(np.linalg.eigvals(Gw)).max()
+        assert abs((rw / rho) ** steps - 1.0) > 1e-3
+    # eps: small enough that the quadratic terms stay below the bar after
+    # `steps` steps of growth, large enough that rounding of the base state
+    # stays below it too
     mode = cs.cosine_mode(n, *kl)
     st = np.stack([v0 + eps * e[0] * mode, w0 + eps * e[1] * mode])[None]
     out, _, _, _ = o.imex_run(model, p, nu, n, L, dt, steps, state=st)
@@ -178,6 +196,96 @@ def test_P3_linear_single_mode_growth(oracle_mod, model, p, nu, n, kl):
     big = np.abs(mode) > 0.3
     assert np.abs(dv[big] / mode[big] - 1).max() < 1e-5
     assert np.abs(dw[big] / mode[big] - 1).max() < 1e-5
+
+
+def _ring_index(n):
+    k = np.arange(n)
+    return np.rint(np.hypot(k[:, None], k[None, :])).astype(int)
+
+
+@pytest.mark.parametrize("model,p,nu,n,L,dt", [(0, FHN_P, FHN_NU, 32, 1.0, 0.01),
+                                               (1, GM_P, GM_NU, 32, 1.0, 0.01),
+                                               (2, GMS_P, GMS_NU, 64, 120.0, 0.2),
+                                               (3, BZ_P, BZ_NU, 32, 1.0, 0.01)])
+def test_P4_dominant_wavenumber_of_the_dispersion_relation(oracle_mod, model, p, nu, n, L, dt):
+    """From small noise about the homogeneous state, the linear phase selects
+    the wavenumber at which the dispersion relation of eq. (rdgen) linearised
+    about that state peaks (Sec. 4.1, operator of App. B.1.1).
+
+    Prediction, written in the test: per cosine mode (k, l) the growth per
+    step is the spectral radius of G_kl = (I + dt Lambda_kl diag nu)^-1 (I + dt J);
+    the radially averaged expected power after S steps is the ring mean of
+    G's radius^(2S) (rings of integer |(k, l)|).  The continuous-time
+    relation sigma(q) = max Re eig(J - q^2 diag nu) gives k* in length units,
+    q* n h / pi in mode units.  The oracle's radially averaged DCT-II power of
+    the deviation after S steps (8 seeds) must peak within one ring of both.
+    S keeps the growth below 1e3 (amplitude 1e-3: still linear)."""
+    o = oracle_mod
+    import scipy.fft as sf
+    v0, w0 = o.homogeneous_state(model, p)
+    J = _jacobian(model, p, v0, w0)
+    h = L / (n - 1)
+    lam = np.array([lam_1d(n, L, k) for k in range(n)])
+    rho = np.empty((n, n))
+    for k in range(n):
+        for l in range(n):
+            G = np.linalg.solve(np.eye(2) + dt * (lam[k] + lam[l]) * np.diag(nu), np.eye(2) + dt * J)
+            rho[k, l] = np.abs(np.linalg.eigvals(G)).max()
+    assert rho[0, 0] <= 1.0 < rho.max()            # Turing: not unstable without diffusion (FHN: neutral)
+    S = int(math.log(1e3) / math.log(rho.max()))
+    ring = _ring_index(n)
+    cnt = np.bincount(ring.ravel())
+    pred = np.bincount(ring.ravel(), (rho ** (2 * S)).ravel()) / cnt
+    ring_pred = int(np.argmax(pred))
+    q = np.linspace(1e-4, math.pi / h, 40001)
+    sig = np.array([np.linalg.eigvals(J - qq * qq * np.diag(nu)).real.max() for qq in q])
+    ring_cont = int(round(q[int(np.argmax(sig))] * n * h / math.pi))
+    st = cs.initial_conditions((v0, w0), n, 8, seed=5, law="additive_sym", delta=1e-6)
+    out, _, _, _ = o.imex_run(model, p, nu, n, L, dt, S, state=st, nthreads=4)
+    dev = out - np.array([v0, w0])[None, :, None, None]
+    assert np.abs(dev).max() < 1e-2
+    power = (sf.dctn(dev, type=2, norm="ortho", axes=(2, 3)) ** 2).sum(axis=(0, 1))
+    avg = np.bincount(ring.ravel(), power.ravel()) / cnt
+    avg[0] = 0.0
+    ring_meas = int(np.argmax(avg))
+    assert abs(ring_meas - ring_pred) <= 1, (ring_meas, ring_pred)
+    assert abs(ring_meas - ring_cont) <= 1, (ring_meas, ring_cont)
+    assert abs(ring_pred - ring_cont) <= 1, (ring_pred, ring_cont)
+
+
+def test_two_oracle_solvers_part_under_pattern_selection(oracle_mod):
+    """The fixed-step FitzHugh-Nagumo workload (32^2, dt = 0.01, 128 solves)
+    run by the oracle's banded Cholesky solve and, in this test, by the dense
+    cosine-mode solve of App. B.1.1's operator (the same IMEX-Euler step):
+    both are FP64 and correct, yet while patterns select (Sec. 1) their
+    last-bit differences grow by orders of magnitude.  They agree within
+    1e-10 (relative to max|u|) at 1000 steps and part beyond it by 5000, so a
+    1e-10 bar at 5000 steps measures the problem's conditioning, not a
+    solver."""
+    o = oracle_mod
+    w = cs.WORKLOADS["fhn32_fixed5000"]
+    n, L, dt, nu = w["n"], w["L"], w["dt"], w["nu"]
+    mu, eps, alpha = w["params"]
+    base = o.homogeneous_state(w["model"], w["params"])
+    ics = np.concatenate([cs.initial_conditions(base, n, w["count"], seed=s, law=w["ic_law"]) for s in w["seeds"]])
+    h = L / (n - 1)
+    i = np.arange(n)
+    V = np.cos(np.pi * np.arange(n)[:, None] * (i + 0.5) / n)
+    V /= np.sqrt((V * V).sum(1, keepdims=True))
+    lam = (4.0 / h ** 2) * np.sin(np.pi * i / (2 * n)) ** 2
+    div = np.stack([1.0 / (1.0 + dt * nu[s] * (lam[:, None] + lam[None, :])) for s in range(2)])
+    cos_st, ref, done, errs = ics.copy(), ics.copy(), 0, {}
+    for upto in (1000, 5000):
+        for _ in range(upto - done):
+            v, u = cos_st[:, 0], cos_st[:, 1]
+            r = np.stack([v + dt * (eps * (u - alpha * v)), u + dt * (-v + mu * u - u * u * u)], 1)
+            cos_st = V.T @ ((V @ r @ V.T) * div) @ V
+        ref, _, _, _ = o.imex_run(w["model"], w["params"], nu, n, L, dt, upto - done, 0.0, upto - done,
+                                  state=ref, nthreads=8)
+        done = upto
+        errs[upto] = np.abs(cos_st - ref).max() / np.abs(ref).max()
+    assert errs[1000] < 1e-10, errs
+    assert errs[5000] > 1e-10, errs
 
 
 def test_P8_converged_pattern_solves_the_stencil_system(oracle_mod):
