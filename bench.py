@@ -116,9 +116,13 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64-fused", "--no-fp32-stepping", dest="no_secondary", action="store_true",
                     help="skip the secondary leg (the same step with FP64 fused stepping throughout)")
-    ap.add_argument("--cpu-sample-solves", type=int, default=384,
-                    help="solves the CPU oracle runs to stationarity for the cpu_baseline leg (about 10 s on 16 "
-                         "threads at the default)")
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="timed steps of the plain FP64 comparison leg (after one warm-up step)")
+    ap.add_argument("--cpu-sample-solves", type=int, default=500,
+                    help="solves the CPU oracle runs to stationarity for the cpu_baseline leg (the whole batch "
+                         "at the default: about 12 s on 16 threads)")
+    ap.add_argument("--cpu-single-solves", type=int, default=12,
+                    help="solves the CPU oracle runs on one thread for the single-thread figure")
     ap.add_argument("--gram-flush", type=int, default=64, choices=[32, 64, 128, 256],
                     help="features4096: FP32 -> FP64 promotion interval of the Gram")
     ap.add_argument("--gram-pipeline", type=int, default=2, choices=[0, 1, 2],
@@ -230,10 +234,13 @@ def main():
         t0 = time.perf_counter()
         cil_ms = 0.0
         reps = []
+        each.clear()
         for _ in range(steps):
+            t1 = time.perf_counter()
             rep, counts, e0, e1, out = one_step(state, ics, path, stat_fp32)
             reps.append(rep)
             torch.cuda.synchronize()
+            each.append(time.perf_counter() - t1)
             cil_ms += e0.elapsed_time(e1)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
@@ -243,6 +250,8 @@ def main():
                 prof[name] = cil.cil_profile_read(name)
             cil.cil_profile(False)
         return el, cil_ms / 1e3, reps, counts, out, prof
+
+    each = []
 
     # batched path: persistent fused FP32 stepping with the FP64 polish from
     # each solve's FP32 floor to the tolerance in the same launch; statistic on
@@ -299,17 +308,21 @@ def main():
 
     plain = None
     if not args.no_plain:
+        # the plain FP64 GPU path timed like the batched one: one warm-up step,
+        # then --plain-steps timed steps
         statep = torch.empty_like(ics64)
-        pel, pcil_s, preps, pcounts, _, _ = timed(statep, ics64, cil.CIL_PATH_PLAIN, False, 1, 0)
-        plain = {"patterns_per_s": round(B / pel, 3), "pairs_per_s": round(pairs / pcil_s, 1),
-                 "ms_per_step": round(1e3 * pel, 2),
-                 "speedup_patterns": round(patterns_per_s / (B / pel), 2),
-                 "speedup_pairs": round(pairs_per_s / (pairs / pcil_s), 2) if pairs_per_s else None,
+        ps_ = max(1, args.plain_steps)
+        pel, pcil_s, preps, pcounts, _, _ = timed(statep, ics64, cil.CIL_PATH_PLAIN, False, ps_, 1)
+        plain = {"patterns_per_s": round(B * ps_ / pel, 3), "pairs_per_s": round(pairs * ps_ / pcil_s, 1),
+                 "ms_per_step": round(1e3 * pel / ps_, 2), "steps": ps_, "warmup": 1,
+                 "ms_per_step_each": [round(1e3 * t, 2) for t in each],
+                 "speedup_patterns": round(patterns_per_s / (B * ps_ / pel), 2),
+                 "speedup_pairs": round(pairs_per_s / (pairs * ps_ / pcil_s), 2) if pairs_per_s else None,
                  "max_steps": int(preps[-1]["steps_taken"].max())}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, ics_host, base, args.cpu_sample_solves, half, d)
+        cpu = cpu_baseline(w, ics_host, base, args.cpu_sample_solves, half, d, args.cpu_single_solves)
 
     line = {
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
@@ -410,12 +423,13 @@ def features_main(args):
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()
-        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
+        threads = cpu_threads()
         k = 768                                          # about 10 s on 16 threads
         t1 = time.perf_counter()
         D = oracle.pair_d2(host[:k], host[half:half + k], nthreads=threads)
         tp = time.perf_counter() - t1
-        cpu = {"value": round(D.size / tp, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+        cpu = {"value": round(D.size / tp, 1), "unit": "pairs/s", "cores": threads, "host_cpus": os.cpu_count(),
+               "kind": "oracle",
                "sample": "%d x %d canonical pair distances of the same sets (%.1f s)" % (k, k, tp)}
     line = {
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
@@ -563,6 +577,10 @@ def fhn32_main(args):
 
     t_fast, rep, counts, prof = run(torch.float32, cil.CIL_PATH_FUSED)
     t_plain, rep64, counts64, prof64 = run(torch.float64, cil.CIL_PATH_PLAIN)
+    # the fused stepper in FP64: the same answers as the plain FP64 path (both
+    # within the FP64 trajectory bar of the oracle), so its speedup compares
+    # like with like
+    t_f64, rep_f64, counts_f64, _ = run(torch.float64, cil.CIL_PATH_FUSED)
     kname = "k_fused_q_f32_n32"
     cnt, tot_ms = prof[kname]
     flops = B * w["max_steps"] * fused_step_flops(w["n"], REACTION_FLOPS[w["model"]])
@@ -576,13 +594,14 @@ def fhn32_main(args):
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()
-        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
+        threads = cpu_threads()
         k = B                                            # the whole batch: a few seconds
         t1 = time.perf_counter()
         oracle.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], w["max_steps"], 0.0,
                         w["check_every"], state=ics_host[:k].copy(), nthreads=threads)
         tp = time.perf_counter() - t1
-        cpu = {"value": round(k / tp, 2), "unit": "patterns/s", "cores": threads, "kind": "oracle",
+        cpu = {"value": round(k / tp, 2), "unit": "patterns/s", "cores": threads, "host_cpus": os.cpu_count(),
+               "kind": "oracle",
                "sample": "%d solves x 5000 FP64 steps on the host (%.1f s)" % (k, tp)}
     line = {
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
@@ -598,8 +617,13 @@ def fhn32_main(args):
                        "speedup_patterns": round(t_plain / t_fast, 2),
                        "what": "FP64, five kernels per time step (reaction, row and column transforms with the "
                                "divide), direct FP64 distances"},
+        "fp64_fused": {"patterns_per_s": round(B / t_f64, 2), "ms_per_step": round(1e3 * t_f64, 3),
+                       "speedup_patterns_vs_plain": round(t_plain / t_f64, 2),
+                       "counts": [int(c) for c in counts_f64],
+                       "what": "the fused stepper in FP64 (the plain path's answers), FP64 statistic"},
         "counts_fp32_path": [int(c) for c in counts], "counts_fp64_path": [int(c) for c in counts64],
-        "all_ok": bool(np.all(rep["status"] == 0) and np.all(rep64["status"] == 0)),
+        "all_ok": bool(np.all(rep["status"] == 0) and np.all(rep64["status"] == 0) and
+                       np.all(rep_f64["status"] == 0)),
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())},
         "cpu_baseline": cpu,
@@ -931,34 +955,61 @@ def de_main(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(w, ics_host, base, n_solves, half, d):
-    """The FP64 oracle on host cores, on a bounded sample of the same step:
-    `n_solves` solves to stationarity, and the canonical distances of a block
-    of pairs of the resulting patterns; scaled to patterns/s of the full step
-    (solve time per pattern + pairs-per-pattern x time per pair)."""
+def cpu_threads() -> int:
+    """Threads the oracle runs on: the host's CPUs, capped by OMP_NUM_THREADS
+    (when set) and at 16."""
+    return min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
+
+
+def cpu_baseline(w, ics_host, base, n_solves, half, d, n_single):
+    """The FP64 oracle on host cores, on the same step: `n_solves` solves to
+    stationarity (the whole batch by default) on all the threads it may use,
+    the first `n_single` of them again on one thread, and the canonical
+    distances of a block of pairs of the resulting patterns; scaled to
+    patterns/s of the full step (solve time per pattern + pairs-per-pattern x
+    time per pair)."""
     import numpy as np
 
     import oracle
 
     oracle.build()
-    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16), 16)
+    threads = cpu_threads()
     ics = ics_host[:n_solves].copy()
     t0 = time.perf_counter()
     out, steps, res, status = oracle.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"],
                                               w["max_steps"], w["tol"], w["check_every"], state=ics,
                                               nthreads=threads)
     t_sim = time.perf_counter() - t0
-    k = n_solves // 2
+    k = min(n_solves // 2, 192)
     A = out[:k].reshape(k, -1).astype(np.float32)
     Bm = out[k:2 * k].reshape(k, -1).astype(np.float32)
     t1 = time.perf_counter()
     D = oracle.pair_d2(A, Bm, nthreads=threads)
     t_pairs = time.perf_counter() - t1
     sec_per_pattern = t_sim / n_solves + (half * half / (2 * half)) * (t_pairs / D.size)
-    return {"value": round(1.0 / sec_per_pattern, 4), "unit": "patterns/s", "cores": threads, "kind": "oracle",
-            "sample": "%d solves to residual < %g (%.1f s) + %d canonical pair distances (%.1f s), scaled to "
-                      "the full step" % (n_solves, w["tol"], t_sim, D.size, t_pairs),
-            "pairs_per_s": round(D.size / t_pairs, 1), "mean_steps": float(steps.mean())}
+    single = None
+    if n_single > 0:
+        t2 = time.perf_counter()
+        _, s1, _, _ = oracle.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], w["max_steps"],
+                                      w["tol"], w["check_every"], state=ics_host[:n_single].copy(), nthreads=1)
+        t_one = time.perf_counter() - t2
+        t3 = time.perf_counter()
+        D1 = oracle.pair_d2(A[:48], Bm[:48], nthreads=1)
+        t_p1 = time.perf_counter() - t3
+        # per pattern: this subsample's time per solve-step x the batch's mean
+        # steps (the subsample's solves need not have the batch's mean length)
+        per_solve = t_one / float(s1.sum()) * float(steps.mean())
+        sp1 = per_solve + (half * half / (2 * half)) * (t_p1 / D1.size)
+        single = {"value": round(1.0 / sp1, 4), "unit": "patterns/s", "cores": 1,
+                  "sample": "%d solves on one thread (%.1f s, %d solve-steps, scaled to the batch's mean of %.0f "
+                            "steps per solve) + %d canonical pair distances (%.2f s)"
+                            % (n_single, t_one, int(s1.sum()), float(steps.mean()), D1.size, t_p1)}
+    return {"value": round(1.0 / sec_per_pattern, 4), "unit": "patterns/s", "cores": threads,
+            "host_cpus": os.cpu_count(), "kind": "oracle",
+            "sample": "%d solves to residual < %g on %d threads (%.1f s) + %d canonical pair distances (%.1f s), "
+                      "scaled to the full step" % (n_solves, w["tol"], threads, t_sim, D.size, t_pairs),
+            "pairs_per_s": round(D.size / t_pairs, 1), "mean_steps": float(steps.mean()),
+            "single_thread": single}
 
 
 if __name__ == "__main__":

@@ -199,8 +199,10 @@ def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int
                           scheme: str = "euler"):
     """Run the solves in place on ``state`` (float32/float64 device tensor).
     scheme "euler": IMEX Euler (cil_simulate_patterns); "sbdf2": the
-    second-order IMEX stepper (cil_simulate_patterns_sbdf2, plain back-end,
-    FP32 with polish=0 only).
+    second-order IMEX stepper (cil_simulate_patterns_sbdf2; with the AUTO
+    path the fused line kernel k_fused_sbdf2 runs n = 32 in FP32 and FP64 and
+    n = 64 in FP32, the plain back-end every other side; FP32 with polish=0
+    only).
     Returns a dict of numpy arrays: steps_taken, steps_fp64, final_resid, status."""
     if scheme not in ("euler", "sbdf2"):
         raise ValueError("unknown scheme %r" % (scheme,))

@@ -126,6 +126,7 @@ struct ClassifyArgs {
     unsigned long long *nlist;
     long long cap;
     unsigned long long *minmax; // range: [min(D~+eps) bits, max(D~-eps) bits]
+    unsigned long long *flag;   // range: set when a distance is not finite
     double *dump_d, *dump_eps;  // dump
 };
 
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
                 hi = rhi[w] > hi ? rhi[w] : hi;
                 bad |= rbad[w];
             }
-            if (bad) atomicOr(c.nlist, 1ull << 63);   // flag: non-finite distance
+            if (bad) atomicOr(c.flag, 1ull);          // a non-finite distance
             if (lo != ~0ull) atomicMin(&c.minmax[0], lo);
             if (hi != 0ull) atomicMax(&c.minmax[1], hi);
         }
@@ -343,6 +344,7 @@ struct CanonOut {
     const int2 *pairs;
     const unsigned long long *npairs_dev;   // count for the list (clamped to cap)
     long long cap;
+    long long first;            // list mode: the launch covers pairs first, first + 1, ...
     const long long *ia, *jb;
     long long npairs;
     long long nA;               // index bounds for the ia/jb source
@@ -368,7 +370,10 @@ __global__ __launch_bounds__(WPP == 1 ? 256 : 64 * WPP) void k_canonical(const T
 {
     const int lane = threadIdx.x & 63;
     const int sub = WPP == 1 ? 0 : threadIdx.x / 64;
-    const long long w = WPP == 1 ? (long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64 : (long long)blockIdx.x;
+    // list mode: the grid may be sized before the list count is known (an
+    // upper bound); waves past the count leave at once
+    const long long w = (WPP == 1 ? (long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64
+                                  : (long long)blockIdx.x) + (o.pairs ? o.first : 0);
     const long long np = o.pairs ? (long long)min((unsigned long long)o.cap, *o.npairs_dev) : o.npairs;
     if (w >= np) return;
     long long i, j;
@@ -455,6 +460,7 @@ struct DistScratch {
     unsigned long long *nlist = nullptr;
     unsigned long long *nexact = nullptr;
     unsigned long long *minmax = nullptr;
+    unsigned long long *flag = nullptr;
     int2 *list = nullptr;
     long long cap = 0;
 };
@@ -469,12 +475,15 @@ int scratch(long long cap, DistScratch *s)
     s->nlist = (unsigned long long *)(c + 4096);
     s->nexact = s->nlist + 1;
     s->minmax = s->nlist + 2;
+    s->flag = s->nlist + 4;
     CIL_TRY(ws_get(WS_DIST_RECHECK, sizeof(int2) * (size_t)std::max<long long>(cap, 1), &p));
     s->list = (int2 *)p;
     s->cap = cap;
     return CIL_OK;
 }
 
+// Launches waves for pairs co.first .. co.first + nwaves - 1 (in list mode
+// nwaves may exceed the list: the surplus waves leave at once).
 template <typename T>
 int run_canonical(const T *A, const T *B, long long dim, CanonOut &co, long long nwaves, hipStream_t st)
 {
@@ -491,6 +500,11 @@ int run_canonical(const T *A, const T *B, long long dim, CanonOut &co, long long
 struct Approx {
     ClassifyArgs c{};
 };
+
+// Re-check launches are sized before the host knows the list's length: an
+// upper bound covers the usual case in the same stream pass, and only a
+// longer list costs a second launch after the count is read back.
+long long recheck_guess(long long dim) { return dim >= 4096 ? 256 : 2048; }
 
 // FP64 sets: direct differences, split over K so the grid fills the chip.
 int approx_pass(const double *A, long long nA, const double *B, long long nB, long long dim, Approx *ap,
@@ -586,10 +600,6 @@ int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long lo
     c.nlist = s.nlist;
     c.cap = s.cap;
     CIL_TRY(classify(c, nA, nB, st));
-    unsigned long long nre = 0;
-    CIL_HIP(hipMemcpyAsync(&nre, s.nlist, sizeof(nre), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
-    if ((long long)nre > s.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
     CanonOut co{};
     co.pairs = s.list;
     co.npairs_dev = s.nlist;
@@ -601,15 +611,26 @@ int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long lo
     co.nB = nB;
     co.nexact = s.nexact;
     co.force_exact = g_force_exact;
-    CIL_TRY(run_canonical(A, B, dim, co, (long long)nre, st));
+    const long long guess = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
+    CIL_TRY(run_canonical(A, B, dim, co, guess, st));
     hist_host.assign(M + 1, 0);
-    unsigned long long nex = 0;
+    unsigned long long cnt[2] = {0ull, 0ull};           // listed pairs, exact fallbacks
     CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipMemcpyAsync(&nex, s.nexact, sizeof(nex), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
+    const unsigned long long nre = cnt[0];
+    if ((long long)nre > s.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
+    if ((long long)nre > guess) {                       // the rest of a long list
+        co.first = guess;
+        CIL_TRY(run_canonical(A, B, dim, co, (long long)nre - guess, st));
+        CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost,
+                               st));
+        CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipStreamSynchronize(st));
+    }
     t_pairs = nA * nB;
     t_rechecked = (long long)nre;
-    t_exact = (long long)nex;
+    t_exact = (long long)cnt[1];
     return CIL_OK;
 }
 
@@ -621,28 +642,23 @@ template <typename T>
 int range_from_approx(const T *A, long long nA, const T *B, long long nB, long long dim, Approx &ap, DistScratch &s,
                       int excl, double *dmin, double *dmax, hipStream_t st)
 {
-    unsigned long long init[4] = {0ull, 0ull, (unsigned long long)0x7ff0000000000000ull, 0ull};  // nlist, nexact, +inf, 0
+    // nlist, nexact, min bound (+inf), max bound (0), non-finite flag
+    unsigned long long init[5] = {0ull, 0ull, (unsigned long long)0x7ff0000000000000ull, 0ull, 0ull};
     CIL_HIP(hipMemcpyAsync(s.nlist, init, sizeof(init), hipMemcpyHostToDevice, st));
     ClassifyArgs &c = ap.c;
     c.exclude_diag = excl;
     c.minmax = s.minmax;
+    c.flag = s.flag;
     c.list = s.list;
     c.nlist = s.nlist;
     c.cap = s.cap;
     c.mode = MODE_RANGE1;
     CIL_TRY(classify(c, nA, nB, st));
-    unsigned long long flag = 0;
-    CIL_HIP(hipMemcpyAsync(&flag, s.nlist, sizeof(flag), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
-    if (flag) return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
-    c.mode = MODE_RANGE2;
+    c.mode = MODE_RANGE2;                 // stream-ordered after the bounds of pass 1
     CIL_TRY(classify(c, nA, nB, st));
-    unsigned long long nc = 0;
-    CIL_HIP(hipMemcpyAsync(&nc, s.nlist, sizeof(nc), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
-    if ((long long)nc > s.cap) return set_error(CIL_EDEVICE, "range candidate overflow");
+    const long long guess = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
     double *cand;
-    CIL_TRY(ws_get(WS_DIST_NORMS, sizeof(double) * std::max<unsigned long long>(nc, 1), (void **)&cand));
+    CIL_TRY(ws_get(WS_DIST_NORMS, sizeof(double) * (size_t)guess, (void **)&cand));
     CanonOut co{};
     co.pairs = s.list;
     co.npairs_dev = s.nlist;
@@ -650,22 +666,36 @@ int range_from_approx(const T *A, long long nA, const T *B, long long nB, long l
     co.d2 = cand;
     co.nexact = s.nexact;
     co.force_exact = g_force_exact;
-    CIL_TRY(run_canonical(A, B, dim, co, (long long)nc, st));
-    std::vector<double> hc(nc);
-    if (nc) CIL_HIP(hipMemcpyAsync(hc.data(), cand, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
-    unsigned long long nex = 0;
-    CIL_HIP(hipMemcpyAsync(&nex, s.nexact, sizeof(nex), hipMemcpyDeviceToHost, st));
+    CIL_TRY(run_canonical(A, B, dim, co, guess, st));
+    std::vector<double> hc(guess);
+    unsigned long long cnt[5];
+    CIL_HIP(hipMemcpyAsync(hc.data(), cand, sizeof(double) * guess, hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
+    if (cnt[4]) return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
+    const long long nc = (long long)cnt[0];
+    if (nc > s.cap) return set_error(CIL_EDEVICE, "range candidate overflow");
+    if (nc > guess) {                     // the rest of a long candidate list
+        CIL_TRY(ws_get(WS_DIST_NORMS, sizeof(double) * (size_t)nc, (void **)&cand));
+        co.d2 = cand;
+        co.first = guess;
+        CIL_TRY(run_canonical(A, B, dim, co, nc - guess, st));
+        hc.resize(nc);
+        CIL_HIP(hipMemcpyAsync(hc.data() + guess, cand + guess, sizeof(double) * (nc - guess), hipMemcpyDeviceToHost,
+                               st));
+        CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipStreamSynchronize(st));
+    }
     double lo = INFINITY, hi = 0.0;
-    for (double v : hc) {
-        lo = std::min(lo, v);
-        hi = std::max(hi, v);
+    for (long long k = 0; k < nc; ++k) {
+        lo = std::min(lo, hc[k]);
+        hi = std::max(hi, hc[k]);
     }
     *dmin = lo;
     *dmax = hi;
     t_pairs = nA * nB;
-    t_rechecked = (long long)nc;
-    t_exact = (long long)nex;
+    t_rechecked = nc;
+    t_exact = (long long)cnt[1];
     return CIL_OK;
 }
 

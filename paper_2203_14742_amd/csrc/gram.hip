@@ -42,9 +42,21 @@ __global__ void k_shift_vector(const float *A, long long nA, const float *B, lon
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= dim) return;
     const long long sa = std::min<long long>(nA, 32), sb = std::min<long long>(nB, 32);
+    // all sampled values are loaded first (independent loads in flight
+    // together), then summed in row order
+    float va[32], vb[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+        va[r] = r < sa ? A[(r * nA / sa) * dim + k] : 0.0f;
+        vb[r] = r < sb ? B[(r * nB / sb) * dim + k] : 0.0f;
+    }
     double s = 0.0;
-    for (long long r = 0; r < sa; ++r) s += A[(r * nA / sa) * dim + k];
-    for (long long r = 0; r < sb; ++r) s += B[(r * nB / sb) * dim + k];
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+        if (r < sa) s += va[r];
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+        if (r < sb) s += vb[r];
     const long long cnt = sa + sb;
     c[k] = cnt ? (float)(s / (double)cnt) : 0.0f;
 }
@@ -63,17 +75,22 @@ __device__ __forceinline__ void split_one(float xs, __bf16 &bh, __bf16 &bl, doub
     s = fma(v, v, s);
 }
 
-__global__ __launch_bounds__(256) void k_split_rows(const float *X, long long dim, long long dimP, const float *c,
-                                                    __bf16 *hi, __bf16 *lo, double *norm2)
+// Both sets in one launch: blocks [0, nX) take rows of X, the rest rows of Y.
+__global__ __launch_bounds__(256) void k_split_rows(const float *X, long long nX, __bf16 *hiX, __bf16 *loX,
+                                                    double *normX, const float *Y, __bf16 *hiY, __bf16 *loY,
+                                                    double *normY, long long dim, long long dimP, const float *c)
 {
     __shared__ double red[4];
-    const long long r = blockIdx.x;
-    const float *x = X + r * dim;
-    __bf16 *h = hi + r * dimP;
-    __bf16 *l = lo + r * dimP;
+    const bool first = (long long)blockIdx.x < nX;
+    const long long r = first ? (long long)blockIdx.x : (long long)blockIdx.x - nX;
+    const float *x = (first ? X : Y) + r * dim;
+    __bf16 *h = (first ? hiX : hiY) + r * dimP;
+    __bf16 *l = (first ? loX : loY) + r * dimP;
+    double *norm2 = first ? normX : normY;
     double s = 0.0;
     const bool vec = (dim & 3) == 0 && (dimP & 3) == 0 && (((uintptr_t)x | (uintptr_t)c) & 15) == 0;
     if (vec) {
+#pragma unroll 4
         for (long long k = 4 * (long long)threadIdx.x; k < dimP; k += 4 * (long long)blockDim.x) {
             union {
                 __bf16 b[4];
@@ -393,12 +410,9 @@ int gram_prepare(const float *A, long long nA, const float *B, long long nB, lon
         CIL_TRY(check_launch("k_shift_vector"));
     }
     const ProfMark pm = prof_begin("k_split_rows", st);
-    if (nA > 0)
-        hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nA), dim3(256), 0, st, A, dim, dimP, (const float *)g->c,
-                           g->Ah, g->Al, g->na);
-    if (nB > 0)
-        hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nB), dim3(256), 0, st, B, dim, dimP, (const float *)g->c,
-                           g->Bh, g->Bl, g->nb);
+    if (nA + nB > 0)
+        hipLaunchKernelGGL(k_split_rows, dim3((unsigned)(nA + nB)), dim3(256), 0, st, A, nA, g->Ah, g->Al, g->na, B,
+                           g->Bh, g->Bl, g->nb, dim, dimP, (const float *)g->c);
     prof_end(pm, st);
     return check_launch("k_split_rows");
 }

@@ -20,8 +20,9 @@ template <int MAXM>
 __global__ __launch_bounds__(256) void k_bootstrap(const uint8_t *bins, long long nA, long long nB, int M,
                                                    const int *idxA, int kA, const int *idxB, int kB,
                                                    int rows_per_block, unsigned long long *Ycnt,
-                                                   int *bad)
+                                                   int *bad, const int *only_if)
 {
+    if (only_if && !(only_if[1] && !only_if[0])) return;   // after the MFMA path: only if it declined
     extern __shared__ int sh[];
     int *sidx = sh;                          // kB column indices of this resample
     unsigned int *red = (unsigned int *)(sh + kB);
@@ -71,8 +72,10 @@ __global__ __launch_bounds__(256) void k_bootstrap(const uint8_t *bins, long lon
 // sums: #{bin > m} = sum over v > m of hist[v].
 __global__ __launch_bounds__(256) void k_bootstrap_hist(const uint8_t *bins, long long nA, long long nB, int M,
                                                         const int *idxA, int kA, const int *idxB, int kB,
-                                                        int rows_per_block, unsigned long long *Ycnt, int *bad)
+                                                        int rows_per_block, unsigned long long *Ycnt, int *bad,
+                                                        const int *only_if)
 {
+    if (only_if && !(only_if[1] && !only_if[0])) return;
     extern __shared__ int sh[];
     int *sidx = sh;
     unsigned int *hist = (unsigned int *)(sh + kB);
@@ -174,8 +177,9 @@ __device__ __forceinline__ bf16x8_t thermometer(uint2 b, unsigned t)
 
 __global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long long nA, long long nB, int M,
                                                    const __bf16 *WA, long long ldA, const int *WB, int n_boot,
-                                                   unsigned long long *acc)
+                                                   unsigned long long *acc, const int *flags)
 {
+    if (flags[0] | flags[1]) return;      // an index out of range, or a multiplicity not exact in bf16
     __shared__ __attribute__((aligned(16))) __bf16 sA[32][BKC + 8];     // resample x i
     __shared__ __attribute__((aligned(16))) uint8_t sT[32][BKC + 16];   // column j x i
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -186,14 +190,29 @@ __global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long lon
 #pragma unroll
         for (int e = 0; e < 16; ++e) c[q][e] = 0.0f;
     for (long long i0 = 0; i0 < nA; i0 += BKC) {
-        __syncthreads();
-        for (int e = tid; e < 32 * (BKC / 8); e += 256) {          // W_A rows (zero padded)
-            const int row = e / (BKC / 8), ch = e % (BKC / 8);
-            *(bf16x8_t *)&sA[row][8 * ch] = *(const bf16x8_t *)(WA + (r0 + row) * ldA + i0 + 8 * ch);
+        // every load of the stage is issued before the first store to LDS
+        bf16x8_t va[32 * (BKC / 8) / 256];
+        uint8_t vt[BKC * 32 / 256];
+#pragma unroll
+        for (int q = 0; q < 32 * (BKC / 8) / 256; ++q) {            // W_A rows (zero padded)
+            const int e = tid + 256 * q, row = e / (BKC / 8), ch = e % (BKC / 8);
+            va[q] = *(const bf16x8_t *)(WA + (r0 + row) * ldA + i0 + 8 * ch);
         }
-        for (int e = tid; e < BKC * 32; e += 256) {                 // bins rows i, columns j -> sT[j][i]
-            const int i = e / 32, j = e % 32;
-            sT[j][i] = (i0 + i < nA && j0 + j < nB) ? bins[(i0 + i) * nB + j0 + j] : (uint8_t)0;
+#pragma unroll
+        for (int q = 0; q < BKC * 32 / 256; ++q) {                  // bins rows i, columns j
+            const int e = tid + 256 * q, i = e / 32, j = e % 32;
+            vt[q] = (i0 + i < nA && j0 + j < nB) ? bins[(i0 + i) * nB + j0 + j] : (uint8_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 32 * (BKC / 8) / 256; ++q) {
+            const int e = tid + 256 * q, row = e / (BKC / 8), ch = e % (BKC / 8);
+            *(bf16x8_t *)&sA[row][8 * ch] = va[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BKC * 32 / 256; ++q) {                  // -> sT[j][i]
+            const int e = tid + 256 * q, i = e / 32, j = e % 32;
+            sT[j][i] = vt[q];
         }
         __syncthreads();
 #pragma unroll 2
@@ -231,17 +250,45 @@ __global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long lon
     }
 }
 
-// MFMA path; returns 0 when it ran, 1 when a multiplicity exceeds 256 (the
-// caller then takes the gather path), or an error.
-int bootstrap_mfma(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA, const int *idxB,
-                   int kB, int n_boot, unsigned long long *acc, hipStream_t st, int *ran)
+// Device memory of one bootstrap call: the library's grow-only workspaces,
+// or (the allocation-free entry point) a fixed region carved in order.
+struct BootMem {
+    char *base = nullptr;           // null: workspaces
+    size_t cap = 0, used = 0;
+    // timing marks create HIP events: none on the allocation-free path
+    ProfMark mark(const char *name, hipStream_t st) const { return base ? ProfMark{} : prof_begin(name, st); }
+    int get(int slot, size_t bytes, void **p)
+    {
+        if (!base) return ws_get(slot, bytes, p);
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off + bytes > cap) return set_error(CIL_EINVAL, "bootstrap scratch of %zu bytes exceeds %zu", off + bytes, cap);
+        *p = base + off;
+        used = off + bytes;
+        return CIL_OK;
+    }
+};
+
+size_t boot_mult_bytes(long long nA, long long nB, int n_boot)
 {
-    *ran = 0;
+    const long long nbP = (n_boot + 31) / 32 * 32, ldA = (nA + BKC - 1) / BKC * BKC;
+    return sizeof(int) * (size_t)(nbP * ldA) + sizeof(int) * (size_t)n_boot * nB + sizeof(__bf16) * (size_t)(nbP * ldA) +
+           64;
+}
+
+// MFMA path.  It runs unless an index is out of range (flags[0]) or a
+// multiplicity exceeds 256 (flags[1], possible only for kA > 256): both are
+// known on the device only, so the kernel checks them itself; *flags_out
+// points at them for a gather launch that runs only when the MFMA kernel
+// declined (*may_decline).
+int bootstrap_mfma(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA, const int *idxB,
+                   int kB, int n_boot, unsigned long long *acc, hipStream_t st, const int **flags_out,
+                   bool *may_decline, BootMem &mem)
+{
     const long long nbP = (n_boot + 31) / 32 * 32, ldA = (nA + BKC - 1) / BKC * BKC;
     const size_t szA = sizeof(int) * (size_t)(nbP * ldA), szB = sizeof(int) * (size_t)n_boot * nB;
     const size_t szW = sizeof(__bf16) * (size_t)(nbP * ldA);
     void *p;
-    CIL_TRY(ws_get(WS_BOOT_MULT, szA + szB + szW + 64, &p));
+    CIL_TRY(mem.get(WS_BOOT_MULT, boot_mult_bytes(nA, nB, n_boot), &p));
     int *cA = (int *)p;
     int *cB = cA + nbP * ldA;
     __bf16 *wA = (__bf16 *)(cB + (size_t)n_boot * nB);
@@ -255,49 +302,58 @@ int bootstrap_mfma(const uint8_t *bins, long long nA, long long nB, int M, const
     hipLaunchKernelGGL(k_mult_to_bf16, dim3((unsigned)((nbP * ldA + 255) / 256)), dim3(256), 0, st, cA, nbP * ldA, wA,
                        flags + 1);
     CIL_TRY(check_launch("k_multiplicity"));
-    int hf[2] = {0, 0};
-    CIL_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
-    if (hf[0]) return set_error(CIL_EINVAL, "bootstrap index out of range");
-    if (hf[1]) return CIL_OK;                        // a multiplicity above 256: not exact in bf16
     dim3 grid((unsigned)((nB + 31) / 32), (unsigned)(nbP / 32));
-    const ProfMark pm = prof_begin("k_bootstrap", st);
-    hipLaunchKernelGGL(k_boot_mfma, grid, dim3(256), 0, st, bins, nA, nB, M, wA, ldA, cB, n_boot, acc);
+    const ProfMark pm = mem.mark("k_bootstrap", st);
+    hipLaunchKernelGGL(k_boot_mfma, grid, dim3(256), 0, st, bins, nA, nB, M, wA, ldA, cB, n_boot, acc, flags);
     prof_end(pm, st);
     CIL_TRY(check_launch("k_boot_mfma"));
-    *ran = 1;
+    *flags_out = flags;
+    *may_decline = kA > 256;
     return CIL_OK;
 }
 
-int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
-                   const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st)
+static bool boot_uses_mfma(int M) { return M <= 4 * BTPW && g_boot_mfma; }
+
+static int bootstrap_run(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
+                         const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st,
+                         BootMem &mem)
 {
     void *p;
     const long long n = (long long)n_boot * M;
-    CIL_TRY(ws_get(WS_BOOT_MISC, sizeof(unsigned long long) * (size_t)(n + 1), &p));
+    CIL_TRY(mem.get(WS_BOOT_MISC, sizeof(unsigned long long) * (size_t)(n + 1), &p));
     unsigned long long *acc = (unsigned long long *)p;
     int *bad = (int *)(acc + n);
     CIL_TRY(fill_zero(acc, sizeof(unsigned long long) * (size_t)(n + 1), st));
-    int ran = 0;
-    if (n_boot > 0 && kA > 0 && kB > 0 && M <= 4 * BTPW && g_boot_mfma)
-        CIL_TRY(bootstrap_mfma(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, acc, st, &ran));
-    if (!ran && n_boot > 0 && kA > 0 && kB > 0) {
-        // split the kA rows of a resample over enough blocks to fill the chip
+    const bool work = n_boot > 0 && kA > 0 && kB > 0;
+    bool mfma = false, may_decline = false;
+    const int *mflags = nullptr;
+    if (work && boot_uses_mfma(M)) {
+        CIL_TRY(bootstrap_mfma(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, acc, st, &mflags, &may_decline, mem));
+        mfma = true;
+    }
+    if (work && (!mfma || may_decline)) {
+        // gather path (after the MFMA kernel: only if that declined); the kA
+        // rows of a resample are split over enough blocks to fill the chip
+        const int *only_if = mfma ? mflags : nullptr;
         int slices = (int)std::max<long long>(1, std::min<long long>(kA, (2048 + n_boot - 1) / n_boot));
         const int rpb = (kA + slices - 1) / slices;
         slices = (kA + rpb - 1) / rpb;
         const size_t shmem = sizeof(int) * (size_t)kB + sizeof(unsigned int) * 256;
         dim3 grid(slices, n_boot);
         if (shmem > 160 * 1024) return set_error(CIL_EUNSUPPORTED, "kB too large for the bootstrap kernel");
-        const ProfMark pm = prof_begin("k_bootstrap", st);
+        const ProfMark pm = mem.mark("k_bootstrap", st);
         if (M <= 16)
-            hipLaunchKernelGGL(k_bootstrap<16>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc, bad);
+            hipLaunchKernelGGL(k_bootstrap<16>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc,
+                               bad, only_if);
         else if (M <= 32)
-            hipLaunchKernelGGL(k_bootstrap<32>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc, bad);
+            hipLaunchKernelGGL(k_bootstrap<32>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc,
+                               bad, only_if);
         else if (M <= 64)
-            hipLaunchKernelGGL(k_bootstrap<64>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc, bad);
+            hipLaunchKernelGGL(k_bootstrap<64>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc,
+                               bad, only_if);
         else
-            hipLaunchKernelGGL(k_bootstrap_hist, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc, bad);
+            hipLaunchKernelGGL(k_bootstrap_hist, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb,
+                               acc, bad, only_if);
         prof_end(pm, st);
         CIL_TRY(check_launch("k_bootstrap"));
     }
@@ -306,43 +362,63 @@ int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const
         hipLaunchKernelGGL(k_boot_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, n, denom, Ycount, Y);
         CIL_TRY(check_launch("k_boot_finish"));
     }
-    int hbad = 0;
-    CIL_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    int hbad[2] = {0, 0};
+    CIL_HIP(hipMemcpyAsync(&hbad[0], bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (mflags) CIL_HIP(hipMemcpyAsync(&hbad[1], mflags, sizeof(int), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
-    if (hbad) return set_error(CIL_EINVAL, "bootstrap index out of range");
+    if (hbad[0] || hbad[1]) return set_error(CIL_EINVAL, "bootstrap index out of range");
     return CIL_OK;
 }
 
+int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
+                   const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st)
+{
+    BootMem mem;
+    return bootstrap_run(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, Ycount, Y, st, mem);
+}
+
 // ---------------------------------------------------------- likelihood
-// One wavefront per problem.  mu and Sigma two-pass (1/(n-1)); bins with a
+// One workgroup per problem.  mu and Sigma two-pass (1/(n-1)); bins with a
 // sample variance of exactly 0 are dropped; Cholesky-Banachiewicz on the
 // kept bins in LDS; z = L^-1 (y - mu); f = |z|^2; loglik = -f/2 - sum log L_ii
-// - (m_eff/2) log 2 pi.  FP64 throughout.
+// - (m_eff/2) log 2 pi.  FP64 throughout.  The resample vectors are staged in
+// LDS by coalesced loads, as many rows at a time as fit (all of them for
+// M <= 15 and n <= 200); every sum still runs over the rows in order, so the
+// mean, the covariance and the dropped-bin decision are those of a plain
+// sequential two-pass evaluation.
 constexpr int LMAX = 64;
+constexpr int YSTAGE = 3072;                 // doubles of resample rows staged per chunk
 
 __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, const double *yobs,
                                                 double *f, double *loglik, int *meff, int *status)
 {
-    constexpr int RC = 32;                                   // rows staged per chunk
     constexpr int NE = (LMAX * (LMAX + 1) / 2 + 255) / 256;  // covariance entries per thread
     __shared__ double mu[LMAX];
     __shared__ double S[LMAX][LMAX + 1];
-    __shared__ double Yc[RC][LMAX];
+    __shared__ double Ys[YSTAGE];
     __shared__ int keep[LMAX];
     __shared__ int nk;
     __shared__ double z[LMAX];
     const int p = blockIdx.x;
     const int lane = threadIdx.x;
     const double *Yp = Y + (size_t)p * n * M;
+    const int RC = YSTAGE / M;                               // rows per chunk (>= 48)
+    const bool resident = n <= RC;                           // every row fits at once
 
-    if (lane < M) {
-        double s = 0.0;
-        for (int r = 0; r < n; ++r) s += Yp[(size_t)r * M + lane];
-        mu[lane] = s / n;
+    // pass 1: mean, each bin summed over the rows in order
+    double s = 0.0;
+    for (int r0 = 0; r0 < n; r0 += RC) {
+        const int cnt = min(RC, n - r0) * M;
+        __syncthreads();
+        for (int q = lane; q < cnt; q += 256) Ys[q] = Yp[(size_t)r0 * M + q];
+        __syncthreads();
+        if (lane < M)
+            for (int q = lane; q < cnt; q += M) s += Ys[q];
     }
+    if (lane < M) mu[lane] = s / n;
     __syncthreads();
-    // covariance entries (i, j), i >= j, spread over the threads; the centred
-    // rows are staged in LDS a chunk at a time, each entry sums over r in order
+    // covariance entries (i, j), i >= j, spread over the threads; each entry
+    // sums the products of the centred rows in order
     const int ne = M * (M + 1) / 2;
     double acc[NE];
     int ei[NE], ej[NE];
@@ -361,23 +437,26 @@ __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, c
     }
     for (int r0 = 0; r0 < n; r0 += RC) {
         const int rows = min(RC, n - r0);
-        for (int q = lane; q < rows * M; q += 256) {
-            const int r = q / M, m = q % M;
-            Yc[r][m] = Yp[(size_t)(r0 + r) * M + m] - mu[m];
+        if (resident) {                                      // centre the staged rows in place
+            for (int q = lane; q < rows * M; q += 256) Ys[q] -= mu[q % M];
+        } else {
+            __syncthreads();
+            for (int q = lane; q < rows * M; q += 256) Ys[q] = Yp[(size_t)r0 * M + q] - mu[q % M];
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < NE; ++t)
-            if (lane + 256 * t < ne)
-                for (int r = 0; r < rows; ++r) acc[t] += Yc[r][ei[t]] * Yc[r][ej[t]];
-        __syncthreads();
+            if (lane + 256 * t < ne) {
+                const double *a = Ys + ei[t], *b = Ys + ej[t];
+                for (int r = 0; r < rows; ++r) acc[t] += a[r * M] * b[r * M];
+            }
     }
 #pragma unroll
     for (int t = 0; t < NE; ++t)
         if (lane + 256 * t < ne) {
-            const double s = acc[t] / (n - 1);
-            S[ei[t]][ej[t]] = s;
-            S[ej[t]][ei[t]] = s;
+            const double sv = acc[t] / (n - 1);
+            S[ei[t]][ej[t]] = sv;
+            S[ej[t]][ei[t]] = sv;
         }
     __syncthreads();
     if (lane == 0) {

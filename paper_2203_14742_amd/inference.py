@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (CIL_SOLVE_NONFINITE, cil_bootstrap_features, cil_gaussian_loglik, cil_pair_bins,
+from . import (CIL_EINVAL, CIL_SOLVE_NONFINITE, CilError, cil_bootstrap_features, cil_gaussian_loglik, cil_pair_bins,
                cil_pair_bins_adaptive, cil_simulate_patterns, make_problems)
 
 
@@ -37,8 +37,9 @@ class SyntheticCIL:
         """params_of_theta(theta) -> the model's parameter tuple for proposal theta;
         data: device tensor [n_set, 2 n^2] (the observed patterns);
         ic_states: host array [n_syn, 2, n, n] (initial states shared by all proposals);
-        resample_index_lists: (s1 [n_boot, n_set], s2 [n_boot, N~], s1_obs [n_set]) as
-        `cil_synth.resample_synthetic` returns them."""
+        resample_index_lists: (s1 [n_boot, n_set], s2 [n_boot, n_syn - n_set], subset
+        [n_syn - n_set]) as `cil_synth.resample_synthetic` returns them; the subset
+        indexes the synthetic patterns the observed vector pairs with the data set."""
         import torch
         self.model, self.n, self.L, self.nu = model, n, L, nu
         self.params_of_theta = params_of_theta
@@ -65,23 +66,41 @@ class SyntheticCIL:
         return st.reshape(P * ns, 2 * self.n * self.n)
 
     def costs_from_patterns(self, S):
-        """f(theta) per proposal and the log-likelihoods (np.inf and -np.inf
-        where the covariance is not positive definite), from the synthetic patterns S
-        [P n_syn, 2 n^2] (proposal-major)."""
+        """f(theta) per proposal and the log-likelihoods, from the synthetic
+        patterns S [P n_syn, 2 n^2] (proposal-major).  np.inf and -np.inf
+        where the covariance is not positive definite, and where the
+        proposal's distinct synthetic patterns give no radius ladder (Sec. 3.2
+        fits the radii between the smallest and largest distance: two equal
+        patterns, or all distances equal, leave no range)."""
         import torch
         ns = self.n_syn
         P = S.shape[0] // ns
         Y = torch.empty((P, self.n_boot, self.M), dtype=torch.float64, device=S.device)
         yobs = torch.empty((P, self.M), dtype=torch.float64, device=S.device)
+        ok = np.ones(P, dtype=bool)
         for p in range(P):
             Sp = S[p * ns:(p + 1) * ns]
-            _, _, radii, bins, _ = cil_pair_bins_adaptive(Sp, Sp, self.M, exclude_diagonal=True)
+            try:
+                _, _, radii, bins, _ = cil_pair_bins_adaptive(Sp, Sp, self.M, exclude_diagonal=True)
+            except CilError as e:
+                if e.code != CIL_EINVAL:
+                    raise
+                # the arguments were checked before: the range is degenerate
+                ok[p] = False
+                continue
             _, Y[p] = cil_bootstrap_features(bins, self.idx[0], self.idx[1], self.M, want_counts=False)
             dbins, _ = cil_pair_bins(self.data, Sp, radii, want_counts=False)
             _, yobs[p] = cil_bootstrap_features(dbins, self.ident, self.idx[2], self.M, want_counts=False)
-        f, ll, _, status = cil_gaussian_loglik(Y, yobs)
-        f, ll, status = f.cpu().numpy(), ll.cpu().numpy(), status.cpu().numpy()
-        return np.where(status == 0, f, np.inf), np.where(status == 0, ll, -np.inf)
+        f, ll = np.full(P, np.inf), np.full(P, -np.inf)
+        good = np.flatnonzero(ok)
+        if good.size:
+            gi = torch.from_numpy(good).to(S.device)
+            fg, lg, _, status = cil_gaussian_loglik(Y[gi].contiguous(), yobs[gi].contiguous())
+            fg, lg, status = fg.cpu().numpy(), lg.cpu().numpy(), status.cpu().numpy()
+            f[good] = np.where(status == 0, fg, np.inf)
+            ll[good] = np.where(status == 0, lg, -np.inf)
+        self.last_degenerate = ~ok
+        return f, ll
 
     def costs(self, thetas):
         """f(theta) and the log-likelihoods of a batch of proposals; a

@@ -372,3 +372,32 @@ def test_end_to_end_fhn32_plain_fp64(cil, oracle_mod):
     radii = oracle_mod.power_radii(math.sqrt(D.max()), w["radii_base"], w["M"])
     c, y = cil.cil_features(A, B, radii)
     assert np.array_equal(c, oracle_mod.counts_from_d2(D, radii))
+
+
+def test_fhn32_fixed5000_fp32_statistic_within_two_percent(cil, oracle_mod):
+    """The plain method's configuration on the batched FP32 path (fused
+    stepper, the benchmark's batched leg): after 5000 FP32 steps the
+    correlation integral vector of the 64 x 64 cross pairs under the oracle's
+    16 radii R0 1.2^-m (eqs. eCDF, CIL) lies within 2 % (relative, Euclidean)
+    of the oracle's vector from its FP64 trajectories."""
+    w = cs.WORKLOADS["fhn32_fixed5000"]
+    base = oracle_mod.homogeneous_state(w["model"], w["params"])
+    ics = np.concatenate([cs.initial_conditions(base, w["n"], w["count"], seed=s, law=w["ic_law"])
+                          for s in w["seeds"]])
+    ics32 = ics.astype(np.float32).astype(np.float64)
+    ref, _, _, _ = oracle_mod.imex_run(w["model"], w["params"], w["nu"], w["n"], w["L"], w["dt"], w["max_steps"],
+                                       0.0, w["max_steps"], state=ics32.copy(), nthreads=16)
+    An, Bn = ref[:64].reshape(64, -1), ref[64:].reshape(64, -1)
+    D = oracle_mod.pair_d2(An, Bn)
+    radii = oracle_mod.power_radii(math.sqrt(D.max()), w["radii_base"], w["M"])
+    want = oracle_mod.counts_from_d2(D, radii) / float(D.size)
+    st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=ics.shape[0])
+    rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], check_every=w["check_every"])
+    assert np.all(rep["status"] == 0)
+    P = st.reshape(128, -1)
+    _, y = cil.cil_features(P[:64], P[64:], radii)
+    rel = np.linalg.norm(y - want) / np.linalg.norm(want)
+    print("fhn32 FP32 statistic: rel dev %.3e, counts %s vs %s" % (rel, (y * D.size).astype(int).tolist(),
+                                                                   (want * D.size).astype(int).tolist()), flush=True)
+    assert rel <= 0.02

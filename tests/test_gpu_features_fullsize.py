@@ -5,11 +5,13 @@ radii, 200 bootstrap resamples): the launch configuration of
 
 The oracle cannot take all 4.2e6 canonical distances at d = 32768 in seconds,
 so it checks: the range end points (the oracle's canonical distance of the
-candidate pairs an FP64 Gram ranks first), the bins of 3000 random pairs and
-of every pair whose distance lies within 1e-4 (relative) of a radius,
-bit-exact; counts and bootstrap vectors are checked through properties that
-hold at any size (histogram of the bins, monotonicity, the identity
-resample).
+candidate pairs an FP64 Gram ranks first) and the radii built from them; the
+bins of 3000 random pairs and of every pair whose distance lies within 1e-4
+(relative) of a radius, bit-exact against the oracle's bins of its own
+canonical distances under its own radii; counts and bootstrap vectors through
+properties that hold at any size (histogram of the bins, monotonicity, the
+identity resample).  The FP64 Gram only selects which pairs to check: no GPU
+value enters the oracle.
 """
 import numpy as np
 import pytest
@@ -59,6 +61,28 @@ def test_range_end_points(cil, oracle_mod, feat):
     assert (feat["lo"], feat["hi"]) == (feat["o_lo"], feat["o_hi"])
     assert np.array_equal(feat["radii"], feat["o_radii"])
     assert cil.cil_distance_range(feat["A"], feat["Bs"]) == (feat["lo"], feat["hi"])
+
+
+def test_bins_on_random_and_near_radius_pairs(cil, oracle_mod, feat):
+    """Sec. 2.1 eq. (eCDF): bin of a pair = #{m : D < R_m^2}, strict; the
+    oracle takes its canonical D of each checked pair and its own radii."""
+    host, half, D64, o_radii = feat["host"], feat["half"], feat["D64"], feat["o_radii"]
+    g = np.random.default_rng(11)
+    rand = g.integers(0, half * half, size=3000)
+    flat = D64.ravel()
+    near = np.zeros(flat.size, dtype=bool)
+    for t in o_radii * o_radii:
+        near |= np.abs(flat - t) <= 1e-4 * t
+    near_idx = np.flatnonzero(near)
+    idx = np.concatenate([rand, near_idx])
+    ia, jb = idx // half, idx % half
+    print("features4096: oracle distances of %d random + %d near-radius pairs" % (rand.size, near_idx.size),
+          flush=True)
+    Dc = oracle_mod.pair_d2_sampled(host[:half], host[half:], ia, jb, nthreads=16)
+    want = oracle_mod.bins_from_d2(Dc, o_radii)
+    got = feat["bins"].cpu().numpy()[ia, jb]
+    assert near_idx.size > 0
+    assert np.array_equal(got, want)
 
 
 def test_counts_are_the_bin_histogram(cil, feat):

@@ -93,6 +93,25 @@ def test_statistic_stage_matches_oracle(problem, oracle_mod):
             assert f[p] == np.inf
 
 
+def test_degenerate_proposal_costs_inf_and_the_rest_are_scored(problem, oracle_mod):
+    """A proposal whose synthetic patterns all coincide (every solve settled
+    on the same state) has no distance range to fit radii to (Sec. 3.2): it
+    costs inf (loglik -inf) and the other proposals of the batch are scored
+    as usual."""
+    want_S = oracle_patterns(oracle_mod, problem, problem["thetas"][:2])
+    S = want_S.copy()
+    S[NSYN:2 * NSYN] = S[NSYN]                       # proposal 1: one pattern, n_syn times
+    f, ll = problem["scil"].costs_from_patterns(torch.tensor(S, device="cuda"))
+    assert f[1] == np.inf and ll[1] == -np.inf
+    assert list(problem["scil"].last_degenerate) == [False, True]
+    r = oracle_cost(oracle_mod, problem, want_S[:NSYN])
+    if r["ok"]:
+        assert f[0] == pytest.approx(r["f"], rel=1e-10)
+        assert ll[0] == pytest.approx(r["loglik"], rel=1e-10)
+    else:
+        assert f[0] == np.inf
+
+
 def test_costs_chain_the_stages(problem):
     scil = problem["scil"]
     f, ll = scil.costs(problem["thetas"])
