@@ -353,6 +353,22 @@ int cil_bootstrap_features(const uint8_t *bins, int64_t nA, int64_t nB, int32_t 
                            const int32_t *idxA, int32_t kA, const int32_t *idxB, int32_t kB,
                            int32_t n_boot, int64_t *Ycount, double *Y, void *hip_stream);
 
+/* cil_bootstrap_features for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results and errors, but the call allocates
+ * nothing -- its counters, resample multiplicities and flags live in a fixed
+ * 16 MiB array per device that the library holds until the process ends.
+ * Sizes whose scratch would exceed it (about 8 n_boot M + 10 n_boot_32
+ * ceil128(nA) + 4 n_boot nB bytes, n_boot_32 = n_boot rounded up to 32; the
+ * last two terms only for M <= 32) return CIL_EINVAL before any device work.
+ * Every call on a device shares that device's array and keeps the last
+ * call's contents (what must start at zero is cleared by a kernel in each
+ * call), so calls that overlap on one device race; synchronises the stream
+ * (index check), like cil_bootstrap_features. */
+int cil_bootstrap_features_noalloc(const uint8_t *bins, int64_t nA, int64_t nB, int32_t M,
+                                   const int32_t *idxA, int32_t kA, const int32_t *idxB, int32_t kB,
+                                   int32_t n_boot, int64_t *Ycount, double *Y, void *hip_stream);
+
 /* Gaussian synthetic likelihood, batched over P independent problems
  * (eqs. cil:CF, cil:CF_synth): per problem p, mu = mean of the n_boot rows of
  * Y[p] (device double[P][n_boot][M]), Sigma = their covariance (1/(n_boot-1),

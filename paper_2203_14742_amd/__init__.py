@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.cil_approx_d2.restype = ctypes.c_int
         L.cil_last_distance_stats.argtypes = [vp, vp, vp]
         L.cil_bootstrap_features.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+        L.cil_bootstrap_features_noalloc.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp]
         L.cil_gaussian_loglik.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.cil_set_option.argtypes = [i32, i64]
         L.cil_profile.argtypes = [i32]
@@ -114,7 +115,7 @@ def lib() -> ctypes.CDLL:
         L.cil_sim_plan_destroy.argtypes = [vp]
         for name in ("cil_homogeneous_state", "cil_simulate_patterns", "cil_features", "cil_pair_bins",
                      "cil_distance_range", "cil_canonical_d2", "cil_radii", "cil_last_distance_stats",
-                     "cil_bootstrap_features", "cil_gaussian_loglik", "cil_set_option", "cil_shutdown",
+                     "cil_bootstrap_features", "cil_bootstrap_features_noalloc", "cil_gaussian_loglik", "cil_set_option", "cil_shutdown",
                      "cil_profile", "cil_profile_read", "cil_profile_names", "cil_sim_plan_create",
                      "cil_sim_plan_tune", "cil_sim_plan_launch", "cil_sim_plan_report", "cil_sim_plan_groups",
                      "cil_sim_plan_group_info", "cil_sim_plan_destroy", "cil_minmax_scale", "cil_augment_patterns",

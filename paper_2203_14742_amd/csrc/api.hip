@@ -34,6 +34,8 @@ template <typename T>
 int approx_d2_impl(const T *, long long, const T *, long long, long long, double *, double *, hipStream_t);
 int bootstrap_impl(const uint8_t *, long long, long long, int, const int *, int, const int *, int, int,
                    long long *, double *, hipStream_t);
+int bootstrap_noalloc_impl(const uint8_t *, long long, long long, int, const int *, int, const int *, int, int,
+                   long long *, double *, hipStream_t);
 int loglik_impl(const double *, int, int, int, const double *, double *, double *, int *, int *,
                 hipStream_t);
 int last_distance_stats(int64_t *, int64_t *, int64_t *);
@@ -580,6 +582,19 @@ int cil_bootstrap_features(const uint8_t *bins, int64_t nA, int64_t nB, int32_t 
     CIL_TRY(check_device());
     return bootstrap_impl(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, (long long *)Ycount, Y,
                           (hipStream_t)hip_stream);
+}
+
+int cil_bootstrap_features_noalloc(const uint8_t *bins, int64_t nA, int64_t nB, int32_t M, const int32_t *idxA,
+                                   int32_t kA, const int32_t *idxB, int32_t kB, int32_t n_boot, int64_t *Ycount,
+                                   double *Y, void *hip_stream)
+{
+    API_BEGIN();
+    if (M < 1 || M > 255) return set_error(CIL_EINVAL, "M must be in [1, 255]");
+    if (nA <= 0 || nB <= 0 || kA <= 0 || kB <= 0 || n_boot < 0) return set_error(CIL_EINVAL, "bad sizes");
+    if (!bins || !idxA || !idxB) return set_error(CIL_EINVAL, "null pointer");
+    CIL_TRY(check_device());
+    return bootstrap_noalloc_impl(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, (long long *)Ycount, Y,
+                                  (hipStream_t)hip_stream);
 }
 
 int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M, const double *y_obs, double *f,

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "cil_internal.hpp"
 
@@ -374,6 +376,56 @@ int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const
                    const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st)
 {
     BootMem mem;
+    return bootstrap_run(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, Ycount, Y, st, mem);
+}
+
+// ------------------------------------- bootstrap without allocation
+// For callers that cannot allocate device memory: the bootstrap's counters,
+// multiplicities and flags live in this fixed per-device array instead of
+// the library's workspaces.  Host code never passes the array's name to a
+// kernel: its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t BOOT_NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;   // 16 MiB per device
+static __device__ __align__(256) char scratch[BOOT_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_ptr;
+
+static int scratch_address(char **out)
+{
+    int dev;
+    CIL_TRY(current_device(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return set_error(CIL_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        it = g_scratch_ptr.emplace(dev, (char *)ptr).first;
+    }
+    *out = it->second;
+    return CIL_OK;
+}
+
+size_t bootstrap_noalloc_bytes(long long nA, long long nB, int M, int n_boot)
+{
+    const size_t acc = sizeof(unsigned long long) * (size_t)((long long)n_boot * M + 1);
+    size_t total = acc;
+    if (boot_uses_mfma(M)) total = ((total + 255) & ~(size_t)255) + boot_mult_bytes(nA, nB, n_boot);
+    return total;
+}
+
+int bootstrap_noalloc_impl(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
+                           const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st)
+{
+    const size_t need = bootstrap_noalloc_bytes(nA, nB, M, n_boot);
+    if (need > BOOT_NOALLOC_SCRATCH_BYTES)
+        return set_error(CIL_EINVAL, "the allocation-free bootstrap needs %zu bytes of scratch, its maximum is %zu",
+                         need, (size_t)BOOT_NOALLOC_SCRATCH_BYTES);
+    BootMem mem;
+    CIL_TRY(scratch_address(&mem.base));
+    mem.cap = BOOT_NOALLOC_SCRATCH_BYTES;
     return bootstrap_run(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, Ycount, Y, st, mem);
 }
 
