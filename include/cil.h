@@ -358,7 +358,7 @@ int cil_bootstrap_features(const uint8_t *bins, int64_t nA, int64_t nB, int32_t 
  * hipMalloc): same arguments, results and errors, but the call allocates
  * nothing -- its counters, resample multiplicities and flags live in a fixed
  * 16 MiB array per device that the library holds until the process ends.
- * Sizes whose scratch would exceed it (about 8 n_boot M + 10 n_boot_32
+ * Sizes whose scratch would exceed it (about 8 n_boot M + 6 n_boot_32
  * ceil128(nA) + 4 n_boot nB bytes, n_boot_32 = n_boot rounded up to 32; the
  * last two terms only for M <= 32) return CIL_EINVAL before any device work.
  * Every call on a device shares that device's array and keeps the last
