@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "fhn32_fixed5000", "features4096", "mcil_stripes64", "bz_uneven2048",
-                             "fhn128_mcmc", "fhn128_de", "fhn32_sbdf2"],
+                             "fhn128_mcmc", "fhn128_de", "fhn32_sbdf2", "gm_source64_lone"],
                     help="the default is the benchmarked configuration; features4096 times the CIL "
                          "statistic alone on 4096 x 32768 FP32 patterns")
     ap.add_argument("--steps", type=int, default=3)
@@ -132,6 +132,9 @@ def parse():
                     help="bz_uneven2048: steps per autotuning trial (0 = the plan's own stepping)")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the stepper sources (recorded beside the HBM counters) and exit")
+    ap.add_argument("--polish-separate", action="store_true",
+                    help="run the FP64 polish as a second launch over the promoted solves (CIL_OPT_POLISH_SEPARATE), "
+                         "so that counters separate the FP32 and FP64 phases")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "that scales HBM byte counters)")
@@ -173,6 +176,9 @@ def main():
     if args.workload == "fhn32_sbdf2":
         sbdf2_main(args)
         return
+    if args.workload == "gm_source64_lone":
+        lone_main(args)
+        return
 
     import cil_synth as cs
     import paper_2203_14742_amd as cil
@@ -180,6 +186,8 @@ def main():
     w = cs.WORKLOADS[WORKLOAD]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.polish_separate:
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 1)
     B, n = w["count"], w["n"]
     half = B // 2
     d = 2 * n * n
@@ -194,6 +202,8 @@ def main():
     idxB = torch.from_numpy(ib).to(dev)
     bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
     pat32 = torch.empty((B, d), dtype=torch.float32, device=dev)
+    y_pin = torch.empty(M, dtype=torch.float64, pin_memory=True)     # the observed vector, staged
+    y_obs = torch.empty(M, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -220,17 +230,21 @@ def main():
         A, Bs = pats[:half], pats[half:]
         lo, hi, radii, _, counts = cil.cil_pair_bins_adaptive(A, Bs, M, bins=bins)
         _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
-        y_obs = torch.tensor(counts / float(half * half), dtype=torch.float64, device=dev)
+        y_pin.copy_(torch.from_numpy(counts / float(half * half)))
+        y_obs.copy_(y_pin, non_blocking=True)
         out = cil.cil_gaussian_loglik(Y, y_obs)
         ev1.record(stream)
         return rep, counts, ev0, ev1, out
 
-    def timed(state, ics, path, stat_fp32, steps, warmup, profile=False):
+    def timed(state, ics, path, stat_fp32, steps, warmup, profile=0):
+        """profile 2: events around the stepper launches only (the timed
+        headline); 1: around every hot kernel (a separate pass for the
+        statistic's kernel table)."""
         for _ in range(warmup):
             one_step(state, ics, path, stat_fp32)
         torch.cuda.synchronize()
         if profile:
-            cil.cil_profile(True)
+            cil.cil_profile(profile)
         t0 = time.perf_counter()
         cil_ms = 0.0
         reps = []
@@ -258,7 +272,10 @@ def main():
     # the FP32 patterns
     state32 = torch.empty_like(ics32)
     el, cil_s, reps, counts, out, prof = timed(state32, ics32, cil.CIL_PATH_AUTO, True, args.steps, args.warmup,
-                                               profile=True)
+                                               profile=2)
+    # the statistic's kernels timed in a pass of their own after the timed
+    # region (events around its short launches would slow the timed one)
+    _, _, _, _, _, prof_stat = timed(state32, ics32, cil.CIL_PATH_AUTO, True, 2, 0, profile=1)
     K = args.steps
     ms_per_step = 1e3 * el / K
     patterns_per_s = B * K / el
@@ -270,6 +287,8 @@ def main():
     fp64_steps = sum(int(r["steps_fp64"].sum()) for r in reps)
 
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in sorted(prof.items())}
+    kernels_stat = {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / v[0], 2)}
+                    for k, v in sorted(prof_stat.items()) if not k.startswith("k_fused")}
     kname = max(prof, key=lambda k: prof[k][1]) if prof else None
     roof = None
     if kname and kname.startswith("k_fused"):
@@ -288,10 +307,10 @@ def main():
                 "solve_steps": solve_steps, "fp64_solve_steps": fp64_steps,
                 "peak_note": "weighted by the FP32 (157.3) and FP64 (78.6 TFLOP/s) steps of the launch"}
     gram = None
-    gk = "k_gram_dma" if "k_gram_dma" in prof else "k_gram_bf16x3"
-    if gk in prof:
-        cnt, tot_ms = prof[gk]
-        executed = 6.0 * d * pairs * K               # three bf16 products per element pair
+    gk = "k_gram_dma" if "k_gram_dma" in prof_stat else "k_gram_bf16x3"
+    if gk in prof_stat:
+        cnt, tot_ms = prof_stat[gk]
+        executed = 6.0 * d * pairs * cnt             # three bf16 products per element pair
         gram = {"kernel": gk, "bound": "mfma", "achieved": round(executed / (tot_ms * 1e-3) / 1e12, 3),
                 "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(executed / (tot_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
@@ -339,7 +358,9 @@ def main():
         "pairs_per_s": round(pairs_per_s, 1) if pairs_per_s else None,
         "solve_steps": solve_steps // K, "fp64_solve_steps": fp64_steps // K,
         "max_solve_steps": int(rep["steps_taken"].max()), "all_converged": status_ok,
-        "roofline": roof, "roofline_gram": gram, "kernels": kernels, "fp64_fused": fp64_fused,
+        "roofline": roof, "roofline_gram": gram, "kernels": kernels,
+        "statistic_kernels": {"what": "average launch times from 2 further profiled steps", "kernels": kernels_stat},
+        "fp64_fused": fp64_fused,
         "plain_fp64": plain, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -372,11 +393,14 @@ def features_main(args):
     bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
     pairs = half * half
+    y_pin = torch.empty(M, dtype=torch.float64, pin_memory=True)
+    y_obs = torch.empty(M, dtype=torch.float64, device=dev)
 
     def one_step():
         lo, hi, radii, _, counts = cil.cil_pair_bins_adaptive(A, Bs, M, bins=bins)
         _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
-        y_obs = torch.tensor(counts / float(pairs), dtype=torch.float64, device=dev)
+        y_pin.copy_(torch.from_numpy(counts / float(pairs)))
+        y_obs.copy_(y_pin, non_blocking=True)
         return cil.cil_gaussian_loglik(Y, y_obs), counts
 
     for _ in range(args.warmup):
@@ -951,6 +975,50 @@ def de_main(args):
         "best_cost_history": [round(h, 6) for h in r["history"]],
         "best_theta": [round(float(v), 6) for v in r["x"]],
         "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def lone_main(args):
+    """One Gierer-Meinhardt (source form) 64x64 solve alone on the GPU, 2000
+    fixed steps in FP32 and in FP64 on the fused stepper: the per-step latency
+    that bounds the stationarity batch's tail (its slowest solve ends up alone
+    on its CU).  `value` is the FP32 steps per second of the lone solve."""
+    import numpy as np
+    import torch
+
+    import cil_synth as cs
+    import paper_2203_14742_amd as cil
+
+    w = cs.WORKLOADS[WORKLOAD]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, steps = w["n"], 2000
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics_host = cs.initial_conditions(base, n, 1, seed=w["seeds"][0], law=w["ic_law"])
+    probs = cil.make_problems(n, w["L"], w["nu"], w["params"], count=1)
+    out = {}
+    for name, dtype in (("fp32", torch.float32), ("fp64", torch.float64)):
+        ics = torch.tensor(ics_host, dtype=dtype, device=dev)
+        st = torch.empty_like(ics)
+        best = None
+        for _ in range(max(1, args.warmup) + max(1, args.steps)):
+            st.copy_(ics)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], steps, check_every=w["check_every"], polish=0)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        out[name] = {"us_per_step": round(1e6 * best / steps, 3)}
+    line = {
+        "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
+        "value": round(1e6 / out["fp32"]["us_per_step"], 1), "unit": "solve-steps/s (one solve alone)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gm_source64_lone", "solves": 1, "grid": n, "fixed_steps": steps,
+                   "parallelism": "none (1 GPU)"},
+        "lone_step": out, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -358,7 +358,7 @@ int cil_bootstrap_features(const uint8_t *bins, int64_t nA, int64_t nB, int32_t 
  * hipMalloc): same arguments, results and errors, but the call allocates
  * nothing -- its counters, resample multiplicities and flags live in a fixed
  * 16 MiB array per device that the library holds until the process ends.
- * Sizes whose scratch would exceed it (about 8 n_boot M + 6 n_boot_32
+ * Sizes whose scratch would exceed it (about 8 n_boot M + 4 n_boot_32
  * ceil128(nA) + 4 n_boot nB bytes, n_boot_32 = n_boot rounded up to 32; the
  * last two terms only for M <= 32) return CIL_EINVAL before any device work.
  * Every call on a device shares that device's array and keeps the last
@@ -425,7 +425,9 @@ int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:
  * every hot kernel launch is then bracketed by two HIP events recorded on the
- * stream it is launched on; cil_profile(0) stops.  cil_profile_read gives the
+ * stream it is launched on; cil_profile(2) does the same for the fused
+ * stepper kernels only (no events on the statistic's short launches);
+ * cil_profile(0) stops.  cil_profile_read gives the
  * number of timed launches and their total duration in milliseconds for one
  * kernel name (0 and 0.0 if none); cil_profile_names writes the timed kernel
  * names, comma-separated, NUL-terminated, into buf[len].  Reading waits for

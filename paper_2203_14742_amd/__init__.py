@@ -505,8 +505,9 @@ def cil_set_option(option: int, value: int):
     _check(lib().cil_set_option(int(option), int(value)))
 
 
-def cil_profile(enable: bool):
-    _check(lib().cil_profile(int(bool(enable))))
+def cil_profile(enable):
+    """False/0: off; True/1: every hot kernel; 2: the fused stepper kernels only."""
+    _check(lib().cil_profile(2 if enable == 2 else int(bool(enable))))
 
 
 def cil_profile_read(name: str):

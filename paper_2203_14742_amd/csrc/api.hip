@@ -3,6 +3,7 @@
 // contract of every function.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -118,6 +119,32 @@ int ws_get(int slot, size_t bytes, void **ptr)
     return CIL_OK;
 }
 
+namespace {
+std::map<std::pair<int, int>, WsEntry> g_hs;
+}  // namespace
+
+int host_stage(int slot, size_t bytes, void **ptr)
+{
+    int dev;
+    CIL_TRY(current_device(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsEntry &w = g_hs[std::make_pair(dev, slot)];
+    if (w.bytes < bytes) {
+        if (w.ptr) (void)hipHostFree(w.ptr);
+        w.ptr = nullptr;
+        w.bytes = 0;
+        const size_t want = std::max<size_t>(bytes, 64 * 1024);
+        if (hipHostMalloc(&w.ptr, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            w.ptr = nullptr;
+            return set_error(CIL_ENOMEM, "pinned host buffer of %zu bytes failed", want);
+        }
+        w.bytes = want;
+    }
+    *ptr = w.ptr;
+    return CIL_OK;
+}
+
 int release_all()
 {
     std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -129,8 +156,11 @@ int release_all()
             (void)hipFree(kv.second.ptr);
         }
     }
+    for (auto &kv : g_hs)
+        if (kv.second.ptr) (void)hipHostFree(kv.second.ptr);
     (void)hipSetDevice(cur);
     g_ws.clear();
+    g_hs.clear();
     return CIL_OK;
 }
 
@@ -138,6 +168,7 @@ int release_all()
 namespace {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+bool g_prof_steppers_only = false;     // cil_profile(2): the fused stepper kernels only
 struct PendingEv {
     std::string name;
     hipEvent_t a, b;
@@ -172,6 +203,7 @@ ProfMark prof_begin(const char *name, hipStream_t st)
 {
     ProfMark m;
     if (!g_prof_on) return m;
+    if (g_prof_steppers_only && strncmp(name, "k_fused", 7) != 0) return m;
     // a stream being captured into a graph gets no timing events
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
@@ -693,9 +725,11 @@ int cil_set_option(int32_t option, int64_t value)
 int cil_profile(int32_t enable)
 {
     API_BEGIN();
+    if (enable < 0 || enable > 2) return set_error(CIL_EINVAL, "cil_profile takes 0, 1 or 2");
     prof_flush();
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = enable != 0;
+    g_prof_steppers_only = enable == 2;
     if (enable) g_prof.clear();
     return CIL_OK;
 }

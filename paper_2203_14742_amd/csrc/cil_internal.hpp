@@ -39,9 +39,15 @@ enum WsSlot {
     WS_STEP_WORK_B, WS_STEP_STATE64, WS_STEP_LIST64, WS_STEP_DCT,
     WS_DIST_NORMS, WS_DIST_SPLIT_A, WS_DIST_SPLIT_B, WS_DIST_RECHECK, WS_DIST_COUNTS,
     WS_DIST_MISC, WS_DIST_SAMPLE, WS_BOOT_MISC, WS_BOOT_MULT, WS_STATS_MISC, WS_FEAT_MISC, WS_FEAT_SEG,
+    WS_DIST_REDUCED,
     WS_NUM_SLOTS
 };
 int ws_get(int slot, size_t bytes, void **ptr);
+// Pinned host buffers for the small copies between the host and the device
+// inside a call (so they run asynchronously), grow-only, one per (device,
+// slot); freed by cil_shutdown().
+enum HostSlot { HS_DIST = 0, HS_BOOT, HS_NUM_SLOTS };
+int host_stage(int slot, size_t bytes, void **ptr);
 int current_device(int *dev);
 int release_all();
 // Zero device memory with a kernel (keeps memset nodes out of captured graphs).

@@ -127,6 +127,7 @@ struct ClassifyArgs {
     long long cap;
     unsigned long long *minmax; // range: [min(D~+eps) bits, max(D~-eps) bits]
     unsigned long long *flag;   // range: set when a distance is not finite
+    double *reduced;            // range pass 1: the summed partials of every pair, or null
     double *dump_d, *dump_eps;  // dump
 };
 
@@ -134,7 +135,20 @@ __device__ __forceinline__ void approx_pair(const ClassifyArgs &c, long long i, 
                                             long long nB, double &D, double &eps)
 {
     double s = 0.0;
-    for (int k = 0; k < c.S; ++k) s += c.P[(long long)k * nA * nB + i * nB + j];
+    const double *pp = c.P + i * nB + j;
+    const long long ps = nA * nB;
+    int k = 0;
+    for (; k + 8 <= c.S; k += 8) {               // eight loads in flight, added in order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pp[(k + u) * ps];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k < c.S; ++k) s += pp[k * ps];
+    // the sum of the partials, for the later passes (0 + s is s exactly, so
+    // they see the same D~ from one partial)
+    if (c.reduced) c.reduced[i * nB + j] = s;
     if (!c.gram) {
         D = s;
         eps = c.eps_rel * s;
@@ -170,9 +184,10 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
     // grid-stride over the pairs (the grid is capped, so per-block reductions stay few)
     for (long long e = (long long)blockIdx.x * 256 + tid; e < n; e += (long long)gridDim.x * 256) {
         const long long i = e / nB, j = e % nB;
-        if (c.exclude_diag && i == j) continue;
+        if (c.exclude_diag && i == j && !c.reduced) continue;
         double D, eps;
         approx_pair(c, i, j, nA, nB, D, eps);
+        if (c.exclude_diag && i == j) continue;     // summed for the later passes, not part of the range
         const bool finite = isfinite(D) && isfinite(eps);
         if (c.mode == MODE_BINS) {
             int bin = 0;
@@ -395,7 +410,20 @@ __global__ __launch_bounds__(WPP == 1 ? 256 : 64 * WPP) void k_canonical(const T
     const T *b = B + j * dim;
     double hi = 0.0, lo = 0.0;
     int inexact = 0;
-    for (long long k = lane + 64LL * sub; k < dim; k += 64LL * WPP) {
+    // four strides' loads in flight; terms accumulated in the same order
+    constexpr long long STR = 64LL * WPP;
+    long long k = lane + 64LL * sub;
+    for (; k + 3 * STR < dim; k += 4 * STR) {
+        double da[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) da[u] = ld(a + k + u * STR) - ld(b + k + u * STR);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double p = da[u] * da[u];
+            dd_add_t(hi, lo, p, fma(da[u], da[u], -p), inexact);
+        }
+    }
+    for (; k < dim; k += STR) {
         const double d = ld(a + k) - ld(b + k);
         const double p = d * d;
         dd_add_t(hi, lo, p, fma(d, d, -p), inexact);
@@ -558,7 +586,8 @@ int classify(ClassifyArgs &c, long long nA, long long nB, hipStream_t st)
     const long long n = nA * nB;
     if (n <= 0) return CIL_OK;
     const long long blocks = std::min<long long>((n + 255) / 256, 4096);
-    const ProfMark pm = prof_begin("k_classify", st);
+    static const char *const names[] = {"k_classify_bins", "k_classify_range1", "k_classify_range2", "k_classify_dump"};
+    const ProfMark pm = prof_begin(names[c.mode], st);
     hipLaunchKernelGGL(k_classify, dim3((unsigned)blocks), dim3(256), 0, st, c, nA, nB);
     prof_end(pm, st);
     return check_launch("k_classify");
@@ -585,11 +614,14 @@ int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long lo
                      const double *radii, int M, uint8_t *bins, std::vector<unsigned long long> &hist_host,
                      hipStream_t st)
 {
-    std::vector<double> thr(M);
+    // pinned staging: [0, 2048) thresholds, [2048, 4096) histogram, [4096, 4112) counters
+    char *hs;
+    CIL_TRY(host_stage(HS_DIST, 4096 + 64, (void **)&hs));
+    double *thr = (double *)hs;
     for (int m = 0; m < M; ++m) thr[m] = radii[m] * radii[m];
-    CIL_HIP(hipMemcpyAsync(s.thr, thr.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
-    CIL_TRY(fill_zero(s.hist, sizeof(unsigned long long) * (M + 1), st));
-    CIL_TRY(fill_zero(s.nlist, sizeof(unsigned long long) * 2, st));
+    CIL_HIP(hipMemcpyAsync(s.thr, thr, sizeof(double) * M, hipMemcpyHostToDevice, st));
+    // the histogram and the two list counters (contiguous) in one clear
+    CIL_TRY(fill_zero(s.hist, (char *)(s.nlist + 2) - (char *)s.hist, st));
     ClassifyArgs &c = ap.c;
     c.mode = MODE_BINS;
     c.thr = s.thr;
@@ -613,21 +645,21 @@ int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long lo
     co.force_exact = g_force_exact;
     const long long guess = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
     CIL_TRY(run_canonical(A, B, dim, co, guess, st));
-    hist_host.assign(M + 1, 0);
-    unsigned long long cnt[2] = {0ull, 0ull};           // listed pairs, exact fallbacks
-    CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    unsigned long long *hh = (unsigned long long *)(hs + 2048);
+    unsigned long long *cnt = (unsigned long long *)(hs + 4096);   // listed pairs, exact fallbacks
+    CIL_HIP(hipMemcpyAsync(hh, s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     const unsigned long long nre = cnt[0];
     if ((long long)nre > s.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
     if ((long long)nre > guess) {                       // the rest of a long list
         co.first = guess;
         CIL_TRY(run_canonical(A, B, dim, co, (long long)nre - guess, st));
-        CIL_HIP(hipMemcpyAsync(hist_host.data(), s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost,
-                               st));
-        CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipMemcpyAsync(hh, s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         CIL_HIP(hipStreamSynchronize(st));
     }
+    hist_host.assign(hh, hh + M + 1);
     t_pairs = nA * nB;
     t_rechecked = (long long)nre;
     t_exact = (long long)cnt[1];
@@ -642,9 +674,19 @@ template <typename T>
 int range_from_approx(const T *A, long long nA, const T *B, long long nB, long long dim, Approx &ap, DistScratch &s,
                       int excl, double *dmin, double *dmax, hipStream_t st)
 {
+    const long long guess = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
+    // pinned staging: [0, 40) initial counters, [64, 104) counters read back,
+    // [4096, ...) candidate distances read back
+    char *hs;
+    CIL_TRY(host_stage(HS_DIST, 4096 + sizeof(double) * (size_t)guess, (void **)&hs));
+    unsigned long long *init = (unsigned long long *)hs;
     // nlist, nexact, min bound (+inf), max bound (0), non-finite flag
-    unsigned long long init[5] = {0ull, 0ull, (unsigned long long)0x7ff0000000000000ull, 0ull, 0ull};
-    CIL_HIP(hipMemcpyAsync(s.nlist, init, sizeof(init), hipMemcpyHostToDevice, st));
+    init[0] = 0ull;
+    init[1] = 0ull;
+    init[2] = (unsigned long long)0x7ff0000000000000ull;
+    init[3] = 0ull;
+    init[4] = 0ull;
+    CIL_HIP(hipMemcpyAsync(s.nlist, init, 5 * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
     ClassifyArgs &c = ap.c;
     c.exclude_diag = excl;
     c.minmax = s.minmax;
@@ -652,11 +694,18 @@ int range_from_approx(const T *A, long long nA, const T *B, long long nB, long l
     c.list = s.list;
     c.nlist = s.nlist;
     c.cap = s.cap;
+    // pass 1 reads every partial once and leaves their sums, so that pass 2
+    // and the bins read one value per pair
+    if (c.S > 1) CIL_TRY(ws_get(WS_DIST_REDUCED, sizeof(double) * (size_t)std::max(nA * nB, 1LL), (void **)&c.reduced));
     c.mode = MODE_RANGE1;
     CIL_TRY(classify(c, nA, nB, st));
+    if (c.reduced) {
+        c.P = c.reduced;
+        c.S = 1;
+        c.reduced = nullptr;
+    }
     c.mode = MODE_RANGE2;                 // stream-ordered after the bounds of pass 1
     CIL_TRY(classify(c, nA, nB, st));
-    const long long guess = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
     double *cand;
     CIL_TRY(ws_get(WS_DIST_NORMS, sizeof(double) * (size_t)guess, (void **)&cand));
     CanonOut co{};
@@ -667,11 +716,12 @@ int range_from_approx(const T *A, long long nA, const T *B, long long nB, long l
     co.nexact = s.nexact;
     co.force_exact = g_force_exact;
     CIL_TRY(run_canonical(A, B, dim, co, guess, st));
-    std::vector<double> hc(guess);
-    unsigned long long cnt[5];
-    CIL_HIP(hipMemcpyAsync(hc.data(), cand, sizeof(double) * guess, hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    double *hcp = (double *)(hs + 4096);
+    unsigned long long *cnt = (unsigned long long *)(hs + 64);
+    CIL_HIP(hipMemcpyAsync(hcp, cand, sizeof(double) * guess, hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
+    std::vector<double> hc(hcp, hcp + guess);
     if (cnt[4]) return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
     const long long nc = (long long)cnt[0];
     if (nc > s.cap) return set_error(CIL_EDEVICE, "range candidate overflow");
@@ -683,7 +733,7 @@ int range_from_approx(const T *A, long long nA, const T *B, long long nB, long l
         hc.resize(nc);
         CIL_HIP(hipMemcpyAsync(hc.data() + guess, cand + guess, sizeof(double) * (nc - guess), hipMemcpyDeviceToHost,
                                st));
-        CIL_HIP(hipMemcpyAsync(cnt, s.nlist, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         CIL_HIP(hipStreamSynchronize(st));
     }
     double lo = INFINITY, hi = 0.0;

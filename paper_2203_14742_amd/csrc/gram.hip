@@ -36,19 +36,38 @@ constexpr int GKC = 256;         // split-K granularity (elements)
 
 // ------------------------------------------------------------------ shift
 // c_k = mean over up to 64 sampled rows of A and B (FP64 sum, rounded to FP32)
-__global__ void k_shift_vector(const float *A, long long nA, const float *B, long long nB, long long dim,
-                               float *c)
+// The sampled row offsets (r nA / sa) dim are the same for every thread: the
+// first 64 threads of a block compute them once into LDS.
+__global__ __launch_bounds__(64) void k_shift_vector(const float *A, long long nA, const float *B, long long nB,
+                                                      long long dim, float *c)
 {
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= dim) return;
+    __shared__ long long rowoff[64];
     const long long sa = std::min<long long>(nA, 32), sb = std::min<long long>(nB, 32);
-    // all sampled values are loaded first (independent loads in flight
-    // together), then summed in row order
+    const int t = threadIdx.x;
+    if (t < 32) rowoff[t] = t < sa ? (t * nA / sa) * dim : 0;
+    else rowoff[t] = t - 32 < sb ? ((t - 32) * nB / sb) * dim : 0;
+    __syncthreads();
+    const long long k = (long long)blockIdx.x * blockDim.x + t;
+    if (k >= dim || sa == 0 || sb == 0) {           // (an empty set: the mean of the other one)
+        if (k < dim && (sa | sb)) {
+            const float *X = sa ? A : B;
+            const long long sx = sa ? sa : sb, nx = sa ? nA : nB;
+            double s = 0.0;
+            for (long long r = 0; r < sx; ++r) s += X[(r * nx / sx) * dim + k];
+            c[k] = (float)(s / (double)sx);
+        } else if (k < dim) {
+            c[k] = 0.0f;
+        }
+        return;
+    }
+    // all sampled values are loaded first (independent, unconditional loads
+    // in flight together: rows past the sample repeat row 0 and are not
+    // added), then summed in row order
     float va[32], vb[32];
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
-        va[r] = r < sa ? A[(r * nA / sa) * dim + k] : 0.0f;
-        vb[r] = r < sb ? B[(r * nB / sb) * dim + k] : 0.0f;
+        va[r] = A[rowoff[r] + k];
+        vb[r] = B[rowoff[32 + r] + k];
     }
     double s = 0.0;
 #pragma unroll
@@ -405,8 +424,9 @@ int gram_prepare(const float *A, long long nA, const float *B, long long nB, lon
     g->c = (float *)(((uintptr_t)(g->nb + nB + 1) + 15) & ~(uintptr_t)15);   // 16-byte aligned (64 B of slack)
     g->dimP = dimP;
     if (dim > 0) {
-        hipLaunchKernelGGL(k_shift_vector, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, st, A, nA, B, nB, dim,
-                           g->c);
+        const ProfMark pm = prof_begin("k_shift_vector", st);
+        hipLaunchKernelGGL(k_shift_vector, dim3((unsigned)((dim + 63) / 64)), dim3(64), 0, st, A, nA, B, nB, dim, g->c);
+        prof_end(pm, st);
         CIL_TRY(check_launch("k_shift_vector"));
     }
     const ProfMark pm = prof_begin("k_split_rows", st);

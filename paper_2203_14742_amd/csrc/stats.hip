@@ -139,26 +139,30 @@ void set_boot_gather(int v) { g_boot_mfma = v ? 0 : 1; }
 constexpr int BKC = 128;     // i per LDS stage
 constexpr int BTPW = 8;      // thresholds per wavefront (M <= 32)
 
-__global__ void k_multiplicity(const int *idx, int k, int n_boot, long long n, int ld, int *cnt, int *bad)
+// Multiplicities of both index lists in one launch: elements e < n_boot kA
+// count idxA into cA[r][*] (row length ldA), the rest idxB into cB[r][*]
+// (row length nB).  flags[0]: an index out of range; flags[1]: a count of
+// cA above 256 (not exact in bf16).
+__global__ void k_multiplicity(const int *idxA, int kA, long long nA, int ldA, int *cA, const int *idxB, int kB,
+                               long long nB, int *cB, int n_boot, int *flags)
 {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)n_boot * k) return;
-    const long long r = e / k;
-    const int v = idx[e];
-    if (v < 0 || v >= n) {
-        atomicOr(bad, 1);
+    const long long eA = (long long)n_boot * kA;
+    if (e >= eA + (long long)n_boot * kB) return;
+    const bool isA = e < eA;
+    const long long f = isA ? e : e - eA;
+    const int k = isA ? kA : kB;
+    const long long r = f / k;
+    const int v = (isA ? idxA : idxB)[f];
+    if (v < 0 || v >= (isA ? nA : nB)) {
+        atomicOr(&flags[0], 1);
         return;
     }
-    atomicAdd(&cnt[r * ld + v], 1);
-}
-
-__global__ void k_mult_to_bf16(const int *cnt, long long total, __bf16 *w, int *over)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    const int v = cnt[e];
-    if (v > 256) atomicOr(over, 1);
-    w[e] = (__bf16)(float)v;
+    if (isA) {
+        if (atomicAdd(&cA[r * ldA + v], 1) >= 256) atomicOr(&flags[1], 1);
+    } else {
+        atomicAdd(&cB[r * nB + v], 1);
+    }
 }
 
 // 8 bin bytes -> 8 bf16 values [byte >= t] (bytes and t below 128): the high
@@ -178,12 +182,13 @@ __device__ __forceinline__ bf16x8_t thermometer(uint2 b, unsigned t)
 }
 
 __global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long long nA, long long nB, int M,
-                                                   const __bf16 *WA, long long ldA, const int *WB, int n_boot,
+                                                   const int *WA, long long ldA, const int *WB, int n_boot,
                                                    unsigned long long *acc, const int *flags)
 {
     if (flags[0] | flags[1]) return;      // an index out of range, or a multiplicity not exact in bf16
     __shared__ __attribute__((aligned(16))) __bf16 sA[32][BKC + 8];     // resample x i
     __shared__ __attribute__((aligned(16))) uint8_t sT[32][BKC + 16];   // column j x i
+    __shared__ int sred[4][16][65];                                    // per wavefront: [element][lane]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long r0 = (long long)blockIdx.y * 32, j0 = (long long)blockIdx.x * 32;
     floatx16_t c[BTPW];
@@ -193,23 +198,37 @@ __global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long lon
         for (int e = 0; e < 16; ++e) c[q][e] = 0.0f;
     for (long long i0 = 0; i0 < nA; i0 += BKC) {
         // every load of the stage is issued before the first store to LDS
-        bf16x8_t va[32 * (BKC / 8) / 256];
+        int4 va[2 * (32 * (BKC / 8) / 256)];
         uint8_t vt[BKC * 32 / 256];
 #pragma unroll
-        for (int q = 0; q < 32 * (BKC / 8) / 256; ++q) {            // W_A rows (zero padded)
+        for (int q = 0; q < 32 * (BKC / 8) / 256; ++q) {            // W_A rows (zero padded), 8 counts
             const int e = tid + 256 * q, row = e / (BKC / 8), ch = e % (BKC / 8);
-            va[q] = *(const bf16x8_t *)(WA + (r0 + row) * ldA + i0 + 8 * ch);
+            const int4 *src = (const int4 *)(WA + (r0 + row) * ldA + i0 + 8 * ch);
+            va[2 * q] = src[0];
+            va[2 * q + 1] = src[1];
         }
 #pragma unroll
-        for (int q = 0; q < BKC * 32 / 256; ++q) {                  // bins rows i, columns j
+        for (int q = 0; q < BKC * 32 / 256; ++q) {                  // bins rows i, columns j (clamped loads)
             const int e = tid + 256 * q, i = e / 32, j = e % 32;
-            vt[q] = (i0 + i < nA && j0 + j < nB) ? bins[(i0 + i) * nB + j0 + j] : (uint8_t)0;
+            const bool in = i0 + i < nA && j0 + j < nB;
+            const uint8_t b = bins[min(i0 + i, nA - 1) * nB + min(j0 + j, nB - 1)];
+            vt[q] = in ? b : (uint8_t)0;
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 32 * (BKC / 8) / 256; ++q) {
+        for (int q = 0; q < 32 * (BKC / 8) / 256; ++q) {            // counts <= 256: exact in bf16
             const int e = tid + 256 * q, row = e / (BKC / 8), ch = e % (BKC / 8);
-            *(bf16x8_t *)&sA[row][8 * ch] = va[q];
+            const int4 u = va[2 * q], w = va[2 * q + 1];
+            bf16x8_t b;
+            b[0] = (__bf16)(float)u.x;
+            b[1] = (__bf16)(float)u.y;
+            b[2] = (__bf16)(float)u.z;
+            b[3] = (__bf16)(float)u.w;
+            b[4] = (__bf16)(float)w.x;
+            b[5] = (__bf16)(float)w.y;
+            b[6] = (__bf16)(float)w.z;
+            b[7] = (__bf16)(float)w.w;
+            *(bf16x8_t *)&sA[row][8 * ch] = b;
         }
 #pragma unroll
         for (int q = 0; q < BKC * 32 / 256; ++q) {                  // -> sT[j][i]
@@ -235,19 +254,33 @@ __global__ __launch_bounds__(256) void k_boot_mfma(const uint8_t *bins, long lon
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const long long r = r0 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
-        wb[e] = (r < n_boot && j < nB) ? WB[r * nB + j] : 0;
+        const int w = WB[min(r, (long long)n_boot - 1) * nB + min(j, nB - 1)];     // clamped: all loads in flight
+        wb[e] = (r < n_boot && j < nB) ? w : 0;
     }
+    // Row sums over the 32 columns of each half go through this wavefront's
+    // slice of LDS: per threshold every lane stores its 16 weighted counts,
+    // then lane k < 32 adds the 32 values of (element k / 2, half k % 2) and
+    // issues one atomic.  Only this wavefront touches its slice, and a
+    // wavefront's LDS accesses are performed in issue order, so a wavefront
+    // barrier (no code motion across it) is the only ordering needed.
 #pragma unroll
     for (int q = 0; q < BTPW; ++q) {
         const int t = wv * BTPW + q + 1;
         if (t > M) break;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            int v = (int)c[q][e] * wb[e];
+        for (int e = 0; e < 16; ++e) sred[wv][e][lane] = (int)c[q][e] * wb[e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < 32) {
+            const int e = lane >> 1, hf = lane & 1;
+            const int *row = &sred[wv][e][32 * hf];
+            int v = 0;
 #pragma unroll
-            for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);   // over the 32 columns of this half
-            const long long r = r0 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
-            if ((lane & 31) == 0 && r < n_boot && v) atomicAdd(&acc[r * M + (t - 1)], (unsigned long long)v);
+            for (int k = 0; k < 32; ++k) v += row[k];
+            const long long r = r0 + 8 * (e / 4) + 4 * hf + (e % 4);
+            if (r < n_boot && v) atomicAdd(&acc[r * M + (t - 1)], (unsigned long long)v);
         }
     }
 }
@@ -270,48 +303,27 @@ struct BootMem {
     }
 };
 
-size_t boot_mult_bytes(long long nA, long long nB, int n_boot)
-{
-    const long long nbP = (n_boot + 31) / 32 * 32, ldA = (nA + BKC - 1) / BKC * BKC;
-    return sizeof(int) * (size_t)(nbP * ldA) + sizeof(int) * (size_t)n_boot * nB + sizeof(__bf16) * (size_t)(nbP * ldA) +
-           64;
-}
+// One device region per call: the resample counters acc[n_boot M], four
+// flag words (gather-path index error, index error, count above 256, pad)
+// and, for the matrix-core path, the multiplicities cA[nbP][ldA] and
+// cB[n_boot][nB]; cleared by one kernel.
+struct BootLayout {
+    long long n, nbP, ldA;
+    size_t off_flags, off_cA, off_cB, clear, total;
+};
 
-// MFMA path.  It runs unless an index is out of range (flags[0]) or a
-// multiplicity exceeds 256 (flags[1], possible only for kA > 256): both are
-// known on the device only, so the kernel checks them itself; *flags_out
-// points at them for a gather launch that runs only when the MFMA kernel
-// declined (*may_decline).
-int bootstrap_mfma(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA, const int *idxB,
-                   int kB, int n_boot, unsigned long long *acc, hipStream_t st, const int **flags_out,
-                   bool *may_decline, BootMem &mem)
+static BootLayout boot_layout(long long nA, long long nB, int M, int n_boot, bool mfma)
 {
-    const long long nbP = (n_boot + 31) / 32 * 32, ldA = (nA + BKC - 1) / BKC * BKC;
-    const size_t szA = sizeof(int) * (size_t)(nbP * ldA), szB = sizeof(int) * (size_t)n_boot * nB;
-    const size_t szW = sizeof(__bf16) * (size_t)(nbP * ldA);
-    void *p;
-    CIL_TRY(mem.get(WS_BOOT_MULT, boot_mult_bytes(nA, nB, n_boot), &p));
-    int *cA = (int *)p;
-    int *cB = cA + nbP * ldA;
-    __bf16 *wA = (__bf16 *)(cB + (size_t)n_boot * nB);
-    int *flags = (int *)((char *)wA + szW);          // bad, over
-    CIL_TRY(fill_zero(cA, szA + szB, st));
-    CIL_TRY(fill_zero(flags, 2 * sizeof(int), st));
-    hipLaunchKernelGGL(k_multiplicity, dim3((unsigned)(((long long)n_boot * kA + 255) / 256)), dim3(256), 0, st, idxA,
-                       kA, n_boot, nA, (int)ldA, cA, flags);
-    hipLaunchKernelGGL(k_multiplicity, dim3((unsigned)(((long long)n_boot * kB + 255) / 256)), dim3(256), 0, st, idxB,
-                       kB, n_boot, nB, (int)nB, cB, flags);
-    hipLaunchKernelGGL(k_mult_to_bf16, dim3((unsigned)((nbP * ldA + 255) / 256)), dim3(256), 0, st, cA, nbP * ldA, wA,
-                       flags + 1);
-    CIL_TRY(check_launch("k_multiplicity"));
-    dim3 grid((unsigned)((nB + 31) / 32), (unsigned)(nbP / 32));
-    const ProfMark pm = mem.mark("k_bootstrap", st);
-    hipLaunchKernelGGL(k_boot_mfma, grid, dim3(256), 0, st, bins, nA, nB, M, wA, ldA, cB, n_boot, acc, flags);
-    prof_end(pm, st);
-    CIL_TRY(check_launch("k_boot_mfma"));
-    *flags_out = flags;
-    *may_decline = kA > 256;
-    return CIL_OK;
+    BootLayout L;
+    L.n = (long long)n_boot * M;
+    L.nbP = (n_boot + 31) / 32 * 32;
+    L.ldA = (nA + BKC - 1) / BKC * BKC;
+    L.off_flags = sizeof(unsigned long long) * (size_t)L.n;
+    L.off_cA = (L.off_flags + 4 * sizeof(int) + 15) & ~(size_t)15;     // 16-byte rows for the staging loads
+    L.off_cB = L.off_cA + (mfma ? sizeof(int) * (size_t)(L.nbP * L.ldA) : 0);
+    L.total = L.off_cB + (mfma ? sizeof(int) * (size_t)n_boot * nB : 0);
+    L.clear = L.total;
+    return L;
 }
 
 static bool boot_uses_mfma(int M) { return M <= 4 * BTPW && g_boot_mfma; }
@@ -320,23 +332,36 @@ static int bootstrap_run(const uint8_t *bins, long long nA, long long nB, int M,
                          const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st,
                          BootMem &mem)
 {
-    void *p;
-    const long long n = (long long)n_boot * M;
-    CIL_TRY(mem.get(WS_BOOT_MISC, sizeof(unsigned long long) * (size_t)(n + 1), &p));
-    unsigned long long *acc = (unsigned long long *)p;
-    int *bad = (int *)(acc + n);
-    CIL_TRY(fill_zero(acc, sizeof(unsigned long long) * (size_t)(n + 1), st));
     const bool work = n_boot > 0 && kA > 0 && kB > 0;
-    bool mfma = false, may_decline = false;
-    const int *mflags = nullptr;
-    if (work && boot_uses_mfma(M)) {
-        CIL_TRY(bootstrap_mfma(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, acc, st, &mflags, &may_decline, mem));
-        mfma = true;
+    const bool mfma = work && boot_uses_mfma(M);
+    const BootLayout L = boot_layout(nA, nB, M, n_boot, mfma);
+    void *p;
+    CIL_TRY(mem.get(WS_BOOT_MISC, L.total, &p));
+    char *base = (char *)p;
+    unsigned long long *acc = (unsigned long long *)base;
+    int *flags = (int *)(base + L.off_flags);
+    CIL_TRY(fill_zero(base, L.clear, st));
+    if (mfma) {
+        // the matrix-core path runs unless an index is out of range
+        // (flags[1]) or a multiplicity exceeds 256 (flags[2], possible only
+        // for kA > 256): the kernel checks both itself, and a gather launch
+        // follows that runs only if it declined
+        int *cA = (int *)(base + L.off_cA), *cB = (int *)(base + L.off_cB);
+        const long long tot = (long long)n_boot * (kA + kB);
+        hipLaunchKernelGGL(k_multiplicity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, idxA, kA, nA,
+                           (int)L.ldA, cA, idxB, kB, nB, cB, n_boot, flags + 1);
+        CIL_TRY(check_launch("k_multiplicity"));
+        dim3 grid((unsigned)((nB + 31) / 32), (unsigned)(L.nbP / 32));
+        const ProfMark pm = mem.mark("k_bootstrap", st);
+        hipLaunchKernelGGL(k_boot_mfma, grid, dim3(256), 0, st, bins, nA, nB, M, cA, L.ldA, cB, n_boot, acc,
+                           flags + 1);
+        prof_end(pm, st);
+        CIL_TRY(check_launch("k_boot_mfma"));
     }
-    if (work && (!mfma || may_decline)) {
-        // gather path (after the MFMA kernel: only if that declined); the kA
-        // rows of a resample are split over enough blocks to fill the chip
-        const int *only_if = mfma ? mflags : nullptr;
+    if (work && (!mfma || kA > 256)) {
+        // gather path (after the matrix-core kernel: only if that declined);
+        // the kA rows of a resample are split over enough blocks to fill the chip
+        const int *only_if = mfma ? flags + 1 : nullptr;
         int slices = (int)std::max<long long>(1, std::min<long long>(kA, (2048 + n_boot - 1) / n_boot));
         const int rpb = (kA + slices - 1) / slices;
         slices = (kA + rpb - 1) / rpb;
@@ -346,27 +371,32 @@ static int bootstrap_run(const uint8_t *bins, long long nA, long long nB, int M,
         const ProfMark pm = mem.mark("k_bootstrap", st);
         if (M <= 16)
             hipLaunchKernelGGL(k_bootstrap<16>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc,
-                               bad, only_if);
+                               flags, only_if);
         else if (M <= 32)
             hipLaunchKernelGGL(k_bootstrap<32>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc,
-                               bad, only_if);
+                               flags, only_if);
         else if (M <= 64)
             hipLaunchKernelGGL(k_bootstrap<64>, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb, acc,
-                               bad, only_if);
+                               flags, only_if);
         else
             hipLaunchKernelGGL(k_bootstrap_hist, grid, dim3(256), shmem, st, bins, nA, nB, M, idxA, kA, idxB, kB, rpb,
-                               acc, bad, only_if);
+                               acc, flags, only_if);
         prof_end(pm, st);
         CIL_TRY(check_launch("k_bootstrap"));
     }
     const double denom = (double)kA * (double)kB;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_boot_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, n, denom, Ycount, Y);
+    if (L.n > 0) {
+        hipLaunchKernelGGL(k_boot_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, acc, L.n, denom, Ycount,
+                           Y);
         CIL_TRY(check_launch("k_boot_finish"));
     }
-    int hbad[2] = {0, 0};
-    CIL_HIP(hipMemcpyAsync(&hbad[0], bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (mflags) CIL_HIP(hipMemcpyAsync(&hbad[1], mflags, sizeof(int), hipMemcpyDeviceToHost, st));
+    // pinned host words keep the copy asynchronous; the allocation-free path
+    // reads into the stack instead (pinned memory would be allocated)
+    int hloc[2];
+    int *hbad = hloc;
+    if (!mem.base) CIL_TRY(host_stage(HS_BOOT, 2 * sizeof(int), (void **)&hbad));
+    hbad[0] = hbad[1] = 0;
+    CIL_HIP(hipMemcpyAsync(hbad, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipStreamSynchronize(st));
     if (hbad[0] || hbad[1]) return set_error(CIL_EINVAL, "bootstrap index out of range");
     return CIL_OK;
@@ -410,10 +440,7 @@ static int scratch_address(char **out)
 
 size_t bootstrap_noalloc_bytes(long long nA, long long nB, int M, int n_boot)
 {
-    const size_t acc = sizeof(unsigned long long) * (size_t)((long long)n_boot * M + 1);
-    size_t total = acc;
-    if (boot_uses_mfma(M)) total = ((total + 255) & ~(size_t)255) + boot_mult_bytes(nA, nB, n_boot);
-    return total;
+    return boot_layout(nA, nB, M, n_boot, boot_uses_mfma(M)).total;
 }
 
 int bootstrap_noalloc_impl(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
@@ -451,6 +478,7 @@ __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, c
     __shared__ int keep[LMAX];
     __shared__ int nk;
     __shared__ double z[LMAX];
+    __shared__ double lgd[LMAX];
     const int p = blockIdx.x;
     const int lane = threadIdx.x;
     const double *Yp = Y + (size_t)p * n * M;
@@ -462,10 +490,26 @@ __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, c
     for (int r0 = 0; r0 < n; r0 += RC) {
         const int cnt = min(RC, n - r0) * M;
         __syncthreads();
-        for (int q = lane; q < cnt; q += 256) Ys[q] = Yp[(size_t)r0 * M + q];
+        for (int q0 = lane; q0 < cnt; q0 += 256 * 8) {     // eight unconditional loads in flight per thread
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = Yp[(size_t)r0 * M + min(q0 + 256 * u, cnt - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + 256 * u < cnt) Ys[q0 + 256 * u] = v[u];
+        }
         __syncthreads();
-        if (lane < M)
-            for (int q = lane; q < cnt; q += M) s += Ys[q];
+        if (lane < M) {
+            int q = lane;
+            for (; q + 7 * M < cnt; q += 8 * M) {       // eight loads in flight, added in row order
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = Ys[q + u * M];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
+            }
+            for (; q < cnt; q += M) s += Ys[q];
+        }
     }
     if (lane < M) mu[lane] = s / n;
     __syncthreads();
@@ -493,14 +537,32 @@ __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, c
             for (int q = lane; q < rows * M; q += 256) Ys[q] -= mu[q % M];
         } else {
             __syncthreads();
-            for (int q = lane; q < rows * M; q += 256) Ys[q] = Yp[(size_t)r0 * M + q] - mu[q % M];
+            for (int q0 = lane; q0 < rows * M; q0 += 256 * 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = Yp[(size_t)r0 * M + min(q0 + 256 * u, rows * M - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (q0 + 256 * u < rows * M) Ys[q0 + 256 * u] = v[u] - mu[(q0 + 256 * u) % M];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < NE; ++t)
             if (lane + 256 * t < ne) {
                 const double *a = Ys + ei[t], *b = Ys + ej[t];
-                for (int r = 0; r < rows; ++r) acc[t] += a[r * M] * b[r * M];
+                int r = 0;
+                for (; r + 8 <= rows; r += 8) {             // eight row pairs in flight, added in row order
+                    double x[8], y[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        x[u] = a[(r + u) * M];
+                        y[u] = b[(r + u) * M];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[t] += x[u] * y[u];
+                }
+                for (; r < rows; ++r) acc[t] += a[r * M] * b[r * M];
             }
     }
 #pragma unroll
@@ -511,53 +573,72 @@ __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, c
             S[ej[t]][ei[t]] = sv;
         }
     __syncthreads();
+    // From here one wavefront works alone: its LDS accesses are performed in
+    // issue order, so a wavefront barrier (no code motion across it) orders
+    // them; the other wavefronts leave.
+    if (lane >= 64) return;
+    auto wsync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     if (lane == 0) {
         int c = 0;
         for (int m = 0; m < M; ++m)
             if (S[m][m] != 0.0) keep[c++] = m;
         nk = c;
     }
-    __syncthreads();
+    wsync();
     const int K = nk;
     // compact the kept rows/columns into the leading K x K block (in place:
-    // keep[] is increasing so keep[a] >= a)
+    // keep[] is increasing so keep[a] >= a); lane c moves column c
     for (int a = 0; a < K; ++a) {
         double v = 0.0;
         if (lane < K) v = S[keep[a]][keep[lane]];
-        __syncthreads();
+        wsync();
         if (lane < K) S[a][lane] = v;
-        __syncthreads();
+        wsync();
     }
     // Cholesky, lower triangle in S; a pivot not above K 2^-52 Sigma_jj means
-    // Sigma is singular to working precision
+    // Sigma is singular to working precision.  The dot products subtract
+    // their terms in index order; the loads run four ahead.
+    auto dot_sub = [](double s, const double *x, const double *y, int len) {
+        int k = 0;
+        for (; k + 4 <= len; k += 4) {
+            const double x0 = x[k], x1 = x[k + 1], x2 = x[k + 2], x3 = x[k + 3];
+            const double y0 = y[k], y1 = y[k + 1], y2 = y[k + 2], y3 = y[k + 3];
+            s -= x0 * y0;
+            s -= x1 * y1;
+            s -= x2 * y2;
+            s -= x3 * y3;
+        }
+        for (; k < len; ++k) s -= x[k] * y[k];
+        return s;
+    };
     int ok = 1;
     for (int j = 0; j < K; ++j) {
         if (lane == 0) {
             const double diag = S[j][j];
-            double s = diag;
-            for (int k = 0; k < j; ++k) s -= S[j][k] * S[j][k];
-            S[j][j] = (s > K * 0x1p-52 * diag) ? sqrt(s) : NAN;
+            const double sv = dot_sub(diag, S[j], S[j], j);
+            S[j][j] = (sv > K * 0x1p-52 * diag) ? sqrt(sv) : NAN;
         }
-        __syncthreads();
+        wsync();
         const double d = S[j][j];
         if (!(d > 0.0)) ok = 0;
-        if (lane > j && lane < K) {
-            double s = S[lane][j];
-            for (int k = 0; k < j; ++k) s -= S[lane][k] * S[j][k];
-            S[lane][j] = s / d;
-        }
-        __syncthreads();
+        if (lane > j && lane < K) S[lane][j] = dot_sub(S[lane][j], S[lane], S[j], j) / d;
+        wsync();
     }
+    if (lane < K) lgd[lane] = ok ? log(S[lane][lane]) : 0.0;   // the logs in parallel, summed in order below
+    wsync();
     if (lane == 0) {
         double ff = NAN, ll = NAN;
         if (ok) {
             double acc = 0.0, ld = 0.0;
             for (int i = 0; i < K; ++i) {
-                double s = yobs[(size_t)p * M + keep[i]] - mu[keep[i]];
-                for (int k = 0; k < i; ++k) s -= S[i][k] * z[k];
-                z[i] = s / S[i][i];
+                const double sv = dot_sub(yobs[(size_t)p * M + keep[i]] - mu[keep[i]], S[i], z, i);
+                z[i] = sv / S[i][i];
                 acc += z[i] * z[i];
-                ld += log(S[i][i]);
+                ld += lgd[i];
             }
             ff = acc;
             ll = -0.5 * acc - ld - 0.5 * K * log(2.0 * M_PI);
