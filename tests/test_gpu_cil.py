@@ -254,6 +254,47 @@ def test_adaptive_bins_bit_exact(cil, oracle_mod, dtype, law):
     assert np.array_equal(counts, oracle_mod.counts_from_d2(D, want_r))
 
 
+def duplicated_sets(dtype, d=515):
+    """Integer sets whose 59 x 59 cross pairs of copies (a against b) all lie
+    at the largest distance; row 0 of each set lies near the origin, so its
+    pairs are shorter.  More than 2048 pairs then sit at the top of the range,
+    or on a radius placed there."""
+    g = np.random.default_rng(21)
+    a = g.integers(4, 8, size=d)
+    b = -g.integers(4, 8, size=d)
+    A = np.tile(a, (60, 1)).astype(dtype)
+    B = np.tile(b, (60, 1)).astype(dtype)
+    A[0] = g.integers(-2, 2, size=d)
+    B[0] = g.integers(-2, 2, size=d)
+    return A, B
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_range_and_bins_with_long_recheck_lists(cil, oracle_mod, dtype):
+    """Re-check lists longer than the first canonical launch covers (3481
+    range candidates, 3481 pairs on a radius) finish in the second launch:
+    range, radii, bins and counts stay those of the oracle (eqs. eCDF, CIL,
+    Sec. 2.1)."""
+    A, B = duplicated_sets(dtype)
+    D = oracle_mod.pair_d2(A, B)
+    assert (D == D.max()).sum() == 59 * 59
+    got = cil.cil_distance_range(dev(A), dev(B))
+    assert got == (D.min(), D.max())
+    assert cil.cil_last_distance_stats()["rechecked"] >= 59 * 59
+    radii = np.array([math.sqrt(D.max()), math.sqrt(D.max()) * 0.5, math.sqrt(D.min()) * 0.999])
+    bins, counts = cil.cil_pair_bins(dev(A), dev(B), radii)
+    assert np.array_equal(bins.cpu().numpy(), oracle_mod.bins_from_d2(D, radii))
+    assert np.array_equal(counts, oracle_mod.counts_from_d2(D, radii))
+    assert cil.cil_last_distance_stats()["rechecked"] >= 59 * 59
+    M = 12
+    lo, hi, r2, bins2, counts2 = cil.cil_pair_bins_adaptive(dev(A), dev(B), M)
+    assert (lo, hi) == (D.min(), D.max())
+    want_r = oracle_mod.radii_ladder(D.min(), D.max(), M)
+    assert np.array_equal(r2, want_r)
+    assert np.array_equal(bins2.cpu().numpy(), oracle_mod.bins_from_d2(D, want_r))
+    assert np.array_equal(counts2, oracle_mod.counts_from_d2(D, want_r))
+
+
 def test_adaptive_bins_rejects_a_degenerate_range(cil):
     A = np.ones((3, 8), dtype=np.float64)
     with pytest.raises(cil.CilError) as e:
