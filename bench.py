@@ -132,6 +132,9 @@ def parse():
                     help="bz_uneven2048: steps per autotuning trial (0 = the plan's own stepping)")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the stepper sources (recorded beside the HBM counters) and exit")
+    ap.add_argument("--polish", type=int, default=2, choices=[1, 2],
+                    help="continuation of each solve from its FP32 floor to the tolerance: 1 = FP64 steps, "
+                         "2 = the refinement form (FP64 state, FP32 correction steps)")
     ap.add_argument("--polish-separate", action="store_true",
                     help="run the FP64 polish as a second launch over the promoted solves (CIL_OPT_POLISH_SEPARATE), "
                          "so that counters separate the FP32 and FP64 phases")
@@ -218,7 +221,7 @@ def main():
         """Whole hot path; stat_fp32: statistic on FP32 patterns (split-bf16x3 Gram)."""
         state.copy_(ics)
         rep = cil.cil_simulate_patterns(w["model"], state, probs, w["dt"], w["max_steps"], tol=w["tol"],
-                                        check_every=w["check_every"], path=path, polish=1)
+                                        check_every=w["check_every"], path=path, polish=args.polish)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -294,8 +297,11 @@ def main():
     if kname and kname.startswith("k_fused"):
         cnt, tot_ms = prof[kname]
         per = fused_step_flops(n, REACTION_FLOPS[w["model"]])
-        f32_flops = (solve_steps - fp64_steps) * per
-        f64_flops = fp64_steps * per
+        # the refinement form's polish steps transform in FP32 (its FP64 work,
+        # the residual at each re-basing, is not counted as algorithmic)
+        f64_steps = fp64_steps if args.polish == 1 else 0
+        f32_flops = (solve_steps - f64_steps) * per
+        f64_flops = f64_steps * per
         avg_ms = tot_ms / cnt
         achieved = (f32_flops + f64_flops) / cnt / (avg_ms * 1e-3) / 1e12
         # the vector ALU peak for this mix of FP32 and FP64 steps: the time the
@@ -304,7 +310,8 @@ def main():
         roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname),
                 "launches": cnt, "avg_launch_ms": round(avg_ms, 4), "flops_per_solve_step": per,
-                "solve_steps": solve_steps, "fp64_solve_steps": fp64_steps,
+                "solve_steps": solve_steps, "polish_solve_steps": fp64_steps,
+                "polish": "FP64 steps" if args.polish == 1 else "refinement form (FP64 state, FP32 correction steps)",
                 "peak_note": "weighted by the FP32 (157.3) and FP64 (78.6 TFLOP/s) steps of the launch"}
     gram = None
     gk = "k_gram_dma" if "k_gram_dma" in prof_stat else "k_gram_bf16x3"
@@ -356,7 +363,7 @@ def main():
                    "statistic": "fp32 patterns, split-bf16x3 MFMA Gram + canonical re-check",
                    "parallelism": "none (1 GPU)"},
         "pairs_per_s": round(pairs_per_s, 1) if pairs_per_s else None,
-        "solve_steps": solve_steps // K, "fp64_solve_steps": fp64_steps // K,
+        "solve_steps": solve_steps // K, "polish_solve_steps": fp64_steps // K,
         "max_solve_steps": int(rep["steps_taken"].max()), "all_converged": status_ok,
         "roofline": roof, "roofline_gram": gram, "kernels": kernels,
         "statistic_kernels": {"what": "average launch times from 2 further profiled steps", "kernels": kernels_stat},
@@ -983,7 +990,8 @@ def lone_main(args):
     """One Gierer-Meinhardt (source form) 64x64 solve alone on the GPU, 2000
     fixed steps in FP32 and in FP64 on the fused stepper: the per-step latency
     that bounds the stationarity batch's tail (its slowest solve ends up alone
-    on its CU).  `value` is the FP32 steps per second of the lone solve."""
+    on its CU); then the batch's slowest solve alone to the tolerance, with
+    each polish.  `value` is the FP32 steps per second of the lone solve."""
     import numpy as np
     import torch
 
@@ -1011,6 +1019,41 @@ def lone_main(args):
             el = time.perf_counter() - t0
             best = el if best is None else min(best, el)
         out[name] = {"us_per_step": round(1e6 * best / steps, 3)}
+
+    # the stationarity batch's slowest solve alone, to the tolerance: FP32 to
+    # its floor (polish 0), then with each polish; the difference over the
+    # polish steps is the polish step's latency
+    ics_all = cs.initial_conditions(base, n, w["count"], seed=w["seeds"][0], law=w["ic_law"])
+    probs_all = cil.make_problems(n, w["L"], w["nu"], w["params"], count=w["count"])
+    st_all = torch.tensor(ics_all, dtype=torch.float32, device=dev)
+    rep = cil.cil_simulate_patterns(w["model"], st_all, probs_all, w["dt"], w["max_steps"], tol=w["tol"],
+                                    check_every=w["check_every"], polish=2)
+    k = int(np.argmax(rep["steps_taken"]))
+    ics_k = torch.tensor(ics_all[k:k + 1], dtype=torch.float32, device=dev)
+    st = torch.empty_like(ics_k)
+    slow = {"solve": k, "batch_steps_max": int(rep["steps_taken"][k])}
+    # (separate: the polish as a launch of its own after the FP32 kernel, so
+    # that the FP32 phase runs in the FP32 kernel in every case)
+    for polish, sep in ((0, 0), (1, 0), (2, 0), (1, 1), (2, 1)):
+        best, r = None, None
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
+        for _ in range(max(1, args.warmup) + max(1, args.steps)):
+            st.copy_(ics_k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                          check_every=w["check_every"], polish=polish)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 0)
+        slow["polish%d%s" % (polish, "_separate" if sep else "")] = {
+            "ms": round(1e3 * best, 3), "steps": int(r["steps_taken"][0]), "polish_steps": int(r["steps_fp64"][0]),
+            "status": int(r["status"][0])}
+    t0 = slow["polish0"]["ms"]
+    for key, e in slow.items():
+        if isinstance(e, dict) and e["polish_steps"] > 0:
+            e["us_per_polish_step"] = round(1e3 * (e["ms"] - t0) / e["polish_steps"], 3)
     line = {
         "metric": "stationary patterns/s + CIL distance pairs/s, batched FP32 vs plain FP64",
         "value": round(1e6 / out["fp32"]["us_per_step"], 1), "unit": "solve-steps/s (one solve alone)",
@@ -1018,7 +1061,7 @@ def lone_main(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "gm_source64_lone", "solves": 1, "grid": n, "fixed_steps": steps,
                    "parallelism": "none (1 GPU)"},
-        "lone_step": out, "roofline": None, "cpu_baseline": None,
+        "lone_step": out, "slowest_solve_alone": slow, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -99,18 +99,28 @@ typedef enum {
  * FP64) is < tol, or at max_steps.  FP32 only: when the residual falls below
  * the FP32 floor fp32_floor_ulps * 2^-24 * max|u| / dt (the state can no
  * longer resolve the residual) and tol is below that floor, polish != 0
- * promotes the solve to FP64 stepping on the GPU until tol is met (the result
- * is rounded back to FP32; on the fused quad-lane path at n = 32 and 64 the
- * switch happens inside the same persistent launch, see
- * CIL_OPT_POLISH_SEPARATE); polish == 0 stops it there with status
- * CIL_SOLVE_FP32_FLOOR. */
+ * continues the solve on the GPU until tol is met, the result rounded back to
+ * FP32 (on the fused quad-lane path at n = 32 and 64 inside the same
+ * persistent launch, see CIL_OPT_POLISH_SEPARATE):
+ *   CIL_POLISH_FP64 (1): FP64 steps;
+ *   CIL_POLISH_REFINE (2): the same steps in the refinement form u = U + v,
+ *     U held in FP64, the correction v stepped with the FP32 transforms
+ *     against the FP64 residual of U (five-point stencil) and the exact
+ *     change of the reaction terms, so FP32 rounding scales with the size of
+ *     v and the iteration has no FP32 floor; U absorbs v every 200 steps or
+ *     so.  On the fused quad-lane path at n = 32 and 64 (default shapes);
+ *     elsewhere as CIL_POLISH_FP64.  The stop rule and its FP64 residual are
+ *     those above.
+ * polish == 0 stops the solve at its floor with status CIL_SOLVE_FP32_FLOOR.
+ * Other values: CIL_EINVAL. */
+typedef enum { CIL_POLISH_OFF = 0, CIL_POLISH_FP64 = 1, CIL_POLISH_REFINE = 2 } cil_polish;
 typedef struct {
     double dt;
     int64_t max_steps;
     double tol;
     int32_t check_every;      /* >= 1 */
     int32_t path;             /* cil_path */
-    int32_t polish;           /* FP32 only, see above */
+    int32_t polish;           /* cil_polish, FP32 only, see above */
     int32_t fp32_floor_ulps;  /* <= 0 selects the default 8 */
 } cil_stepping;
 
@@ -123,7 +133,7 @@ typedef enum {
 
 typedef struct {
     int64_t steps_taken;   /* steps applied to this solve                     */
-    int64_t steps_fp64;    /* of which in FP64 polish (FP32 calls)            */
+    int64_t steps_fp64;    /* of which in the polish (FP32 calls)             */
     double final_resid;    /* residual of the last evaluated step (NaN if non-finite) */
     int32_t status;        /* cil_solve_status                                */
     int32_t reserved;
@@ -414,11 +424,11 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   which set the batch's time, win the SIMDs they share.  0 = off.  Results
  *   are unchanged (priority changes timing only).  CIL_EINVAL for 1 or
  *   values outside the range.
- * CIL_OPT_POLISH_SEPARATE (value 0/1): FP32 solves with polish = 1 on the
- *   fused quad-lane path at n = 32 or 64 (default shapes) switch to FP64 at
- *   their FP32 floor inside the same persistent launch (0, default); 1 = the
- *   FP64 polish runs as a launch of its own after the whole FP32 phase.  Both
- *   give identical results. */
+ * CIL_OPT_POLISH_SEPARATE (value 0/1): FP32 solves with polish != 0 on the
+ *   fused quad-lane path at n = 32 or 64 (default shapes) continue from their
+ *   FP32 floor inside the same persistent launch (0, default); 1 = the polish
+ *   runs as a launch of its own after the whole FP32 phase.  Both give
+ *   identical results. */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
        CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6, CIL_OPT_POLISH_SEPARATE = 7 };
 int cil_set_option(int32_t option, int64_t value);

@@ -23,6 +23,7 @@ CIL_FHN, CIL_GM, CIL_GM_SOURCE, CIL_BRUSSELATOR, CIL_HEAT = 0, 1, 2, 3, 4
 CIL_FP64, CIL_FP32 = 0, 1
 CIL_PATH_AUTO, CIL_PATH_PLAIN, CIL_PATH_FUSED, CIL_PATH_FUSED_LINE, CIL_PATH_FUSED_QUAD = 0, 1, 2, 3, 4
 CIL_SOLVE_OK, CIL_SOLVE_NONFINITE, CIL_SOLVE_MAXSTEPS, CIL_SOLVE_FP32_FLOOR = 0, 1, 2, 3
+CIL_POLISH_OFF, CIL_POLISH_FP64, CIL_POLISH_REFINE = 0, 1, 2
 CIL_OPT_FORCE_EXACT_SUM = 1
 CIL_OPT_QUAD_SHAPE = 2
 CIL_OPT_BOOTSTRAP_GATHER = 3

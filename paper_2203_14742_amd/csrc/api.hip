@@ -358,6 +358,7 @@ static int simulate_checked(cil_model model, cil_precision prec, const cil_probl
     if (stepping->check_every < 1) return set_error(CIL_EINVAL, "check_every < 1");
     if (stepping->path < CIL_PATH_AUTO || stepping->path > CIL_PATH_FUSED_QUAD)
         return set_error(CIL_EINVAL, "unknown path");
+    if (stepping->polish < 0 || stepping->polish > 2) return set_error(CIL_EINVAL, "polish must be 0, 1 or 2");
     for (int b = 0; b < B; ++b) {
         const cil_problem &p = probs[b];
         if (p.n < 2 || p.n > 4096) return set_error(CIL_EINVAL, "solve %d: n = %d out of range [2, 4096]", b, p.n);
@@ -411,6 +412,7 @@ int cil_sim_plan_create(cil_model model, cil_precision prec, const cil_problem *
     if (stepping->check_every < 1) return set_error(CIL_EINVAL, "check_every < 1");
     if (stepping->path < CIL_PATH_AUTO || stepping->path > CIL_PATH_FUSED_QUAD)
         return set_error(CIL_EINVAL, "unknown path");
+    if (stepping->polish < 0 || stepping->polish > 2) return set_error(CIL_EINVAL, "polish must be 0, 1 or 2");
     for (int b = 0; b < B; ++b) {
         const cil_problem &p = probs[b];
         if (p.n < 2 || p.n > 4096) return set_error(CIL_EINVAL, "solve %d: n = %d out of range [2, 4096]", b, p.n);

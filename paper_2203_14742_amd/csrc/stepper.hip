@@ -822,14 +822,16 @@ struct SimCtx {
     std::vector<double> fres;
     std::vector<int> status;
     std::vector<int64_t> sw;      // mixed launches: step of the FP32 -> FP64 switch (-1: not a mixed solve)
+    int polish = 0;               // 0 none, 1 FP64 steps, 2 refinement form (FP32 calls)
     int scheme = 0;               // 0 IMEX Euler, 1 second-order IMEX (plain back-end)
     void *uh = nullptr, *fh = nullptr;   // second-order history, state layout
 };
 
 // FP32 -> FP64 within one launch (k_fused_q_mixed) for these grid sides.
 struct MixedArgs {
-    double *state64;              // FP64 snapshots, same element layout as the FP32 state
+    double *state64;              // FP64 snapshots or FP64 state, same element layout as the FP32 state
     long long *sw;                // per solve: switch step
+    int refine;                   // 1: the continuation is the refinement form, else FP64 steps
 };
 
 bool mixed_supported(int n, bool quad)
@@ -882,14 +884,17 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
 {
     if (byn.empty()) return CIL_OK;
     std::vector<void *> tabs, tabs64;
+    std::vector<char> mixed;
     for (auto &kv : byn) {
         void *t, *t64 = nullptr;
         CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &t,
                                quad && kQuadShape[quad_shape(std::is_same<T, float>::value, kv.first)].vform));
-        if (mx && mixed_supported(kv.first, quad))
+        const bool mix = mx && mixed_supported(kv.first, quad);
+        if (mix && !mx->refine)
             CIL_TRY(make_tables<double>(c, kv.first, kv.second, hs, &t64, kQuadShape[quad_shape(false, kv.first)].vform));
         tabs.push_back(t);
         tabs64.push_back(t64);
+        mixed.push_back(mix);
     }
     const int B = (int)hs.size();
     CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
@@ -933,13 +938,13 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
         }
         const int shape = quad_shape(std::is_same<T, float>::value, kv.first);
         if constexpr (std::is_same<T, float>::value) {
-            if (tabs64[gi]) {
+            if (mixed[gi]) {
                 PersistArgs pa64 = pa;
                 pa64.floor_coef = 0.0;
                 const ProfMark pm = prof_begin(kv.first == 32 ? "k_fused_q_mixed_n32" : "k_fused_q_mixed_n64", gst);
                 const int rc = launch_quad_mixed(kv.first, (int)kv.second.size(), dS, dls[gi], state, mx->state64,
                                                  (const float *)tabs[gi], (const double *)tabs64[gi], c.model, c.dt,
-                                                 pa, pa64, mx->sw, gst);
+                                                 pa, pa64, mx->sw, mx->refine, gst);
                 prof_end(pm, gst);
                 if (rc) return set_error(rc, "no mixed-precision kernel for n = %d", kv.first);
                 CIL_TRY(check_launch("k_fused_q_mixed"));
@@ -973,7 +978,53 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
             c.steps[b] = hsteps[b];
             c.fres[b] = hres[b];
             c.status[b] = hstat[b];
-            if (mx && tabs64[gi]) c.sw[b] = hsw[b];
+            if (mixed[gi]) c.sw[b] = hsw[b];
+        }
+    return CIL_OK;
+}
+
+// The refinement form as a launch of its own over FP32 solves stopped at
+// their floor (quad-lane, n = 32 and 64, default shapes): the separate-launch
+// counterpart of the mixed launch's continuation.  u64: FP64 state, same
+// element layout as `state`.
+int run_refine(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<DevSolve> &hs, DevSolve *dS,
+               float *state, double *u64, long long *dsteps, double *dres, int *dstat)
+{
+    if (byn.empty()) return CIL_OK;
+    const int B = (int)hs.size();
+    std::vector<void *> tabs;
+    for (auto &kv : byn) {
+        void *t;
+        CIL_TRY(make_tables<float>(c, kv.first, kv.second, hs, &t, kQuadShape[quad_shape(true, kv.first)].vform));
+        tabs.push_back(t);
+    }
+    CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
+    std::vector<long long> hsteps(c.steps.begin(), c.steps.end());
+    CIL_HIP(hipMemcpyAsync(dsteps, hsteps.data(), sizeof(long long) * B, hipMemcpyHostToDevice, c.st));
+    const PersistArgs pa{(long long)c.max_steps, c.tol, c.check, 0.0, dsteps, dres, dstat, g_wave_priority};
+    size_t gi = 0;
+    for (auto &kv : byn) {
+        int *dl;
+        CIL_TRY(c.cb->alloc((void **)&dl, sizeof(int) * kv.second.size()));
+        CIL_HIP(hipMemcpyAsync(dl, kv.second.data(), sizeof(int) * kv.second.size(), hipMemcpyHostToDevice, c.st));
+        const ProfMark pm = prof_begin(kv.first == 32 ? "k_fused_q_refine_n32" : "k_fused_q_refine_n64", c.st);
+        const int rc = launch_quad_refine(kv.first, (int)kv.second.size(), dS, dl, state, u64,
+                                          (const float *)tabs[gi++], c.model, c.dt, pa, c.st);
+        prof_end(pm, c.st);
+        if (rc) return set_error(rc, "no refinement kernel for n = %d", kv.first);
+        CIL_TRY(check_launch("k_fused_q_refine"));
+    }
+    std::vector<double> hres(B);
+    std::vector<int> hstat(B);
+    CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipStreamSynchronize(c.st));
+    for (auto &kv : byn)
+        for (int b : kv.second) {
+            c.steps[b] = hsteps[b];
+            c.fres[b] = hres[b];
+            c.status[b] = hstat[b];
         }
     return CIL_OK;
 }
@@ -1138,6 +1189,7 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     c.fres.assign(B, 0.0);
     c.status.assign(B, CIL_SOLVE_OK);
     const bool polish = f32 && stp->polish && stp->tol > 0.0;
+    c.polish = polish ? stp->polish : 0;
     const bool quad = stp->path != CIL_PATH_FUSED_LINE;
     if (scheme) {
         if (stp->path == CIL_PATH_FUSED_QUAD)
@@ -1198,7 +1250,7 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
     CIL_TRY(cb.alloc((void **)&R.bad, sizeof(int) * B));
 
     c.sw.assign(B, -1);
-    MixedArgs mx{nullptr, nullptr};
+    MixedArgs mx{nullptr, nullptr, c.polish == 2};
     bool use_mixed = false;
     if (polish)
         for (auto &kv : fused_byn) use_mixed |= mixed_supported(kv.first, quad);
@@ -1229,12 +1281,35 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         }
     }
 
-    // phase 2: FP32 solves stopped at the FP32 floor continue in FP64
+    // phase 2: FP32 solves stopped at the FP32 floor continue in FP64 steps,
+    // or in the refinement form where its kernel exists
     std::vector<int64_t> steps64(B, 0);
     std::vector<int> promoted;
+    std::map<int, std::vector<int>> refine_byn;
+    std::vector<char> on_fused(B, 0);
+    for (auto &kv : fused_byn)
+        for (int b : kv.second) on_fused[b] = 1;
     for (int b = 0; b < B; ++b) {
         if (c.sw[b] >= 0) steps64[b] = c.steps[b] - c.sw[b];     // polished inside the mixed launch
-        if (polish && c.status[b] == CIL_SOLVE_FP32_FLOOR) promoted.push_back(b);
+        if (!polish || c.status[b] != CIL_SOLVE_FP32_FLOOR) continue;
+        if (c.polish == 2 && on_fused[b] && quad && g_quad_shape_option < 0 && (hs[b].n == 32 || hs[b].n == 64))
+            refine_byn[hs[b].n].push_back(b);
+        else
+            promoted.push_back(b);
+    }
+    if (!refine_byn.empty()) {
+        double *u64 = mx.state64;
+        if (!u64) {
+            int64_t end = 0;
+            for (int b = 0; b < B; ++b) end = std::max<int64_t>(end, hs[b].off + elems[b]);
+            CIL_TRY(cb.alloc((void **)&u64, sizeof(double) * (size_t)end));
+        }
+        std::vector<int64_t> before(c.steps);
+        for (auto &kv : refine_byn)
+            for (int b : kv.second) c.status[b] = CIL_SOLVE_OK;
+        CIL_TRY(run_refine(c, refine_byn, hs, dS, (float *)state, u64, dsteps, dres, dstat));
+        for (auto &kv : refine_byn)
+            for (int b : kv.second) steps64[b] = c.steps[b] - before[b];
     }
     if (!promoted.empty()) {
         std::vector<DevSolve> hs64 = hs;

@@ -69,8 +69,39 @@ __device__ __forceinline__ void kinetics(const T *p, T v, T w, T &f, T &g)
     }
 }
 
+// The change of the Sec. 4.1 reaction terms between the point (v, w) = (a, b)
+// and (a + x, b + y): df = f(a + x, b + y) - f(a, b), dg likewise, expanded
+// so that only terms of order x or y remain (no difference of O(1) values
+// cancels).  Evaluated in T at a rounded (a, b), the error is a few units of
+// T relative to the change itself, however small the change.
+template <int MODEL, typename T>
+__device__ __forceinline__ void kinetics_delta(const T *p, T a, T b, T x, T y, T &df, T &dg)
+{
+    if constexpr (MODEL == CIL_FHN) {
+        df = p[1] * (y - p[2] * x);
+        dg = -x + p[0] * y - y * (T(3) * b * (b + y) + y * y);        // (b + y)^3 - b^3
+    } else if constexpr (MODEL == CIL_GM || MODEL == CIL_GM_SOURCE) {
+        const T sq = (a + a + x) * x;                                   // (a + x)^2 - a^2
+        const T dq = (sq * b - a * a * y) * recip(b * (b + y));         // (a + x)^2/(b + y) - a^2/b
+        if constexpr (MODEL == CIL_GM) {
+            df = -p[0] * x + dq;
+            dg = -p[1] * y + sq;
+        } else {
+            df = -p[1] * x + dq;
+            dg = sq - y;
+        }
+    } else if constexpr (MODEL == CIL_BRUSSELATOR) {
+        const T dc = (a + a + x) * x * (b + y) + a * a * y;             // (a + x)^2 (b + y) - a^2 b
+        df = -(p[1] + T(1)) * x + dc;
+        dg = p[1] * x - dc;
+    } else {
+        df = T(0);
+        dg = T(0);
+    }
+}
+
 template <typename F>
-__device__ __forceinline__ void dispatch_model(int model, F &&f)
+__host__ __device__ __forceinline__ void dispatch_model(int model, F &&f)
 {
     switch (model) {
     case CIL_FHN: f(std::integral_constant<int, CIL_FHN>{}); break;
@@ -118,9 +149,15 @@ __device__ __forceinline__ void set_issue_priority(double ratio, double base)
 
 // Mixed-precision quad launch (stepper_quad_mixed.hip): n = 32 and 64 with the
 // default shapes (FP32 shape 1 / FP64 shape 1 at n = 32, 2 / 0 at n = 64).
+// refine = 1: the continuation is the refinement form (FP64 state in state64,
+// FP32 correction steps; tab64 unused), else FP64 steps.
 int launch_quad_mixed(int n, int nl, const DevSolve *S, const int *list, float *state, double *state64,
                       const float *tab32, const double *tab64, int model, double dt, const PersistArgs &pa32,
-                      const PersistArgs &pa64, long long *switch_step, hipStream_t st);
+                      const PersistArgs &pa64, long long *switch_step, int refine, hipStream_t st);
+// The refinement form alone, from the FP32 state (n = 32 and 64, default
+// FP32 shapes); state64 (same layout) holds the FP64 state meanwhile.
+int launch_quad_refine(int n, int nl, const DevSolve *S, const int *list, float *state, double *state64,
+                       const float *tab32, int model, double dt, const PersistArgs &pa, hipStream_t st);
 
 // Quad-variant launch, one translation unit per precision (stepper_quad_*.hip).
 int launch_quad_f32(int n, int shape, int nl, const DevSolve *S, const int *list, float *state, const float *tables,

@@ -17,11 +17,29 @@ namespace cil {
 // `state` first when LOAD, stored to `out` (element type TS, same layout) at
 // the end.  `step` enters as the first step and leaves as the last; the
 // return value is the status of the last evaluation (-1 if none ran).
-template <typename T, int N, int SPL, bool VF, typename MD, bool LOAD, typename TS>
+//
+// RF (refinement form, T = float): u = U + v with U in FP64 (u64, state
+// layout) and the correction v in ur/ui.  One step of the same IMEX Euler
+// iteration in these variables is
+//     v' = S(v + dt (R + f(U + v) - f(U))),   R = f(U) + nu Lap U,
+// S the diffusion solve: the transforms act on v, whose size is that of the
+// motion since U was last set, so FP32 rounding stays proportional to it and
+// the iteration has no FP32 floor.  R is formed in FP64 (five-point stencil
+// with ghost copies, the Laplacian the DCT-II solve diagonalises) and the
+// reaction change by kinetics_delta; U absorbs v (U += v, v = 0) at the
+// start and after evaluations at least kRebase steps apart, which keeps v of
+// the size of the motion over that many steps (each re-basing costs about one
+// FP64 step).  The stop rule compares v with its snapshot taken since, which
+// is u^s - u^(s-1).  sm must then hold 2 N (N + 1) doubles.
+constexpr int kRebase = 200;
+
+template <typename T, int N, int SPL, bool VF, typename MD, bool LOAD, typename TS, bool RF = false>
 __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, const DevSolve &s, int b, T *state,
                                              TS *out, const T *tables, double dt, const PersistArgs &pa,
-                                             long long &step, T (&ur)[SPL][N / 8], T (&ui)[SPL][N / 8])
+                                             long long &step, T (&ur)[SPL][N / 8], T (&ui)[SPL][N / 8],
+                                             double *u64 = nullptr)
 {
+    static_assert(!RF || std::is_same<T, float>::value, "the refinement form steps its correction in FP32");
     using Q = QuadLine<T, N>;
     constexpr int P = Q::P, M = N / 2;
     constexpr int LD = N + 1, SP = N * LD, NN = N * N;
@@ -80,7 +98,65 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
             }
         });
     }
+    // refinement form: U rounded to T (own species c at (m1, h); o32 the other
+    // species at the same points when SPL == 1) and R rounded to T
+    constexpr int RP = RF ? P : 1;
+    T u32[SPL][2][RP], r32[SPL][2][RP], o32[2][(RF && SPL == 1) ? P : 1];
+    const auto u64r = make_rsrc(RF ? u64 + s.off : nullptr, RF ? 2 * NN * sizeof(double) : 0);
+    const unsigned du0 = (sp0 * NN + g * N + lo) * sizeof(double), du1 = (sp0 * NN + g * N + hi0) * sizeof(double);
+    auto rebase = [&](bool first) __attribute__((always_inline)) {
+        double *const sd = reinterpret_cast<double *>(sm);
+        __syncthreads();                                   // the LDS's last readers are done
+        static_for<0, P>([&](auto Mi) {
+            constexpr int m1 = Mi;
+            static_for<0, 2>([&](auto Hc) {
+                constexpr int h = Hc;
+                const int pos = (m1 < P / 2 ? lo : hi0) + line_off(Mi, Hc);
+                const unsigned off = (m1 < P / 2 ? du0 : du1) + line_off(Mi, Hc) * sizeof(double);
+#pragma unroll
+                for (int c = 0; c < SPL; ++c) {
+                    double U;
+                    if constexpr (h == 0) U = (double)ur[c][m1];
+                    else U = (double)ui[c][m1];
+                    if (!first) U += buf_load<double>(u64r, off, c * NN * sizeof(double));
+                    buf_store<double>(U, u64r, off, c * NN * sizeof(double));
+                    sd[(sp0 + c) * SP + g * LD + pos] = U;
+                    if constexpr (h == 0) ur[c][m1] = T(0);
+                    else ui[c][m1] = T(0);
+                }
+            });
+        });
+        __syncthreads();
+        const double pd[4] = {s.p[0], s.p[1], s.p[2], s.p[3]};
+        const int gu = g > 0 ? g - 1 : 0, gd = g < N - 1 ? g + 1 : N - 1;
+        static_for<0, P>([&](auto Mi) {
+            constexpr int m1 = Mi;
+            static_for<0, 2>([&](auto Hc) {
+                constexpr int h = Hc;
+                const int pos = (m1 < P / 2 ? lo : hi0) + line_off(Mi, Hc);
+                const int pl = pos > 0 ? pos - 1 : 0, pr = pos < N - 1 ? pos + 1 : N - 1;
+#pragma unroll
+                for (int c = 0; c < SPL; ++c) {
+                    const int cs = sp0 + c;
+                    const double *const fld = sd + cs * SP;
+                    const double U0 = fld[g * LD + pos];
+                    const double Uo = sd[(1 - cs) * SP + g * LD + pos];
+                    const double lap =
+                        (fld[g * LD + pl] + fld[g * LD + pr] + fld[gu * LD + pos] + fld[gd * LD + pos] - 4.0 * U0) *
+                        s.inv_h2;
+                    double f, gg;
+                    kinetics<MD::value>(pd, cs ? Uo : U0, cs ? U0 : Uo, f, gg);
+                    r32[c][h][m1] = (T)((cs ? gg : f) + (cs ? s.nu[1] : s.nu[0]) * lap);
+                    u32[c][h][m1] = (T)U0;
+                    if constexpr (SPL == 1) o32[h][m1] = (T)Uo;
+                }
+            });
+        });
+        __syncthreads();                                   // the row forward writes the LDS next
+    };
     const long long start = step;
+    long long last_rebase = step;
+    if constexpr (RF) rebase(true);
     int fin = -1;
     while (true) {
         const bool eval_now = step > start && ((step % pa.check == 0) || step == pa.max_steps);
@@ -95,7 +171,7 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
                     const double d0 = fabs(v0 - (double)o0), d1 = fabs(v1 - (double)o1);
                     bad |= !isfinite(v0) || !isfinite(v1);
                     d = fmax(d, fmax(isnan(d0) ? 0.0 : d0, isnan(d1) ? 0.0 : d1));
-                    a = fmax(a, fmax(isnan(v0) ? 0.0 : fabs(v0), isnan(v1) ? 0.0 : fabs(v1)));
+                    if constexpr (!RF) a = fmax(a, fmax(isnan(v0) ? 0.0 : fabs(v0), isnan(v1) ? 0.0 : fabs(v1)));
                 }
             });
             d = wave_max(d);
@@ -128,6 +204,12 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
             fin = st;
             if (st >= 0) break;
             if (pa.prio > 1.0 && pa.tol > 0.0) set_issue_priority(r / pa.tol, pa.prio);
+            if constexpr (RF) {
+                if (step - last_rebase >= kRebase) {      // uniform over the workgroup
+                    rebase(false);
+                    last_rebase = step;
+                }
+            }
         }
         if (step >= pa.max_steps) break;
         const long long next = step + 1;
@@ -146,7 +228,23 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
             constexpr int m1 = Mi;
             constexpr int pb = bitrev(m1, Q::LOGP);
             T f, gg;
-            if constexpr (SPL == 2) {
+            if constexpr (RF && SPL == 2) {               // v + dt (R + f(U + v) - f(U))
+                kinetics_delta<MD::value>(p, u32[0][0][m1], u32[1][0][m1], ur[0][m1], ur[1][m1], f, gg);
+                xr[0][pb] = ur[0][m1] + tdt * (r32[0][0][m1] + f);
+                xr[1][pb] = ur[1][m1] + tdt * (r32[1][0][m1] + gg);
+                kinetics_delta<MD::value>(p, u32[0][1][m1], u32[1][1][m1], ui[0][m1], ui[1][m1], f, gg);
+                xi[0][pb] = ui[0][m1] + tdt * (r32[0][1][m1] + f);
+                xi[1][pb] = ui[1][m1] + tdt * (r32[1][1][m1] + gg);
+            } else if constexpr (RF) {
+                const T pr = dpp_mov<DPP_HALF_MIRROR>(ur[0][m1]), pi = dpp_mov<DPP_HALF_MIRROR>(ui[0][m1]);
+                const T a0 = u32[0][0][m1], o0 = o32[0][m1], a1 = u32[0][1][m1], o1 = o32[1][m1];
+                kinetics_delta<MD::value>(p, sp0 ? o0 : a0, sp0 ? a0 : o0, sp0 ? pr : ur[0][m1], sp0 ? ur[0][m1] : pr,
+                                          f, gg);
+                xr[0][pb] = ur[0][m1] + tdt * (r32[0][0][m1] + (sp0 ? gg : f));
+                kinetics_delta<MD::value>(p, sp0 ? o1 : a1, sp0 ? a1 : o1, sp0 ? pi : ui[0][m1], sp0 ? ui[0][m1] : pi,
+                                          f, gg);
+                xi[0][pb] = ui[0][m1] + tdt * (r32[0][1][m1] + (sp0 ? gg : f));
+            } else if constexpr (SPL == 2) {
                 kinetics<MD::value>(p, ur[0][m1], ur[1][m1], f, gg);
                 xr[0][pb] = ur[0][m1] + tdt * f;
                 xr[1][pb] = ur[1][m1] + tdt * gg;
@@ -230,6 +328,18 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
         }
         step = next;
     }
+    if constexpr (RF) {                                    // u = U + v
+        static_for<0, P>([&](auto Mi) {
+            constexpr int m1 = Mi;
+            const unsigned b0 = (m1 < P / 2 ? du0 : du1);
+#pragma unroll
+            for (int c = 0; c < SPL; ++c) {
+                const int so = c * NN * sizeof(double);
+                ur[c][m1] = T(buf_load<double>(u64r, b0 + line_off(Mi, I0{}) * sizeof(double), so) + (double)ur[c][m1]);
+                ui[c][m1] = T(buf_load<double>(u64r, b0 + line_off(Mi, I1{}) * sizeof(double), so) + (double)ui[c][m1]);
+            }
+        });
+    }
     const auto ob = make_rsrc(out + s.off, 2 * NN * sizeof(TS));
     static_for<0, P>([&](auto Mi) {
 #pragma unroll
@@ -282,10 +392,13 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(W
 // followed by an FP64 launch over the promoted solves, without the second
 // launch waiting for the whole batch's FP32 phase.  switch_step[b]: the step
 // at which solve b changed precision (its last step if it did not).
-template <int N, int SPL, bool VF32, bool VF64>
+// RF: the continuation is the refinement form instead (FP64 state in
+// state64, FP32 correction steps; tab64 unused).  One kernel per model, so
+// that each model's two phases get a register allocation of their own.
+template <int MODEL, int N, int SPL, bool VF32, bool VF64, bool RF>
 __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_q_mixed(
     const DevSolve *S, const int *list, float *state, double *state64, const float *tab32, const double *tab64,
-    int model, double dt, PersistArgs pa32, PersistArgs pa64, long long *switch_step)
+    double dt, PersistArgs pa32, PersistArgs pa64, long long *switch_step)
 {
     constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64, P = N / 8;
     __shared__ double sm[2 * SP];
@@ -294,12 +407,17 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
     long long step = pa32.steps[b];
-    dispatch_model(model, [&](auto MD) {
+    [&](auto MD) {
         float ur[SPL][P], ui[SPL][P];
         const int fin = fused_q_solve<float, N, SPL, VF32, decltype(MD), true, float>(
             reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa32, step, ur, ui);
         const long long sw = step;
-        if (fin == CIL_SOLVE_FP32_FLOOR) {         // uniform: every lane holds the same stop decision
+        if constexpr (RF) {
+            if (fin == CIL_SOLVE_FP32_FLOOR)
+                fused_q_solve<float, N, SPL, VF32, decltype(MD), false, float, true>(
+                    reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa64, step, ur, ui,
+                    state64);
+        } else if (fin == CIL_SOLVE_FP32_FLOOR) {  // uniform: every lane holds the same stop decision
             double vr[SPL][P], vi[SPL][P];
 #pragma unroll
             for (int c = 0; c < SPL; ++c)
@@ -313,7 +431,25 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2
                                                                             dt, pa64, step, vr, vi);
         }
         if (threadIdx.x == 0) switch_step[b] = sw;
-    });
+    }(std::integral_constant<int, MODEL>{});
+}
+
+// The refinement form alone (the second phase of the mixed launch as a
+// launch of its own): from the FP32 state, U in state64.
+template <int MODEL, int N, int SPL, bool VF>
+__global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_q_refine(
+    const DevSolve *S, const int *list, float *state, double *state64, const float *tab32, double dt, PersistArgs pa)
+{
+    constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64, P = N / 8;
+    __shared__ double sm[2 * SP];
+    __shared__ double red[2 * WAVES];
+    __shared__ int sbad[WAVES];
+    const int b = list[blockIdx.x];
+    const DevSolve s = S[b];
+    long long step = pa.steps[b];
+    float ur[SPL][P], ui[SPL][P];
+    fused_q_solve<float, N, SPL, VF, std::integral_constant<int, MODEL>, true, float, true>(
+        reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa, step, ur, ui, state64);
 }
 
 template <typename T, int N, int SPL, int WPE, bool VF>

@@ -86,7 +86,8 @@ def test_simulate_argument_validation_before_device():
     assert _simulate_raw(probs, good) == cil.CIL_EINVAL
     assert b"n = 1" in cil.lib().cil_last_error()
     probs = cil.make_problems(8, 1.0, (0.1, 0.1), (1.0, 1.0, 1.0))
-    for field, val in (("dt", 0.0), ("dt", -1.0), ("max_steps", -1), ("check_every", 0), ("path", 7)):
+    for field, val in (("dt", 0.0), ("dt", -1.0), ("max_steps", -1), ("check_every", 0), ("path", 7), ("polish", 3),
+                       ("polish", -1)):
         st = cil.Stepping(dt=0.01, max_steps=10, tol=0.0, check_every=1, path=0, polish=1, fp32_floor_ulps=0)
         setattr(st, field, val)
         assert _simulate_raw(probs, st) == cil.CIL_EINVAL, field
@@ -103,7 +104,7 @@ def test_second_order_entry_validates_like_the_euler_one():
     e = "cil_simulate_patterns_sbdf2"
     assert _simulate_raw(cil.make_problems(1, 1.0, (0.1, 0.1), (1.0, 1.0, 1.0)), good, entry=e) == cil.CIL_EINVAL
     probs = cil.make_problems(8, 1.0, (0.1, 0.1), (1.0, 1.0, 1.0))
-    for field, val in (("dt", 0.0), ("max_steps", -1), ("check_every", 0), ("path", 7)):
+    for field, val in (("dt", 0.0), ("max_steps", -1), ("check_every", 0), ("path", 7), ("polish", 3)):
         st = cil.Stepping(dt=0.01, max_steps=10, tol=0.0, check_every=1, path=0, polish=0, fp32_floor_ulps=0)
         setattr(st, field, val)
         assert _simulate_raw(probs, st, entry=e) == cil.CIL_EINVAL, field

@@ -3,14 +3,15 @@ times): 500 Gierer-Meinhardt (source form) solves on 64x64 grids to FP64
 residual < 1e-8, then the CIL statistic of the two 250-pattern halves stored
 as FP32 (d = 8192, 13 radii, 200 bootstrap resamples) and the likelihood.
 
-The benchmarked stepping is FP32 with each solve's FP64 polish (from its FP32
-floor to the tolerance) in the same launch.  Its patterns are checked by
-properties that hold one by one: every stored pattern is stationary under
-one IMEX-Euler step (residual within what FP32 storage rounding allows,
-tol + 4 x 2^-24 max|u| / dt; the step is evaluated here with scipy's
-orthonormal DCT-II, itself checked on the oracle's stationary patterns), and
-the whole batch is bit-identical to the FP32 launch followed by a separate
-FP64 launch.  The FP64 fused stepping is checked against the oracle directly
+The benchmarked stepping is FP32 with each solve's polish (from its FP32
+floor to the tolerance) in the same launch, in the refinement form (FP64
+state, FP32 correction steps); the FP64-step polish is checked the same way.
+Their patterns are checked by properties that hold one by one: every stored
+pattern is stationary under one IMEX-Euler step (residual within what FP32
+storage rounding allows, tol + 4 x 2^-24 max|u| / dt; the step is evaluated
+here with scipy's orthonormal DCT-II, itself checked on the oracle's
+stationary patterns), and the whole batch is bit-identical to the FP32
+launch followed by a separate polish launch.  The FP64 fused stepping is checked against the oracle directly
 (sampled solves: step counts identical, patterns within 1e-8).  The
 statistic is checked in full on the oracle's own 500 stationary patterns,
 stored as FP32 and as FP64: the oracle computes all 62 500 canonical
@@ -86,23 +87,27 @@ def stepped32(cil):
     base = cil.cil_homogeneous_state(w["model"], w["params"])
     ics = cs.initial_conditions(base, w["n"], w["count"], seed=w["seeds"][0], law=w["ic_law"])
     probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=w["count"])
-    out = []
+    out = {}
     try:
-        for sep in (0, 1):
-            cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
-            st = torch.tensor(ics, dtype=torch.float32, device="cuda")
-            print("full-size GM-source run, FP32 + FP64 polish (separate launch: %d)" % sep, flush=True)
-            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
-                                            check_every=w["check_every"], polish=1)
-            out.append((st, rep))
+        for polish in (1, 2):
+            for sep in (0, 1):
+                cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
+                st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+                print("full-size GM-source run, FP32 + polish %d (separate launch: %d)" % (polish, sep), flush=True)
+                rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                                check_every=w["check_every"], polish=polish)
+                out.setdefault(polish, []).append((st, rep))
     finally:
         cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 0)
     return w, ics, out
 
 
-def test_full_workload_fp32_polished_patterns(cil, oracle_mod, stepped32):
+@pytest.mark.parametrize("polish", [1, 2])
+def test_full_workload_fp32_polished_patterns(cil, oracle_mod, stepped32, polish):
+    """polish 1: FP64 steps from the FP32 floor; 2: the refinement form (FP64
+    state, FP32 correction steps), the benchmarked configuration."""
     w, ics, out = stepped32
-    (st, rep), (st2, rep2) = out
+    (st, rep), (st2, rep2) = out[polish]
     assert torch.equal(st, st2)
     for k in ("steps_taken", "steps_fp64", "final_resid", "status"):
         assert np.array_equal(rep[k], rep2[k]), k

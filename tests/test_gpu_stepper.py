@@ -343,6 +343,44 @@ def test_mixed_polish_equals_separate_launch(cil, n, L):
         assert np.all(out[0][1]["status"] == 0) and np.all(out[0][1]["final_resid"] < w["tol"])
 
 
+@pytest.mark.parametrize("n,L", [(64, 120.0), (32, 60.0)])
+def test_refinement_polish(cil, n, L):
+    """The refinement polish (polish = 2: FP64 state, FP32 correction steps
+    with the FP64 residual of the five-point system) gives the same bits
+    inside the mixed launch and as a launch of its own; it stops where the
+    FP64-step polish stops (same statuses, step counts within one
+    evaluation interval) and its patterns agree with that polish's to two
+    FP32 roundings plus the motion of one interval at the tolerance."""
+    w, ics, probs = _gm_batch(cil, n, 24, seed=51 + n, L=L)
+    out = []
+    try:
+        for polish, sep in ((2, 0), (2, 1), (1, 0)):
+            cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, sep)
+            st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+            print("polish=%d separate=%d n=%d" % (polish, sep, n), flush=True)
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                            check_every=w["check_every"], polish=polish)
+            out.append((st, rep))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_POLISH_SEPARATE, 0)
+    (a, ra), (b, rb), (c, rc) = out
+    assert torch.equal(a, b)
+    for k in ("steps_taken", "steps_fp64", "final_resid", "status"):
+        assert np.array_equal(ra[k], rb[k]), k
+    assert np.any(ra["steps_fp64"] > 0)
+    assert np.array_equal(ra["status"], rc["status"])
+    ok = ra["status"] == 0
+    if n == 64:
+        assert np.all(ok)
+    assert np.all(ra["final_resid"][ok] < w["tol"])
+    assert np.all(np.abs(ra["steps_taken"] - rc["steps_taken"]) <= w["check_every"])
+    ga, gc = a.double().cpu().numpy(), c.double().cpu().numpy()
+    diff = np.abs(ga - gc).reshape(len(probs), -1).max(axis=1)
+    bar = 2.0 ** -22 * np.abs(gc).reshape(len(probs), -1).max(axis=1) + w["check_every"] * w["tol"] * w["dt"]
+    print("refinement vs FP64-step polish: max difference %.3e (bar %.3e)" % (diff.max(), bar.min()))
+    assert np.all(diff[ok] <= bar[ok])
+
+
 def test_mixed_polish_uneven_sides(cil):
     """Sides 32, 64 (mixed launches) and 128 (FP32 launch + FP64 plain
     polish) in one call: identical to the separate polish launches."""
