@@ -426,9 +426,10 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   values outside the range.
  * CIL_OPT_POLISH_SEPARATE (value 0/1): FP32 solves with polish != 0 on the
  *   fused quad-lane path at n = 32 or 64 (default shapes) continue from their
- *   FP32 floor inside the same persistent launch (0, default); 1 = the polish
- *   runs as a launch of its own after the whole FP32 phase.  Both give
- *   identical results. */
+ *   FP32 floor inside the same persistent launch (0, default); 1 = the same
+ *   kernel runs twice, the FP32 phase of the whole batch, then the polish of
+ *   the solves at their floor.  Both give identical results.  (Other sides
+ *   always polish in FP64 steps in a launch of their own.) */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
        CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6, CIL_OPT_POLISH_SEPARATE = 7 };
 int cil_set_option(int32_t option, int64_t value);

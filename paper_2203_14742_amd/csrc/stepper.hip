@@ -587,7 +587,7 @@ int fused_supported(int n, bool f32)
 }
 
 int g_quad_shape_option = -1;
-int g_polish_separate = 0;         // 1: FP64 polish always in a launch of its own
+int g_polish_separate = 0;         // 1: the polish always in a launch of its own
 // 0: off, else the base of the priority levels.  Measured on the 500-solve GM
 // batch (FP64, residual 1e-8): off 30.5 ms; base 3: 30.2; 10: 29.9; 100: 29.5;
 // 1000: 29.4.
@@ -836,7 +836,7 @@ struct MixedArgs {
 
 bool mixed_supported(int n, bool quad)
 {
-    return quad && !g_polish_separate && g_quad_shape_option < 0 && (n == 32 || n == 64);
+    return quad && g_quad_shape_option < 0 && (n == 32 || n == 64);
 }
 
 // Spectral tables for the solves in `ids` (side n): one per distinct (h, nu);
@@ -890,7 +890,7 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
         CIL_TRY(make_tables<T>(c, kv.first, kv.second, hs, &t,
                                quad && kQuadShape[quad_shape(std::is_same<T, float>::value, kv.first)].vform));
         const bool mix = mx && mixed_supported(kv.first, quad);
-        if (mix && !mx->refine)
+        if (mix && !mx->refine && !g_polish_separate)
             CIL_TRY(make_tables<double>(c, kv.first, kv.second, hs, &t64, kQuadShape[quad_shape(false, kv.first)].vform));
         tabs.push_back(t);
         tabs64.push_back(t64);
@@ -941,10 +941,15 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
             if (mixed[gi]) {
                 PersistArgs pa64 = pa;
                 pa64.floor_coef = 0.0;
-                const ProfMark pm = prof_begin(kv.first == 32 ? "k_fused_q_mixed_n32" : "k_fused_q_mixed_n64", gst);
+                // separate polish: the FP32 phase here, the continuation in a
+                // launch of its own over the solves at their floor (run_phase2)
+                const int mode = g_polish_separate ? 1 : 0;
+                const ProfMark pm = prof_begin(kv.first == 32 ? (mode ? "k_fused_q_mixed_n32_phase1" : "k_fused_q_mixed_n32")
+                                                              : (mode ? "k_fused_q_mixed_n64_phase1" : "k_fused_q_mixed_n64"),
+                                               gst);
                 const int rc = launch_quad_mixed(kv.first, (int)kv.second.size(), dS, dls[gi], state, mx->state64,
                                                  (const float *)tabs[gi], (const double *)tabs64[gi], c.model, c.dt,
-                                                 pa, pa64, mx->sw, mx->refine, gst);
+                                                 pa, pa64, mx->sw, mx->refine, mode, gst);
                 prof_end(pm, gst);
                 if (rc) return set_error(rc, "no mixed-precision kernel for n = %d", kv.first);
                 CIL_TRY(check_launch("k_fused_q_mixed"));
@@ -983,20 +988,23 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
     return CIL_OK;
 }
 
-// The refinement form as a launch of its own over FP32 solves stopped at
-// their floor (quad-lane, n = 32 and 64, default shapes): the separate-launch
-// counterpart of the mixed launch's continuation.  u64: FP64 state, same
-// element layout as `state`.
-int run_refine(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<DevSolve> &hs, DevSolve *dS,
-               float *state, double *u64, long long *dsteps, double *dres, int *dstat)
+// The mixed kernel's continuation as a launch of its own (mode 2) over FP32
+// solves that its FP32-phase launch (mode 1) left at their floor: FP64 steps,
+// or the refinement form with `refine`.  state64: same element layout as
+// `state`.
+int run_phase2(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector<DevSolve> &hs, DevSolve *dS,
+               float *state, double *state64, long long *sw, bool refine, long long *dsteps, double *dres, int *dstat)
 {
     if (byn.empty()) return CIL_OK;
     const int B = (int)hs.size();
-    std::vector<void *> tabs;
+    std::vector<void *> tabs, tabs64;
     for (auto &kv : byn) {
-        void *t;
+        void *t, *t64 = nullptr;
         CIL_TRY(make_tables<float>(c, kv.first, kv.second, hs, &t, kQuadShape[quad_shape(true, kv.first)].vform));
+        if (!refine)
+            CIL_TRY(make_tables<double>(c, kv.first, kv.second, hs, &t64, kQuadShape[quad_shape(false, kv.first)].vform));
         tabs.push_back(t);
+        tabs64.push_back(t64);
     }
     CIL_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(DevSolve) * B, hipMemcpyHostToDevice, c.st));
     std::vector<long long> hsteps(c.steps.begin(), c.steps.end());
@@ -1007,12 +1015,15 @@ int run_refine(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vecto
         int *dl;
         CIL_TRY(c.cb->alloc((void **)&dl, sizeof(int) * kv.second.size()));
         CIL_HIP(hipMemcpyAsync(dl, kv.second.data(), sizeof(int) * kv.second.size(), hipMemcpyHostToDevice, c.st));
-        const ProfMark pm = prof_begin(kv.first == 32 ? "k_fused_q_refine_n32" : "k_fused_q_refine_n64", c.st);
-        const int rc = launch_quad_refine(kv.first, (int)kv.second.size(), dS, dl, state, u64,
-                                          (const float *)tabs[gi++], c.model, c.dt, pa, c.st);
+        const ProfMark pm =
+            prof_begin(kv.first == 32 ? "k_fused_q_mixed_n32_phase2" : "k_fused_q_mixed_n64_phase2", c.st);
+        const int rc = launch_quad_mixed(kv.first, (int)kv.second.size(), dS, dl, state, state64,
+                                         (const float *)tabs[gi], (const double *)tabs64[gi], c.model, c.dt, pa, pa,
+                                         sw, refine, 2, c.st);
+        ++gi;
         prof_end(pm, c.st);
-        if (rc) return set_error(rc, "no refinement kernel for n = %d", kv.first);
-        CIL_TRY(check_launch("k_fused_q_refine"));
+        if (rc) return set_error(rc, "no mixed-precision kernel for n = %d", kv.first);
+        CIL_TRY(check_launch("k_fused_q_mixed"));
     }
     std::vector<double> hres(B);
     std::vector<int> hstat(B);
@@ -1281,35 +1292,25 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
         }
     }
 
-    // phase 2: FP32 solves stopped at the FP32 floor continue in FP64 steps,
-    // or in the refinement form where its kernel exists
+    // phase 2: FP32 solves stopped at the FP32 floor continue: those whose
+    // FP32 phase ran in the mixed kernel (separate polish) in its second
+    // launch, the others in FP64 steps
     std::vector<int64_t> steps64(B, 0);
     std::vector<int> promoted;
-    std::map<int, std::vector<int>> refine_byn;
-    std::vector<char> on_fused(B, 0);
-    for (auto &kv : fused_byn)
-        for (int b : kv.second) on_fused[b] = 1;
+    std::map<int, std::vector<int>> cont_byn;
     for (int b = 0; b < B; ++b) {
         if (c.sw[b] >= 0) steps64[b] = c.steps[b] - c.sw[b];     // polished inside the mixed launch
         if (!polish || c.status[b] != CIL_SOLVE_FP32_FLOOR) continue;
-        if (c.polish == 2 && on_fused[b] && quad && g_quad_shape_option < 0 && (hs[b].n == 32 || hs[b].n == 64))
-            refine_byn[hs[b].n].push_back(b);
-        else
-            promoted.push_back(b);
+        if (c.sw[b] >= 0) cont_byn[hs[b].n].push_back(b);
+        else promoted.push_back(b);
     }
-    if (!refine_byn.empty()) {
-        double *u64 = mx.state64;
-        if (!u64) {
-            int64_t end = 0;
-            for (int b = 0; b < B; ++b) end = std::max<int64_t>(end, hs[b].off + elems[b]);
-            CIL_TRY(cb.alloc((void **)&u64, sizeof(double) * (size_t)end));
-        }
-        std::vector<int64_t> before(c.steps);
-        for (auto &kv : refine_byn)
+    if (!cont_byn.empty()) {
+        for (auto &kv : cont_byn)
             for (int b : kv.second) c.status[b] = CIL_SOLVE_OK;
-        CIL_TRY(run_refine(c, refine_byn, hs, dS, (float *)state, u64, dsteps, dres, dstat));
-        for (auto &kv : refine_byn)
-            for (int b : kv.second) steps64[b] = c.steps[b] - before[b];
+        CIL_TRY(run_phase2(c, cont_byn, hs, dS, (float *)state, mx.state64, mx.sw, c.polish == 2, dsteps, dres,
+                           dstat));
+        for (auto &kv : cont_byn)
+            for (int b : kv.second) steps64[b] = c.steps[b] - c.sw[b];
     }
     if (!promoted.empty()) {
         std::vector<DevSolve> hs64 = hs;

@@ -150,14 +150,11 @@ __device__ __forceinline__ void set_issue_priority(double ratio, double base)
 // Mixed-precision quad launch (stepper_quad_mixed.hip): n = 32 and 64 with the
 // default shapes (FP32 shape 1 / FP64 shape 1 at n = 32, 2 / 0 at n = 64).
 // refine = 1: the continuation is the refinement form (FP64 state in state64,
-// FP32 correction steps; tab64 unused), else FP64 steps.
+// FP32 correction steps; tab64 unused), else FP64 steps.  mode 0: both
+// phases; 1: the FP32 phase only; 2: the continuation only (k_fused_q_mixed).
 int launch_quad_mixed(int n, int nl, const DevSolve *S, const int *list, float *state, double *state64,
                       const float *tab32, const double *tab64, int model, double dt, const PersistArgs &pa32,
-                      const PersistArgs &pa64, long long *switch_step, int refine, hipStream_t st);
-// The refinement form alone, from the FP32 state (n = 32 and 64, default
-// FP32 shapes); state64 (same layout) holds the FP64 state meanwhile.
-int launch_quad_refine(int n, int nl, const DevSolve *S, const int *list, float *state, double *state64,
-                       const float *tab32, int model, double dt, const PersistArgs &pa, hipStream_t st);
+                      const PersistArgs &pa64, long long *switch_step, int refine, int mode, hipStream_t st);
 
 // Quad-variant launch, one translation unit per precision (stepper_quad_*.hip).
 int launch_quad_f32(int n, int shape, int nl, const DevSolve *S, const int *list, float *state, const float *tables,

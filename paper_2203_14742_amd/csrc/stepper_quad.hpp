@@ -364,11 +364,12 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
 //   column pass  column forward, spectral divide, column inverse, all in
 //                registers (the split-step partners come by DPP) -> LDS.
 // The first row pass loads u from HBM instead; the last stores it there.
-// The model is dispatched once, outside the step loop.  WPE is the occupancy
-// the register allocation aims at (waves per SIMD).
-template <typename T, int N, int SPL, int WPE, bool VF>
+// One kernel per model (the host picks it), so that each model's step gets a
+// register allocation of its own.  WPE is the occupancy the register
+// allocation aims at (waves per SIMD).
+template <int MODEL, typename T, int N, int SPL, int WPE, bool VF>
 __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(WPE))) void k_fused_q(
-    const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt, PersistArgs pa)
+    const DevSolve *S, const int *list, T *state, const T *tables, double dt, PersistArgs pa)
 {
     constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64;
     __shared__ T sm[2 * SP];
@@ -377,28 +378,28 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(W
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
     long long step = pa.steps[b];
-    dispatch_model(model, [&](auto MD) {
-        T ur[SPL][N / 8], ui[SPL][N / 8];
-        fused_q_solve<T, N, SPL, VF, decltype(MD), true, T>(sm, red, sbad, s, b, state, state, tables, dt, pa, step,
-                                                            ur, ui);
-    });
+    T ur[SPL][N / 8], ui[SPL][N / 8];
+    fused_q_solve<T, N, SPL, VF, std::integral_constant<int, MODEL>, true, T>(sm, red, sbad, s, b, state, state,
+                                                                             tables, dt, pa, step, ur, ui);
 }
 
-// FP32 stepping with the FP64 polish in one persistent launch.  A solve that
-// stops at the FP32 floor converts its registers to FP64 and continues with
-// the FP64 step (FP64 tables, FP64 snapshots for its stop rule in state64) to
-// the tolerance; its final state is stored as FP32.  Each phase is the
-// one-precision solve above, so the result equals that of the FP32 launch
-// followed by an FP64 launch over the promoted solves, without the second
-// launch waiting for the whole batch's FP32 phase.  switch_step[b]: the step
-// at which solve b changed precision (its last step if it did not).
-// RF: the continuation is the refinement form instead (FP64 state in
-// state64, FP32 correction steps; tab64 unused).  One kernel per model, so
-// that each model's two phases get a register allocation of their own.
+// FP32 stepping with the polish in one persistent launch.  A solve that
+// stops at the FP32 floor continues to the tolerance either with FP64 steps
+// (its registers converted, FP64 tables, FP64 snapshots for its stop rule in
+// state64) or, with RF, in the refinement form (FP64 state in state64, FP32
+// correction steps; tab64 unused); its final state is stored as FP32.
+// switch_step[b]: the step at which solve b stopped its FP32 phase.
+// mode 0: both phases in this launch; 1: the FP32 phase only (solves at the
+// floor keep that status); 2: the second phase only, for solves that a
+// mode-1 launch left at their floor (the FP32 phase takes no step: it loads
+// the state and stores it back unchanged).  A mode-1 launch followed by a
+// mode-2 launch runs the same instructions as one mode-0 launch, so the two
+// give the same bits.  One kernel per model, so that each model's two phases
+// get a register allocation of their own.
 template <int MODEL, int N, int SPL, bool VF32, bool VF64, bool RF>
 __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_q_mixed(
     const DevSolve *S, const int *list, float *state, double *state64, const float *tab32, const double *tab64,
-    double dt, PersistArgs pa32, PersistArgs pa64, long long *switch_step)
+    double dt, PersistArgs pa32, PersistArgs pa64, long long *switch_step, int mode)
 {
     constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64, P = N / 8;
     __shared__ double sm[2 * SP];
@@ -407,17 +408,19 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2
     const int b = list[blockIdx.x];
     const DevSolve s = S[b];
     long long step = pa32.steps[b];
+    if (mode == 2) pa32.max_steps = step;
     [&](auto MD) {
         float ur[SPL][P], ui[SPL][P];
         const int fin = fused_q_solve<float, N, SPL, VF32, decltype(MD), true, float>(
             reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa32, step, ur, ui);
         const long long sw = step;
+        const bool go = mode == 2 || (mode == 0 && fin == CIL_SOLVE_FP32_FLOOR);   // uniform over the workgroup
         if constexpr (RF) {
-            if (fin == CIL_SOLVE_FP32_FLOOR)
+            if (go)
                 fused_q_solve<float, N, SPL, VF32, decltype(MD), false, float, true>(
                     reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa64, step, ur, ui,
                     state64);
-        } else if (fin == CIL_SOLVE_FP32_FLOOR) {  // uniform: every lane holds the same stop decision
+        } else if (go) {
             double vr[SPL][P], vi[SPL][P];
 #pragma unroll
             for (int c = 0; c < SPL; ++c)
@@ -430,34 +433,18 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2
             fused_q_solve<double, N, SPL, VF64, decltype(MD), false, float>(sm, red, sbad, s, b, state64, state, tab64,
                                                                             dt, pa64, step, vr, vi);
         }
-        if (threadIdx.x == 0) switch_step[b] = sw;
+        if (threadIdx.x == 0 && mode != 2) switch_step[b] = sw;
     }(std::integral_constant<int, MODEL>{});
-}
-
-// The refinement form alone (the second phase of the mixed launch as a
-// launch of its own): from the FP32 state, U in state64.
-template <int MODEL, int N, int SPL, bool VF>
-__global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_q_refine(
-    const DevSolve *S, const int *list, float *state, double *state64, const float *tab32, double dt, PersistArgs pa)
-{
-    constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64, P = N / 8;
-    __shared__ double sm[2 * SP];
-    __shared__ double red[2 * WAVES];
-    __shared__ int sbad[WAVES];
-    const int b = list[blockIdx.x];
-    const DevSolve s = S[b];
-    long long step = pa.steps[b];
-    float ur[SPL][P], ui[SPL][P];
-    fused_q_solve<float, N, SPL, VF, std::integral_constant<int, MODEL>, true, float, true>(
-        reinterpret_cast<float *>(sm), red, sbad, s, b, state, state, tab32, dt, pa, step, ur, ui, state64);
 }
 
 template <typename T, int N, int SPL, int WPE, bool VF>
 void launch_q1(int nl, const DevSolve *S, const int *list, T *state, const T *tables, int model, double dt,
                const PersistArgs &pa, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fused_q<T, N, SPL, WPE, VF>), dim3(nl), dim3((8 / SPL) * N), 0, st, S, list, state, tables,
-                       model, dt, pa);
+    dispatch_model(model, [&](auto MD) {
+        hipLaunchKernelGGL((k_fused_q<decltype(MD)::value, T, N, SPL, WPE, VF>), dim3(nl), dim3((8 / SPL) * N), 0, st,
+                           S, list, state, tables, dt, pa);
+    });
 }
 
 template <typename T, int N>

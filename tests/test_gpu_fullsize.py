@@ -10,8 +10,8 @@ Their patterns are checked by properties that hold one by one: every stored
 pattern is stationary under one IMEX-Euler step (residual within what FP32
 storage rounding allows, tol + 4 x 2^-24 max|u| / dt; the step is evaluated
 here with scipy's orthonormal DCT-II, itself checked on the oracle's
-stationary patterns), and the whole batch is bit-identical to the FP32
-launch followed by a separate polish launch.  The FP64 fused stepping is checked against the oracle directly
+stationary patterns), and the whole batch is bit-identical to the same
+kernel run as two launches (FP32 phase, then the polish).  The FP64 fused stepping is checked against the oracle directly
 (sampled solves: step counts identical, patterns within 1e-8).  The
 statistic is checked in full on the oracle's own 500 stationary patterns,
 stored as FP32 and as FP64: the oracle computes all 62 500 canonical

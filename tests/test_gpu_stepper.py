@@ -319,9 +319,9 @@ def _gm_batch(cil, n, count, seed, L):
 @pytest.mark.parametrize("n,L", [(64, 120.0), (32, 60.0)])
 def test_mixed_polish_equals_separate_launch(cil, n, L):
     """FP32 stepping with the FP64 polish inside one persistent launch gives
-    the bits of the FP32 launch followed by an FP64 launch over the solves
-    promoted at the FP32 floor: states, step counts (total and FP64),
-    residuals and statuses."""
+    the bits of the same kernel run as two launches (the FP32 phase of the
+    whole batch, then the polish of the solves at their FP32 floor): states,
+    step counts (total and FP64), residuals and statuses."""
     w, ics, probs = _gm_batch(cil, n, 24, seed=51 + n, L=L)
     out = []
     try:
@@ -382,8 +382,9 @@ def test_refinement_polish(cil, n, L):
 
 
 def test_mixed_polish_uneven_sides(cil):
-    """Sides 32, 64 (mixed launches) and 128 (FP32 launch + FP64 plain
-    polish) in one call: identical to the separate polish launches."""
+    """Sides 32, 64 (mixed launches) and 128 (FP32 launch + FP64 polish in a
+    launch of its own) in one call: identical to the separate polish
+    launches."""
     w = cs.WORKLOADS["gm_source64_stationary"]
     ns = [32, 64, 128, 64, 32]
     base = cil.cil_homogeneous_state(w["model"], w["params"])
