@@ -313,6 +313,11 @@ def main():
                 "solve_steps": solve_steps, "polish_solve_steps": fp64_steps,
                 "polish": "FP64 steps" if args.polish == 1 else "refinement form (FP64 state, FP32 correction steps)",
                 "peak_note": "weighted by the FP32 (157.3) and FP64 (78.6 TFLOP/s) steps of the launch"}
+        # the launch lasts as long as its slowest solve: mean over maximum
+        # steps per solve is the fraction a balanced batch would reach
+        st = rep["steps_taken"]
+        roof["tail_ceiling"] = round(float(st.mean()) / float(st.max()), 4)
+        roof["frac_over_tail_ceiling"] = round(roof["frac"] / roof["tail_ceiling"], 4)
     gram = None
     gk = "k_gram_dma" if "k_gram_dma" in prof_stat else "k_gram_bf16x3"
     if gk in prof_stat:
