@@ -26,21 +26,89 @@
 namespace cil {
 
 // DPP controls.  quad_perm: lane q reads lane q ^ 1, q ^ 2, q ^ 3 of its quad;
-// row_half_mirror: lane i reads lane 7 - i of its group of eight.
+// row_half_mirror: lane i reads lane 7 - i of its group of eight.  Every
+// source lane of these patterns exists, so bound_ctrl (zero for a missing
+// source) never acts; it is set because it lets the compiler fold a move into
+// the VOP2 instruction that consumes it (v_add_f32_dpp and the like).
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_XOR3 = 0x1B, DPP_HALF_MIRROR = 0x141;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v)
 {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v)
 {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
+
+// v[k] += c * (v[k] of the quad partner CTRL selects), for every k: a
+// radix-2 stage across the quad with a lane sign c.  FP32: one
+// v_fmac_f32_dpp per value, which the compiler does not form from a move and
+// a multiply-add by itself, all in one asm block behind one s_nop: a DPP read
+// of a VGPR needs two wait states after a VALU write of it, the hazard check
+// does not look inside asm, and within the block every read is of a value
+// written before it.  FP64: a move and a multiply-add per value.  Either way
+// one rounding of v + c partner, as the two-instruction form.
+#define CIL_QP1 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+#define CIL_QP2 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+#define CIL_QF(i, c, qp) "v_fmac_f32_dpp %" #i ", %" #i ", %" #c " " qp
+#define CIL_QF4(a, b, d, e, c, qp) CIL_QF(a, c, qp) CIL_QF(b, c, qp) CIL_QF(d, c, qp) CIL_QF(e, c, qp)
+
+template <int QP, int P>
+__device__ __forceinline__ void quad_fmac_all_f32(float (&v)[P], float c)
+{
+    static_assert(QP == 1 || QP == 2, "quad_fmac_all: xor-1 or xor-2 partner");
+    if constexpr (P == 4) {
+        if constexpr (QP == 1)
+            asm("s_nop 1\n\t" CIL_QF4(0, 1, 2, 3, 4, CIL_QP1) : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : "v"(c));
+        else
+            asm("s_nop 1\n\t" CIL_QF4(0, 1, 2, 3, 4, CIL_QP2) : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : "v"(c));
+    } else if constexpr (P == 8) {
+        if constexpr (QP == 1)
+            asm("s_nop 1\n\t" CIL_QF4(0, 1, 2, 3, 8, CIL_QP1) CIL_QF4(4, 5, 6, 7, 8, CIL_QP1)
+                : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+                : "v"(c));
+        else
+            asm("s_nop 1\n\t" CIL_QF4(0, 1, 2, 3, 8, CIL_QP2) CIL_QF4(4, 5, 6, 7, 8, CIL_QP2)
+                : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+                : "v"(c));
+    } else if constexpr (P == 16) {
+        if constexpr (QP == 1)
+            asm("s_nop 1\n\t" CIL_QF4(0, 1, 2, 3, 16, CIL_QP1) CIL_QF4(4, 5, 6, 7, 16, CIL_QP1)
+                    CIL_QF4(8, 9, 10, 11, 16, CIL_QP1) CIL_QF4(12, 13, 14, 15, 16, CIL_QP1)
+                : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+                  "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+                : "v"(c));
+        else
+            asm("s_nop 1\n\t" CIL_QF4(0, 1, 2, 3, 16, CIL_QP2) CIL_QF4(4, 5, 6, 7, 16, CIL_QP2)
+                    CIL_QF4(8, 9, 10, 11, 16, CIL_QP2) CIL_QF4(12, 13, 14, 15, 16, CIL_QP2)
+                : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+                  "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+                : "v"(c));
+    } else {
+        static_assert(P == 4 || P == 8 || P == 16, "quad_fmac_all: P = 4, 8 or 16");
+    }
+}
+
+template <int QP, typename T, int P>
+__device__ __forceinline__ void quad_fmac_all(T (&v)[P], T c)
+{
+    if constexpr (sizeof(T) == 4) {
+        quad_fmac_all_f32<QP, P>(v, c);
+    } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = fma(dpp_mov<QP == 1 ? DPP_XOR1 : DPP_XOR2>(v[k]), c, v[k]);
+    }
+}
+
+#undef CIL_QF4
+#undef CIL_QF
+#undef CIL_QP2
+#undef CIL_QP1
 
 template <typename T, int N>
 struct QuadLine {
@@ -52,7 +120,7 @@ struct QuadLine {
     // Per-lane constants, computed once per kernel.
     struct Lane {
         int q, k2;
-        T tw_r[P], tw_i[P];   // W_M^(q k1) = exp(-2 pi i q k1 / M)
+        T tw_r[P], tw_i[P];   // rho W_M^(q k1), W_M^(q k1) = exp(-2 pi i q k1 / M), for k1 >= 1
         T al_r, al_i;         // exp(-2 pi i P k2 / N)
         T be_r, be_i;         // exp(-i pi P k2 / (2N))
     };
@@ -65,12 +133,12 @@ struct QuadLine {
         L.k2 = (q >> 1) + 2 * (q & 1);
         static_for<0, P>([&](auto Ki) {
             constexpr int k1 = Ki;
-            // W_M^(q k1) for q = 0..3
+            // rho W_M^(q k1) for q = 0..3, rho = rho(q) of the cross-lane stage
             constexpr T r1 = (T)ce_cospi(2 * k1, M), i1 = (T)(-ce_sinpi(2 * k1, M));
             constexpr T r2 = (T)ce_cospi(4 * k1, M), i2 = (T)(-ce_sinpi(4 * k1, M));
             constexpr T r3 = (T)ce_cospi(6 * k1, M), i3 = (T)(-ce_sinpi(6 * k1, M));
-            L.tw_r[k1] = q == 0 ? T(1) : (q == 1 ? r1 : (q == 2 ? r2 : r3));
-            L.tw_i[k1] = q == 0 ? T(0) : (q == 1 ? i1 : (q == 2 ? i2 : i3));
+            L.tw_r[k1] = q == 0 ? T(1) : (q == 1 ? -r1 : (q == 2 ? -r2 : r3));
+            L.tw_i[k1] = q == 0 ? T(0) : (q == 1 ? -i1 : (q == 2 ? -i2 : i3));
         });
         // alpha = exp(-2 pi i P k2 / N), beta = exp(-i pi P k2 / 2N) for k2 = 0..3
         const int k2 = L.k2;
@@ -131,38 +199,50 @@ struct QuadLine {
         });
     }
 
-    // 4-point DFT across the quad.  Forward: lane q enters with Y_q, leaves
-    // with the output index k2(q).  Backward: lane q enters holding index
-    // k2(q) and leaves with output index q.
+    // 4-point DFT across the quad.  Forward: lane q enters with rho(q) Y_q and
+    // leaves with the output index k2(q).  Backward: lane q enters holding
+    // index k2(q) and leaves with rho(q) times output index q.  rho = +1, -1,
+    // -1, +1 on q = 0..3 is the sign that lets every radix-2 stage be
+    // own + c(q) partner (one quad_fmac: the lane's own value with coefficient
+    // 1, the partner's with a lane sign), and it is folded into the lane
+    // twiddles around the stage (and applied to k1 = 0, which has none).
+    // Forward: stage 1 (partner q ^ 2) c = -1, -1, +1, +1; lane 3 times -i;
+    // stage 2 (partner q ^ 1) c = -1, +1, -1, +1.  Backward: stage 1 (q ^ 1)
+    // c = +1, -1, +1, -1; lane 3 times +i; stage 2 (q ^ 2) c = +1, +1, -1, -1.
+    // Sign flips are exact, so the values equal those of the plain
+    // sum-and-difference butterflies bit for bit.
+    __device__ __forceinline__ static T rho(const Lane &L) { return ((L.q >> 1) ^ (L.q & 1)) ? T(-1) : T(1); }
     __device__ __forceinline__ static void cross_fwd(const Lane &L, T (&re)[P], T (&im)[P])
     {
-        const T s1 = (L.q >> 1) ? T(-1) : T(1);
-        const T s2 = (L.q & 1) ? T(-1) : T(1);
+        const T c1 = (L.q >> 1) ? T(1) : T(-1);
+        const T c2 = (L.q & 1) ? T(1) : T(-1);
         const bool rot = (L.q == 3);
+        quad_fmac_all<2>(re, c1);
+        quad_fmac_all<2>(im, c1);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const T pr = dpp_mov<DPP_XOR2>(re[k]), pi = dpp_mov<DPP_XOR2>(im[k]);
-            T ar = pr + s1 * re[k], ai = pi + s1 * im[k];
-            const T tr = rot ? ai : ar, ti = rot ? -ar : ai;      // times -i on lane 3
-            const T qr = dpp_mov<DPP_XOR1>(tr), qi = dpp_mov<DPP_XOR1>(ti);
-            re[k] = qr + s2 * tr;
-            im[k] = qi + s2 * ti;
+        for (int k = 0; k < P; ++k) {                             // times -i on lane 3
+            const T ar = re[k], ai = im[k];
+            re[k] = rot ? ai : ar;
+            im[k] = rot ? -ar : ai;
         }
+        quad_fmac_all<1>(re, c2);
+        quad_fmac_all<1>(im, c2);
     }
     __device__ __forceinline__ static void cross_bwd(const Lane &L, T (&re)[P], T (&im)[P])
     {
-        const T s1 = (L.q & 1) ? T(-1) : T(1);
-        const T s2 = (L.q >> 1) ? T(-1) : T(1);
+        const T c1 = (L.q & 1) ? T(-1) : T(1);
+        const T c2 = (L.q >> 1) ? T(-1) : T(1);
         const bool rot = (L.q == 3);
+        quad_fmac_all<1>(re, c1);
+        quad_fmac_all<1>(im, c1);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const T pr = dpp_mov<DPP_XOR1>(re[k]), pi = dpp_mov<DPP_XOR1>(im[k]);
-            T cr = pr + s1 * re[k], ci = pi + s1 * im[k];
-            const T tr = rot ? -ci : cr, ti = rot ? cr : ci;      // times +i on lane 3
-            const T qr = dpp_mov<DPP_XOR2>(tr), qi = dpp_mov<DPP_XOR2>(ti);
-            re[k] = qr + s2 * tr;
-            im[k] = qi + s2 * ti;
+        for (int k = 0; k < P; ++k) {                             // times +i on lane 3
+            const T cr = re[k], ci = im[k];
+            re[k] = rot ? -ci : cr;
+            im[k] = rot ? cr : ci;
         }
+        quad_fmac_all<2>(re, c2);
+        quad_fmac_all<2>(im, c2);
     }
 
     // Forward, from the lane's 2P line values (bit-reversed m1 order: zr[bitrev(m1)]
@@ -173,6 +253,8 @@ struct QuadLine {
                                                         T (&xb)[P], T &xm)
     {
         fftP<-1>(zr, zi);
+        zr[0] *= rho(L);
+        zi[0] *= rho(L);
 #pragma unroll
         for (int k1 = 1; k1 < P; ++k1) {
             const T r = zr[k1] * L.tw_r[k1] - zi[k1] * L.tw_i[k1];
@@ -225,6 +307,8 @@ struct QuadLine {
                                                      T &xm)
     {
         fftP<-1>(zr, zi);
+        zr[0] *= rho(L);
+        zi[0] *= rho(L);
 #pragma unroll
         for (int k1 = 1; k1 < P; ++k1) {
             const T r = zr[k1] * L.tw_r[k1] - zi[k1] * L.tw_i[k1];
@@ -349,6 +433,8 @@ struct QuadLine {
     __device__ __forceinline__ static void inverse_core(const Lane &L, T (&zr)[P], T (&zi)[P])
     {
         cross_bwd(L, zr, zi);
+        zr[0] *= rho(L);
+        zi[0] *= rho(L);
         static_for<1, P>([&](auto Ki) {
             constexpr int k1 = Ki;
             constexpr int p = bitrev(k1, LOGP);

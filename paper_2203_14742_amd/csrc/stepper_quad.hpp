@@ -105,54 +105,56 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
     const auto u64r = make_rsrc(RF ? u64 + s.off : nullptr, RF ? 2 * NN * sizeof(double) : 0);
     const unsigned du0 = (sp0 * NN + g * N + lo) * sizeof(double), du1 = (sp0 * NN + g * N + hi0) * sizeof(double);
     auto rebase = [&](bool first) __attribute__((always_inline)) {
-        double *const sd = reinterpret_cast<double *>(sm);
-        __syncthreads();                                   // the LDS's last readers are done
-        static_for<0, P>([&](auto Mi) {
-            constexpr int m1 = Mi;
-            static_for<0, 2>([&](auto Hc) {
-                constexpr int h = Hc;
-                const int pos = (m1 < P / 2 ? lo : hi0) + line_off(Mi, Hc);
-                const unsigned off = (m1 < P / 2 ? du0 : du1) + line_off(Mi, Hc) * sizeof(double);
-#pragma unroll
-                for (int c = 0; c < SPL; ++c) {
-                    double U;
-                    if constexpr (h == 0) U = (double)ur[c][m1];
-                    else U = (double)ui[c][m1];
-                    if (!first) U += buf_load<double>(u64r, off, c * NN * sizeof(double));
-                    buf_store<double>(U, u64r, off, c * NN * sizeof(double));
-                    sd[(sp0 + c) * SP + g * LD + pos] = U;
-                    if constexpr (h == 0) ur[c][m1] = T(0);
-                    else ui[c][m1] = T(0);
-                }
+        if constexpr (RF) {
+            double *const sd = reinterpret_cast<double *>(sm);
+            __syncthreads();                                   // the LDS's last readers are done
+            static_for<0, P>([&](auto Mi) {
+                constexpr int m1 = Mi;
+                static_for<0, 2>([&](auto Hc) {
+                    constexpr int h = Hc;
+                    const int pos = (m1 < P / 2 ? lo : hi0) + line_off(Mi, Hc);
+                    const unsigned off = (m1 < P / 2 ? du0 : du1) + line_off(Mi, Hc) * sizeof(double);
+    #pragma unroll
+                    for (int c = 0; c < SPL; ++c) {
+                        double U;
+                        if constexpr (h == 0) U = (double)ur[c][m1];
+                        else U = (double)ui[c][m1];
+                        if (!first) U += buf_load<double>(u64r, off, c * NN * sizeof(double));
+                        buf_store<double>(U, u64r, off, c * NN * sizeof(double));
+                        sd[(sp0 + c) * SP + g * LD + pos] = U;
+                        if constexpr (h == 0) ur[c][m1] = T(0);
+                        else ui[c][m1] = T(0);
+                    }
+                });
             });
-        });
-        __syncthreads();
-        const double pd[4] = {s.p[0], s.p[1], s.p[2], s.p[3]};
-        const int gu = g > 0 ? g - 1 : 0, gd = g < N - 1 ? g + 1 : N - 1;
-        static_for<0, P>([&](auto Mi) {
-            constexpr int m1 = Mi;
-            static_for<0, 2>([&](auto Hc) {
-                constexpr int h = Hc;
-                const int pos = (m1 < P / 2 ? lo : hi0) + line_off(Mi, Hc);
-                const int pl = pos > 0 ? pos - 1 : 0, pr = pos < N - 1 ? pos + 1 : N - 1;
-#pragma unroll
-                for (int c = 0; c < SPL; ++c) {
-                    const int cs = sp0 + c;
-                    const double *const fld = sd + cs * SP;
-                    const double U0 = fld[g * LD + pos];
-                    const double Uo = sd[(1 - cs) * SP + g * LD + pos];
-                    const double lap =
-                        (fld[g * LD + pl] + fld[g * LD + pr] + fld[gu * LD + pos] + fld[gd * LD + pos] - 4.0 * U0) *
-                        s.inv_h2;
-                    double f, gg;
-                    kinetics<MD::value>(pd, cs ? Uo : U0, cs ? U0 : Uo, f, gg);
-                    r32[c][h][m1] = (T)((cs ? gg : f) + (cs ? s.nu[1] : s.nu[0]) * lap);
-                    u32[c][h][m1] = (T)U0;
-                    if constexpr (SPL == 1) o32[h][m1] = (T)Uo;
-                }
+            __syncthreads();
+            const double pd[4] = {s.p[0], s.p[1], s.p[2], s.p[3]};
+            const int gu = g > 0 ? g - 1 : 0, gd = g < N - 1 ? g + 1 : N - 1;
+            static_for<0, P>([&](auto Mi) {
+                constexpr int m1 = Mi;
+                static_for<0, 2>([&](auto Hc) {
+                    constexpr int h = Hc;
+                    const int pos = (m1 < P / 2 ? lo : hi0) + line_off(Mi, Hc);
+                    const int pl = pos > 0 ? pos - 1 : 0, pr = pos < N - 1 ? pos + 1 : N - 1;
+    #pragma unroll
+                    for (int c = 0; c < SPL; ++c) {
+                        const int cs = sp0 + c;
+                        const double *const fld = sd + cs * SP;
+                        const double U0 = fld[g * LD + pos];
+                        const double Uo = sd[(1 - cs) * SP + g * LD + pos];
+                        const double lap =
+                            (fld[g * LD + pl] + fld[g * LD + pr] + fld[gu * LD + pos] + fld[gd * LD + pos] - 4.0 * U0) *
+                            s.inv_h2;
+                        double f, gg;
+                        kinetics<MD::value>(pd, cs ? Uo : U0, cs ? U0 : Uo, f, gg);
+                        r32[c][h][m1] = (T)((cs ? gg : f) + (cs ? s.nu[1] : s.nu[0]) * lap);
+                        u32[c][h][m1] = (T)U0;
+                        if constexpr (SPL == 1) o32[h][m1] = (T)Uo;
+                    }
+                });
             });
-        });
-        __syncthreads();                                   // the row forward writes the LDS next
+            __syncthreads();                                   // the row forward writes the LDS next
+        }
     };
     const long long start = step;
     long long last_rebase = step;
