@@ -429,9 +429,16 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   FP32 floor inside the same persistent launch (0, default); 1 = the same
  *   kernel runs twice, the FP32 phase of the whole batch, then the polish of
  *   the solves at their floor.  Both give identical results.  (Other sides
- *   always polish in FP64 steps in a launch of their own.) */
+ *   always polish in FP64 steps in a launch of their own.)
+ * CIL_OPT_SYNC_SPIN_US (value 0..1e7, default 200000): where a call waits
+ *   for its stream (to read back results), it polls the stream's progress for
+ *   up to this many microseconds before a blocking wait; 0 = block at once.
+ *   Polling keeps a host core busy but avoids the wake-up delay of a blocking
+ *   wait, which is about as long as the statistic's short launches.  Results
+ *   are unchanged.  CIL_EINVAL outside the range. */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
-       CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6, CIL_OPT_POLISH_SEPARATE = 7 };
+       CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6, CIL_OPT_POLISH_SEPARATE = 7,
+       CIL_OPT_SYNC_SPIN_US = 8 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

@@ -31,6 +31,7 @@ CIL_OPT_GRAM_FLUSH = 4
 CIL_OPT_GRAM_PIPELINE = 5
 CIL_OPT_WAVE_PRIORITY = 6
 CIL_OPT_POLISH_SEPARATE = 7
+CIL_OPT_SYNC_SPIN_US = 8
 CIL_QUAD_SHAPES = 4
 
 

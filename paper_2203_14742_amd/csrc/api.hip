@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -142,6 +144,48 @@ int host_stage(int slot, size_t bytes, void **ptr)
         w.bytes = want;
     }
     *ptr = w.ptr;
+    return CIL_OK;
+}
+
+// Host waits.  A blocking wait puts the host thread to sleep until the
+// device signals; the statistic's short launches are waited on for tens of
+// microseconds at a time, about what the wake-up costs.  So the stream's work
+// is recorded as an event and polled first, for up to g_spin_us microseconds
+// (CIL_OPT_SYNC_SPIN_US), then waited on blocking.  One event per (thread,
+// device), kept for the thread's life.
+std::atomic<long long> g_spin_us{200000};
+
+int set_sync_spin(int64_t us)
+{
+    if (us < 0 || us > 10000000) return set_error(CIL_EINVAL, "sync spin %lld us out of range [0, 1e7]", (long long)us);
+    g_spin_us.store(us);
+    return CIL_OK;
+}
+
+int stream_wait(hipStream_t st)
+{
+    const long long budget = g_spin_us.load();
+    if (budget <= 0) {
+        CIL_HIP(hipStreamSynchronize(st));
+        return CIL_OK;
+    }
+    int dev;
+    CIL_TRY(current_device(&dev));
+    thread_local std::map<int, hipEvent_t> evs;
+    hipEvent_t &ev = evs[dev];
+    if (!ev) CIL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    CIL_HIP(hipEventRecord(ev, st));
+    const auto t0 = std::chrono::steady_clock::now();
+    while (true) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return CIL_OK;
+        if (e != hipErrorNotReady)
+            return set_error(CIL_EDEVICE, "hipEventQuery failed: %s", hipGetErrorString(e));
+        const long long us =
+            std::chrono::duration_cast<std::chrono::microseconds>(std::chrono::steady_clock::now() - t0).count();
+        if (us >= budget) break;
+    }
+    CIL_HIP(hipEventSynchronize(ev));
     return CIL_OK;
 }
 
@@ -721,6 +765,7 @@ int cil_set_option(int32_t option, int64_t value)
     if (option == CIL_OPT_GRAM_PIPELINE) return set_gram_pipeline(value);
     if (option == CIL_OPT_WAVE_PRIORITY) return set_wave_priority(value);
     if (option == CIL_OPT_POLISH_SEPARATE) return set_polish_separate(value);
+    if (option == CIL_OPT_SYNC_SPIN_US) return set_sync_spin(value);
     return set_error(CIL_EINVAL, "unknown option %d", option);
 }
 

@@ -46,9 +46,11 @@ int ws_get(int slot, size_t bytes, void **ptr);
 // Pinned host buffers for the small copies between the host and the device
 // inside a call (so they run asynchronously), grow-only, one per (device,
 // slot); freed by cil_shutdown().
-enum HostSlot { HS_DIST = 0, HS_BOOT, HS_NUM_SLOTS };
+enum HostSlot { HS_DIST = 0, HS_BOOT, HS_STEP, HS_NUM_SLOTS };
 int host_stage(int slot, size_t bytes, void **ptr);
 int current_device(int *dev);
+// Wait for everything issued to `st` (polls, then blocks; CIL_OPT_SYNC_SPIN_US).
+int stream_wait(hipStream_t st);
 int release_all();
 // Zero device memory with a kernel (keeps memset nodes out of captured graphs).
 int fill_zero(void *p, size_t bytes, hipStream_t st);

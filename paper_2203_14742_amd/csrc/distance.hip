@@ -649,7 +649,7 @@ int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long lo
     unsigned long long *cnt = (unsigned long long *)(hs + 4096);   // listed pairs, exact fallbacks
     CIL_HIP(hipMemcpyAsync(hh, s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
     CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     const unsigned long long nre = cnt[0];
     if ((long long)nre > s.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
     if ((long long)nre > guess) {                       // the rest of a long list
@@ -657,7 +657,7 @@ int bins_from_approx(const T *A, long long nA, const T *B, long long nB, long lo
         CIL_TRY(run_canonical(A, B, dim, co, (long long)nre - guess, st));
         CIL_HIP(hipMemcpyAsync(hh, s.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
         CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        CIL_HIP(hipStreamSynchronize(st));
+        CIL_TRY(stream_wait(st));
     }
     hist_host.assign(hh, hh + M + 1);
     t_pairs = nA * nB;
@@ -720,7 +720,7 @@ int range_from_approx(const T *A, long long nA, const T *B, long long nB, long l
     unsigned long long *cnt = (unsigned long long *)(hs + 64);
     CIL_HIP(hipMemcpyAsync(hcp, cand, sizeof(double) * guess, hipMemcpyDeviceToHost, st));
     CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     std::vector<double> hc(hcp, hcp + guess);
     if (cnt[4]) return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
     const long long nc = (long long)cnt[0];
@@ -734,7 +734,7 @@ int range_from_approx(const T *A, long long nA, const T *B, long long nB, long l
         CIL_HIP(hipMemcpyAsync(hc.data() + guess, cand + guess, sizeof(double) * (nc - guess), hipMemcpyDeviceToHost,
                                st));
         CIL_HIP(hipMemcpyAsync(cnt, s.nlist, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        CIL_HIP(hipStreamSynchronize(st));
+        CIL_TRY(stream_wait(st));
     }
     double lo = INFINITY, hi = 0.0;
     for (long long k = 0; k < nc; ++k) {
@@ -852,7 +852,7 @@ int canonical_pairs_impl(const T *A, long long nA, const T *B, long long nB, lon
     CIL_TRY(run_canonical(A, B, dim, co, np, st));
     unsigned long long flags[2];
     CIL_HIP(hipMemcpyAsync(flags, s.nlist, sizeof(flags), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     t_pairs = np;
     t_rechecked = np;
     t_exact = (long long)flags[1];

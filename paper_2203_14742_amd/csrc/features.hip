@@ -307,7 +307,7 @@ int value_range_impl(const double *V, long long n, double *vmin, double *vmax, h
     CIL_TRY(check_launch("k_value_range"));
     unsigned long long h[2];
     CIL_HIP(hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     double lo, hi;
     std::memcpy(&lo, &h[0], 8);
     std::memcpy(&hi, &h[1], 8);
@@ -332,7 +332,7 @@ int bin_values_impl(const double *V, long long n, const double *radii, int M, ui
     }
     std::vector<unsigned long long> h(M + 1);
     CIL_HIP(hipMemcpyAsync(h.data(), hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     unsigned long long tail = 0;
     for (int m = M; m >= 1; --m) {
         tail += h[m];

@@ -397,7 +397,7 @@ static int bootstrap_run(const uint8_t *bins, long long nA, long long nB, int M,
     if (!mem.base) CIL_TRY(host_stage(HS_BOOT, 2 * sizeof(int), (void **)&hbad));
     hbad[0] = hbad[1] = 0;
     CIL_HIP(hipMemcpyAsync(hbad, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     if (hbad[0] || hbad[1]) return set_error(CIL_EINVAL, "bootstrap index out of range");
     return CIL_OK;
 }

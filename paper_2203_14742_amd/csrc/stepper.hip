@@ -875,6 +875,32 @@ int make_tables(SimCtx &c, int n, const std::vector<int> &ids, std::vector<DevSo
     return check_launch("k_make_tables");
 }
 
+// Per-solve results of fused launches (steps, last residual, status and, for
+// mixed launches, the switch step) back to the host: pinned staging, so the
+// copies are queued without blocking, and one wait.
+struct HostResults {
+    const long long *steps;
+    const double *res;
+    const int *stat;
+    const long long *sw;
+};
+int fetch_results(SimCtx &c, int B, const long long *dsteps, const double *dres, const int *dstat,
+                  const long long *dsw, HostResults *out)
+{
+    char *hb;
+    const size_t b8 = sizeof(long long) * (size_t)B;
+    CIL_TRY(host_stage(HS_STEP, 3 * b8 + sizeof(int) * (size_t)B, (void **)&hb));
+    out->steps = (const long long *)hb;
+    out->res = (const double *)(hb + b8);
+    out->sw = dsw ? (const long long *)(hb + 2 * b8) : nullptr;
+    out->stat = (const int *)(hb + 3 * b8);
+    CIL_HIP(hipMemcpyAsync(hb, dsteps, b8, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hb + b8, dres, b8, hipMemcpyDeviceToHost, c.st));
+    CIL_HIP(hipMemcpyAsync(hb + 3 * b8, dstat, sizeof(int) * (size_t)B, hipMemcpyDeviceToHost, c.st));
+    if (dsw) CIL_HIP(hipMemcpyAsync(hb + 2 * b8, dsw, b8, hipMemcpyDeviceToHost, c.st));
+    return stream_wait(c.st);
+}
+
 // Fused solves, all sides in one go: every workgroup runs its solve from
 // steps[b] until its stop rule fires.  `dsteps/dres/dstat` are per-solve
 // device arrays; the host copies are refreshed after the launches.
@@ -967,23 +993,14 @@ int run_fused(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vector
             CIL_HIP(hipStreamWaitEvent(c.st, aux->ev[1 + gi], 0));
         }
     }
-    std::vector<double> hres(B);
-    std::vector<int> hstat(B);
-    CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
-    std::vector<long long> hsw;
-    if (mx) {
-        hsw.resize(B);
-        CIL_HIP(hipMemcpyAsync(hsw.data(), mx->sw, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
-    }
-    CIL_HIP(hipStreamSynchronize(c.st));
+    HostResults h;
+    CIL_TRY(fetch_results(c, B, dsteps, dres, dstat, mx ? mx->sw : nullptr, &h));
     for (size_t gi = 0; gi < groups.size(); ++gi)
         for (int b : groups[gi]->second) {
-            c.steps[b] = hsteps[b];
-            c.fres[b] = hres[b];
-            c.status[b] = hstat[b];
-            if (mixed[gi]) c.sw[b] = hsw[b];
+            c.steps[b] = h.steps[b];
+            c.fres[b] = h.res[b];
+            c.status[b] = h.stat[b];
+            if (mixed[gi]) c.sw[b] = h.sw[b];
         }
     return CIL_OK;
 }
@@ -1025,17 +1042,13 @@ int run_phase2(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::vecto
         if (rc) return set_error(rc, "no mixed-precision kernel for n = %d", kv.first);
         CIL_TRY(check_launch("k_fused_q_mixed"));
     }
-    std::vector<double> hres(B);
-    std::vector<int> hstat(B);
-    CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipStreamSynchronize(c.st));
+    HostResults h;
+    CIL_TRY(fetch_results(c, B, dsteps, dres, dstat, nullptr, &h));
     for (auto &kv : byn)
         for (int b : kv.second) {
-            c.steps[b] = hsteps[b];
-            c.fres[b] = hres[b];
-            c.status[b] = hstat[b];
+            c.steps[b] = h.steps[b];
+            c.fres[b] = h.res[b];
+            c.status[b] = h.stat[b];
         }
     return CIL_OK;
 }
@@ -1085,17 +1098,13 @@ int run_fused_sbdf2(SimCtx &c, const std::map<int, std::vector<int>> &byn, std::
         prof_end(pm, c.st);
         CIL_TRY(check_launch(name));
     }
-    std::vector<double> hres(B);
-    std::vector<int> hstat(B);
-    CIL_HIP(hipMemcpyAsync(hsteps.data(), dsteps, sizeof(long long) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipMemcpyAsync(hstat.data(), dstat, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
-    CIL_HIP(hipStreamSynchronize(c.st));
+    HostResults h;
+    CIL_TRY(fetch_results(c, B, dsteps, dres, dstat, nullptr, &h));
     for (auto &kv : byn)
         for (int b : kv.second) {
-            c.steps[b] = hsteps[b];
-            c.fres[b] = hres[b];
-            c.status[b] = hstat[b];
+            c.steps[b] = h.steps[b];
+            c.fres[b] = h.res[b];
+            c.status[b] = h.stat[b];
         }
     return CIL_OK;
 }
@@ -1354,7 +1363,7 @@ int simulate_impl(cil_model model, cil_precision prec, const cil_problem *probs,
                            (const DevSolve *)dS64, (const DevSolve *)dS, dprom, (const double *)state64, (float *)state);
         CIL_TRY(check_launch("k_convert_solves"));
     }
-    CIL_HIP(hipStreamSynchronize(st));
+    CIL_TRY(stream_wait(st));
     cb.done = true;
 
     int rc = CIL_OK;

@@ -134,6 +134,10 @@ def test_statistic_argument_validation():
     assert L.cil_gaussian_loglik(None, 1, 10, 65, None, None, None, None, None, None) == cil.CIL_EINVAL
     assert L.cil_bootstrap_features(None, 4, 4, 0, None, 1, None, 1, 1, None, None, None) == cil.CIL_EINVAL
     assert L.cil_set_option(99, 0) == cil.CIL_EINVAL
+    for bad in (-1, 10000001):
+        assert L.cil_set_option(cil.CIL_OPT_SYNC_SPIN_US, bad) == cil.CIL_EINVAL
+    for good in (0, 200000):
+        assert L.cil_set_option(cil.CIL_OPT_SYNC_SPIN_US, good) == cil.CIL_OK
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

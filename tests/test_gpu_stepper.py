@@ -309,6 +309,31 @@ def test_wave_priority_changes_timing_only(cil):
             cil.cil_set_option(cil.CIL_OPT_WAVE_PRIORITY, bad)
 
 
+def test_polling_waits_change_nothing(cil, oracle_mod):
+    """Host waits that poll (CIL_OPT_SYNC_SPIN_US, default) or block at once
+    (0): the same stepping reports and the same adaptive bins and counts."""
+    w = cs.WORKLOADS["gm_source64_stationary"]
+    base = cil.cil_homogeneous_state(w["model"], w["params"])
+    ics = cs.initial_conditions(base, w["n"], 24, seed=43, law=w["ic_law"])
+    probs = cil.make_problems(w["n"], w["L"], w["nu"], w["params"], count=24)
+    out = []
+    try:
+        for spin in (0, 200000):
+            cil.cil_set_option(cil.CIL_OPT_SYNC_SPIN_US, spin)
+            st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+            rep = cil.cil_simulate_patterns(w["model"], st, probs, w["dt"], w["max_steps"], tol=w["tol"],
+                                            check_every=w["check_every"], polish=2)
+            P = st.reshape(24, -1)
+            lo, hi, radii, bins, counts = cil.cil_pair_bins_adaptive(P[:12], P[12:], 8)
+            out.append((st, rep, (lo, hi), bins, counts))
+    finally:
+        cil.cil_set_option(cil.CIL_OPT_SYNC_SPIN_US, 200000)
+    (a, ra, ga, ba, ca), (b, rb, gb, bb, cb) = out
+    assert torch.equal(a, b) and torch.equal(ba, bb) and ga == gb and np.array_equal(ca, cb)
+    for k in ("steps_taken", "steps_fp64", "final_resid", "status"):
+        assert np.array_equal(ra[k], rb[k]), k
+
+
 def _gm_batch(cil, n, count, seed, L):
     w = cs.WORKLOADS["gm_source64_stationary"]
     base = cil.cil_homogeneous_state(w["model"], w["params"])
