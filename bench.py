@@ -252,13 +252,15 @@ def main():
         cil_ms = 0.0
         reps = []
         each.clear()
+        stat_each.clear()
         for _ in range(steps):
             t1 = time.perf_counter()
             rep, counts, e0, e1, out = one_step(state, ics, path, stat_fp32)
             reps.append(rep)
             torch.cuda.synchronize()
             each.append(time.perf_counter() - t1)
-            cil_ms += e0.elapsed_time(e1)
+            stat_each.append(e0.elapsed_time(e1))
+            cil_ms += stat_each[-1]
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = {}
@@ -269,13 +271,16 @@ def main():
         return el, cil_ms / 1e3, reps, counts, out, prof
 
     each = []
+    stat_each = []
 
-    # batched path: persistent fused FP32 stepping with the FP64 polish from
-    # each solve's FP32 floor to the tolerance in the same launch; statistic on
-    # the FP32 patterns
     state32 = torch.empty_like(ics32)
+    # batched path: persistent fused FP32 stepping, each solve continuing
+    # from its FP32 floor to the tolerance in the same launch; statistic on
+    # the FP32 patterns
     el, cil_s, reps, counts, out, prof = timed(state32, ics32, cil.CIL_PATH_AUTO, True, args.steps, args.warmup,
                                                profile=2)
+    head_each = [round(1e3 * t, 3) for t in each]
+    head_stat_each = [round(t, 4) for t in stat_each]
     # the statistic's kernels timed in a pass of their own after the timed
     # region (events around its short launches would slow the timed one)
     _, _, _, _, _, prof_stat = timed(state32, ics32, cil.CIL_PATH_AUTO, True, 2, 0, profile=1)
@@ -363,11 +368,14 @@ def main():
         "config": {"workload": WORKLOAD, "model": "gierer_meinhardt_source", "solves": B, "grid": n,
                    "dt": w["dt"], "tol": w["tol"], "radii": M, "bootstrap": n_boot,
                    "pairs_per_step": pairs,
-                   "stepping": "fp32 fused persistent (quad-lane DCT), fp64 from each solve's fp32 floor to tol "
-                               "in the same launch, fp64 residual",
+                   "stepping": "fp32 fused persistent (quad-lane DCT); from each solve's fp32 floor to tol in the "
+                               "same launch " + ("fp64 steps" if args.polish == 1 else
+                                                 "in refinement form (fp64 state, fp32 correction steps)") +
+                               "; fp64 residual",
                    "statistic": "fp32 patterns, split-bf16x3 MFMA Gram + canonical re-check",
                    "parallelism": "none (1 GPU)"},
         "pairs_per_s": round(pairs_per_s, 1) if pairs_per_s else None,
+        "ms_per_step_each": head_each, "statistic_ms_each": head_stat_each,
         "solve_steps": solve_steps // K, "polish_solve_steps": fp64_steps // K,
         "max_solve_steps": int(rep["steps_taken"].max()), "all_converged": status_ok,
         "roofline": roof, "roofline_gram": gram, "kernels": kernels,
