@@ -46,6 +46,19 @@ class Problem(ctypes.Structure):
                 ("nu", ctypes.c_double * 2), ("p", ctypes.c_double * 4)]
 
 
+# numpy view of a Problem array (same field order, sizes and offsets)
+_PROBLEM_DTYPE = np.dtype([("n", np.int32), ("reserved", np.int32), ("L", np.float64), ("nu", np.float64, 2),
+                           ("p", np.float64, 4)])
+
+
+def _state_sizes(problems, B: int) -> np.ndarray:
+    """Elements of each solve's state, 2 n^2 (a view of the array, no loop over ctypes fields)."""
+    if B == 0:
+        return np.zeros(0, dtype=np.int64)
+    n = np.frombuffer(problems, dtype=_PROBLEM_DTYPE, count=B)["n"].astype(np.int64)
+    return 2 * n * n
+
+
 class Stepping(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("max_steps", ctypes.c_int64), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("path", ctypes.c_int32), ("polish", ctypes.c_int32),
@@ -183,16 +196,19 @@ def make_problems(n, L, nu, p, count: int | None = None):
     nu_arr = np.atleast_2d(np.asarray(nu, dtype=np.float64))
     p_arr = np.atleast_2d(np.asarray(p, dtype=np.float64))
     B = count or max(n_arr.size, L_arr.size, nu_arr.shape[0], p_arr.shape[0])
+    if nu_arr.shape[1] != 2:
+        raise ValueError("nu needs two diffusion coefficients per solve")
     probs = (Problem * B)()
-    for b in range(B):
-        pr = probs[b]
-        pr.n = int(n_arr[b % n_arr.size])
-        pr.L = float(L_arr[b % L_arr.size])
-        nu_b = nu_arr[b % nu_arr.shape[0]]
-        pr.nu[0], pr.nu[1] = float(nu_b[0]), float(nu_b[1])
-        p_b = p_arr[b % p_arr.shape[0]]
-        for k in range(min(4, p_b.size)):
-            pr.p[k] = float(p_b[k])
+    if B == 0:
+        return probs
+    rows = np.arange(B)
+    a = np.zeros(B, dtype=_PROBLEM_DTYPE)
+    a["n"] = n_arr[rows % n_arr.size]
+    a["L"] = L_arr[rows % L_arr.size]
+    a["nu"] = nu_arr[rows % nu_arr.shape[0], :2]
+    k = min(4, p_arr.shape[1])
+    a["p"][:, :k] = p_arr[rows % p_arr.shape[0], :k]
+    ctypes.memmove(probs, a.ctypes.data, a.nbytes)
     return probs
 
 
@@ -214,7 +230,7 @@ def cil_simulate_patterns(model: int, state, problems, dt: float, max_steps: int
                   polish=int(polish), fp32_floor_ulps=int(fp32_floor_ulps))
     reps = (SolveReport * max(B, 1))()
     offs = None
-    sizes = np.array([2 * problems[b].n * problems[b].n for b in range(B)], dtype=np.int64)
+    sizes = _state_sizes(problems, B)
     if offsets is not None:
         offs = _arr(offsets, np.int64)
         need = int((offs + sizes).max()) if B else 0
@@ -246,7 +262,7 @@ class SimPlan:
         self._h = ctypes.c_void_p()
         stp = Stepping(dt=dt, max_steps=int(max_steps), tol=tol, check_every=int(check_every), path=int(path),
                        polish=0, fp32_floor_ulps=int(fp32_floor_ulps))
-        sizes = np.array([2 * problems[b].n * problems[b].n for b in range(self.B)], dtype=np.int64)
+        sizes = _state_sizes(problems, self.B)
         offs = None
         if offsets is not None:
             offs = _arr(offsets, np.int64)
