@@ -406,6 +406,38 @@ def test_refinement_polish(cil, n, L):
     assert np.all(diff[ok] <= bar[ok])
 
 
+@pytest.mark.parametrize("case,n,L,dt", [(FHN, 32, 1.0, 0.01), (GM, 32, 1.0, 0.05), (BZ, 32, 1.0, 0.05),
+                                         (GMS, 32, 60.0, 0.2), (FHN, 64, 1.0, 0.01), (GM, 64, 1.0, 0.05),
+                                         (BZ, 64, 1.0, 0.05), (GMS, 64, 120.0, 0.2)])
+def test_refinement_form_every_model(cil, case, n, L, dt):
+    """The refinement form's reaction change (kinetics_delta, per model) and
+    its FP64 residual, against the FP64-step polish over 200 steps of each
+    model's transient: a floor of 2^20 FP32 units switches every solve at its
+    first evaluation (step 25), so both polishes run steps 25-225 from the
+    same FP32 state.  They agree to FP32 rounding of the motion since the
+    switch (measured up to 1.7e-5 of max|u|, GM source); a wrong or dropped
+    term in the change of the reaction would put them apart by a fair part of
+    that motion (over 1e-2)."""
+    model, p, nu = case
+    base = cil.cil_homogeneous_state(model, p)
+    ics = cs.initial_conditions(base, n, 8, seed=80 + model, law="additive_pos")
+    probs = cil.make_problems(n, L, nu, p, count=8)
+    out = {}
+    for polish in (1, 2):
+        st = torch.tensor(ics, dtype=torch.float32, device="cuda")
+        print("refinement model=%d n=%d polish=%d" % (model, n, polish), flush=True)
+        rep = cil.cil_simulate_patterns(model, st, probs, dt, 225, tol=1e-8, check_every=25, polish=polish,
+                                        fp32_floor_ulps=1 << 20)
+        out[polish] = (st.double().cpu().numpy().reshape(8, -1), rep)
+    (a, ra), (b, rb) = out[1], out[2]
+    for r in (ra, rb):
+        assert np.all(r["steps_fp64"] == 200) and np.all(r["steps_taken"] == 225)
+        assert np.all(r["status"] == cil.CIL_SOLVE_MAXSTEPS)
+    d = (np.abs(a - b).max(axis=1) / np.abs(a).max(axis=1)).max()
+    print("refinement vs FP64-step polish after 200 steps: %.2e of max|u|" % d)
+    assert d <= 1e-4
+
+
 def test_mixed_polish_uneven_sides(cil):
     """Sides 32, 64 (mixed launches) and 128 (FP32 launch + FP64 polish in a
     launch of its own) in one call: identical to the separate polish
