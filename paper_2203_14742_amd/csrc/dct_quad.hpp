@@ -110,11 +110,15 @@ __device__ __forceinline__ void quad_fmac_all(T (&v)[P], T c)
 #undef CIL_QP2
 #undef CIL_QP1
 
-template <typename T, int N>
+// CT: the split step's twiddles w_k, ph_k and e^{i pi/4} ph_k (k = k1 + P k2)
+// are held per lane in registers (6P more), one complex product each; else
+// each is a lane constant times a literal, two products and no register.
+template <typename T, int N, bool CT = false>
 struct QuadLine {
     static constexpr int M = N / 2;
     static constexpr int P = M / 4;
     static constexpr int LOGP = ilog2(P);
+    static constexpr int PC = CT ? P : 1;
     static_assert(P >= 2 && (1 << LOGP) == P, "N must be a power of two >= 16");
 
     // Per-lane constants, computed once per kernel.
@@ -123,6 +127,9 @@ struct QuadLine {
         T tw_r[P], tw_i[P];   // rho W_M^(q k1), W_M^(q k1) = exp(-2 pi i q k1 / M), for k1 >= 1
         T al_r, al_i;         // exp(-2 pi i P k2 / N)
         T be_r, be_i;         // exp(-i pi P k2 / (2N))
+        T w_r[PC], w_i[PC];   // CT: w_k = exp(-2 pi i k / N)
+        T ph_r[PC], ph_i[PC]; // CT: ph_k = exp(-i pi k / 2N)
+        T g_r[PC], g_i[PC];   // CT: e^{i pi/4} ph_k = exp(-i pi (k - N/2) / 2N)
     };
 
     // The lane constants, selected from compile-time values (exact to the
@@ -152,6 +159,26 @@ struct QuadLine {
         L.al_i = k2 == 0 ? T(0) : (k2 == 1 ? a1i : (k2 == 2 ? a2i : a3i));
         L.be_r = k2 == 0 ? T(1) : (k2 == 1 ? b1r : (k2 == 2 ? b2r : b3r));
         L.be_i = k2 == 0 ? T(0) : (k2 == 1 ? b1i : (k2 == 2 ? b2i : b3i));
+        if constexpr (CT) {
+            // each rounded once from its exact value, selected by k2
+            static_for<0, P>([&](auto Ki) {
+                constexpr int k1 = Ki;
+                auto sel = [&](auto f0, auto f1, auto f2, auto f3) { return k2 == 0 ? f0 : (k2 == 1 ? f1 : (k2 == 2 ? f2 : f3)); };
+                L.w_r[k1] = sel((T)ce_cospi(2 * k1, N), (T)ce_cospi(2 * (k1 + P), N), (T)ce_cospi(2 * (k1 + 2 * P), N),
+                                (T)ce_cospi(2 * (k1 + 3 * P), N));
+                L.w_i[k1] = sel((T)-ce_sinpi(2 * k1, N), (T)-ce_sinpi(2 * (k1 + P), N),
+                                (T)-ce_sinpi(2 * (k1 + 2 * P), N), (T)-ce_sinpi(2 * (k1 + 3 * P), N));
+                L.ph_r[k1] = sel((T)ce_cospi(k1, 2 * N), (T)ce_cospi(k1 + P, 2 * N), (T)ce_cospi(k1 + 2 * P, 2 * N),
+                                 (T)ce_cospi(k1 + 3 * P, 2 * N));
+                L.ph_i[k1] = sel((T)-ce_sinpi(k1, 2 * N), (T)-ce_sinpi(k1 + P, 2 * N), (T)-ce_sinpi(k1 + 2 * P, 2 * N),
+                                 (T)-ce_sinpi(k1 + 3 * P, 2 * N));
+                constexpr int h = N / 2;
+                L.g_r[k1] = sel((T)ce_cospi(k1 - h, 2 * N), (T)ce_cospi(k1 + P - h, 2 * N),
+                                (T)ce_cospi(k1 + 2 * P - h, 2 * N), (T)ce_cospi(k1 + 3 * P - h, 2 * N));
+                L.g_i[k1] = sel((T)-ce_sinpi(k1 - h, 2 * N), (T)-ce_sinpi(k1 + P - h, 2 * N),
+                                (T)-ce_sinpi(k1 + 2 * P - h, 2 * N), (T)-ce_sinpi(k1 + 3 * P - h, 2 * N));
+            });
+        }
     }
 
     // index of the input element that lands at position j of the reordering
@@ -285,13 +312,19 @@ struct QuadLine {
             // The lane constant multiplies the data first, then the literal:
             // the same operation count as forming w and ph, and no per-k1 lane
             // twiddles that the compiler could precompute and keep live.
-            constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
-            constexpr T l2r = (T)ce_cospi(k1, 2 * N), l2i = (T)(-ce_sinpi(k1, 2 * N));
-            const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
-            const T Vr = Er + (l1r * ar - l1i * ai), Vi = Ei + (l1r * ai + l1i * ar);
-            const T br = L.be_r * Vr - L.be_i * Vi, bi = L.be_r * Vi + L.be_i * Vr;      // beta V
-            xa[k1] = l2r * br - l2i * bi;
-            xb[k1] = -(l2r * bi + l2i * br);
+            if constexpr (CT) {
+                const T Vr = Er + (L.w_r[k1] * Or - L.w_i[k1] * Oi), Vi = Ei + (L.w_r[k1] * Oi + L.w_i[k1] * Or);
+                xa[k1] = L.ph_r[k1] * Vr - L.ph_i[k1] * Vi;
+                xb[k1] = -(L.ph_r[k1] * Vi + L.ph_i[k1] * Vr);
+            } else {
+                constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
+                constexpr T l2r = (T)ce_cospi(k1, 2 * N), l2i = (T)(-ce_sinpi(k1, 2 * N));
+                const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
+                const T Vr = Er + (l1r * ar - l1i * ai), Vi = Ei + (l1r * ai + l1i * ar);
+                const T br = L.be_r * Vr - L.be_i * Vi, bi = L.be_r * Vi + L.be_i * Vr;      // beta V
+                xa[k1] = l2r * br - l2i * bi;
+                xb[k1] = -(l2r * bi + l2i * br);
+            }
             if constexpr (k1 == 0) {
                 // k = M from the same pair on lane 0: w = -1, ph = exp(-i pi / 4)
                 constexpr T c4 = (T)ce_cospi(1, 4);
@@ -331,10 +364,15 @@ struct QuadLine {
             }
             const T a = zr[k1], b = zi[k1];
             const T Er = a + c, Ei = b + d, Or = b - d, Oi = c - a;
-            constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
-            const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
-            vr[k1] = Er + (l1r * ar - l1i * ai);
-            vi[k1] = Ei + (l1r * ai + l1i * ar);
+            if constexpr (CT) {
+                vr[k1] = Er + (L.w_r[k1] * Or - L.w_i[k1] * Oi);
+                vi[k1] = Ei + (L.w_r[k1] * Oi + L.w_i[k1] * Or);
+            } else {
+                constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
+                const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
+                vr[k1] = Er + (l1r * ar - l1i * ai);
+                vi[k1] = Ei + (l1r * ai + l1i * ar);
+            }
             if constexpr (k1 == 0) {
                 constexpr T c4 = (T)ce_cospi(1, 4);
                 xm = c4 * ((Er - Or) + (Ei - Oi));
@@ -364,9 +402,16 @@ struct QuadLine {
             }
             const T Er = vr[k1] + mr, Ei = vi[k1] - mi;
             const T pr = vr[k1] - mr, pi = vi[k1] + mi;
-            constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
-            const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;   // p conj(alpha)
-            const T Or = l1r * t3r + l1i * t3i, Oi = l1r * t3i - l1i * t3r;
+            T Or, Oi;
+            if constexpr (CT) {                                                            // p conj(w)
+                Or = pr * L.w_r[k1] + pi * L.w_i[k1];
+                Oi = pi * L.w_r[k1] - pr * L.w_i[k1];
+            } else {
+                constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
+                const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;   // p conj(alpha)
+                Or = l1r * t3r + l1i * t3i;
+                Oi = l1r * t3i - l1i * t3r;
+            }
             constexpr int p = bitrev(k1, LOGP);
             zr[p] = Er - Oi;
             zi[p] = Ei + Or;
@@ -408,6 +453,18 @@ struct QuadLine {
     template <int K1>
     __device__ __forceinline__ static void build_z_c(const Lane &L, T xk, T xn, T ym, T yp, T (&zr)[P], T (&zi)[P])
     {
+        if constexpr (CT) {
+            // conj(ph) (xk - i xn); conj(g (ym - i yp)), g = e^{i pi/4} ph; O = p conj(w)
+            const T ar = L.ph_r[K1] * xk - L.ph_i[K1] * xn, ai = -(L.ph_r[K1] * xn + L.ph_i[K1] * xk);
+            const T c = L.g_r[K1] * ym + L.g_i[K1] * yp, d = L.g_r[K1] * yp - L.g_i[K1] * ym;
+            const T Er = ar + c, Ei = ai + d;
+            const T pr = ar - c, pi = ai - d;
+            const T Or = pr * L.w_r[K1] + pi * L.w_i[K1], Oi = pi * L.w_r[K1] - pr * L.w_i[K1];
+            constexpr int p = bitrev(K1, LOGP);
+            zr[p] = Er - Oi;
+            zi[p] = Ei + Or;
+            return;
+        }
         constexpr T l2r = (T)ce_cospi(K1, 2 * N), l2i = (T)(-ce_sinpi(K1, 2 * N));
         constexpr T l1r = (T)ce_cospi(2 * K1, N), l1i = (T)(-ce_sinpi(2 * K1, N));
         constexpr T c4 = (T)ce_cospi(1, 4);

@@ -40,7 +40,10 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
                                              double *u64 = nullptr)
 {
     static_assert(!RF || std::is_same<T, float>::value, "the refinement form steps its correction in FP32");
-    using Q = QuadLine<T, N>;
+    // split-step twiddles in registers where the register budget allows
+    // (not in the refinement form, whose FP64 re-basing state fills it)
+    constexpr bool CT = !RF && sizeof(T) * N <= 256;
+    using Q = QuadLine<T, N, CT>;
     constexpr int P = Q::P, M = N / 2;
     constexpr int LD = N + 1, SP = N * LD, NN = N * N;
     constexpr int THREADS = (8 / SPL) * N, WAVES = THREADS / 64;
@@ -272,10 +275,34 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
             });
             if (q == 0) rm[c * SP] = xm[c];
         }
+        // The column pass's divisor values are loaded ahead of their use
+        // (the first species' before the barrier, a second species' before
+        // its column reads), so that the table reads' latency overlaps the
+        // barrier and the forward transform instead of stalling the divide.
+        T da[P], db[P], dc[VF ? P : 1], dm;
+        auto load_div = [&](int c) __attribute__((always_inline)) {
+            const int cso = c * VSP * sizeof(T);
+            static_for<0, P>([&](auto Ki) {
+                constexpr int k1 = Ki;
+                if constexpr (VF) {
+                    da[k1] = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
+                    db[k1] = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + VPL * sizeof(T));
+                    dc[k1] = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + 2 * VPL * sizeof(T));
+                } else {
+                    da[k1] = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
+                    if constexpr (k1 == 0) db[0] = buf_load<T>(tb, kb == 0 ? tmo : tno + (P - 1) * N * sizeof(T), cso);
+                    else db[k1] = buf_load<T>(tb, tno + (P - 1 - k1) * N * sizeof(T), cso);
+                }
+            });
+            dm = buf_load<T>(tb, tmo, cso);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        load_div(0);
         __syncthreads();
         // column g: forward, divide, inverse
 #pragma unroll
         for (int c = 0; c < SPL; ++c) {
+            if (c > 0) load_div(c);
             static_for<0, P>([&](auto Mi) {
                 constexpr int m1 = Mi;
                 constexpr int pb = bitrev(m1, Q::LOGP);
@@ -283,29 +310,24 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
                 xr[c][pb] = cc[line_off(Mi, I0{}) * LD];
                 xi[c][pb] = cc[line_off(Mi, I1{}) * LD];
             });
-            const int cso = c * VSP * sizeof(T);
             if constexpr (VF) {
                 Q::forward_v(L, xr[c], xi[c], xa[c], xb[c], xm[c]);       // xa/xb: Re/Im V_k
                 static_for<0, P>([&](auto Ki) {
                     constexpr int k1 = Ki;
-                    const T A = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
-                    const T B = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + VPL * sizeof(T));
-                    const T C = buf_load<T>(tb, tko + k1 * N * sizeof(T), cso + 2 * VPL * sizeof(T));
                     const T re = xa[c][k1], im = xb[c][k1];
-                    xa[c][k1] = A * re + C * im;
-                    xb[c][k1] = B * im + C * re;
+                    xa[c][k1] = da[k1] * re + dc[k1] * im;
+                    xb[c][k1] = db[k1] * im + dc[k1] * re;
                 });
-                xm[c] *= buf_load<T>(tb, tmo, cso);
+                xm[c] *= dm;
                 Q::inverse_v(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
             } else {
                 Q::forward_regs(L, xr[c], xi[c], xa[c], xb[c], xm[c]);
                 static_for<0, P>([&](auto Ki) {
                     constexpr int k1 = Ki;
-                    xa[c][k1] *= buf_load<T>(tb, tko + k1 * N * sizeof(T), cso);
-                    if constexpr (k1 == 0) xb[c][0] *= buf_load<T>(tb, kb == 0 ? tmo : tno + (P - 1) * N * sizeof(T), cso);
-                    else xb[c][k1] *= buf_load<T>(tb, tno + (P - 1 - k1) * N * sizeof(T), cso);
+                    xa[c][k1] *= da[k1];
+                    xb[c][k1] *= db[k1];
                 });
-                xm[c] *= buf_load<T>(tb, tmo, cso);
+                xm[c] *= dm;
                 Q::inverse_regs(L, xa[c], xb[c], xm[c], xr[c], xi[c]);
             }
             static_for<0, P>([&](auto Mi) {
