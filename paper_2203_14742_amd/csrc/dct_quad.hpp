@@ -110,15 +110,16 @@ __device__ __forceinline__ void quad_fmac_all(T (&v)[P], T c)
 #undef CIL_QP2
 #undef CIL_QP1
 
-// CT: the split step's twiddles w_k, ph_k and e^{i pi/4} ph_k (k = k1 + P k2)
-// are held per lane in registers (6P more), one complex product each; else
-// each is a lane constant times a literal, two products and no register.
-template <typename T, int N, bool CT = false>
+// CT >= 1: the split step's twiddles w_k and ph_k (k = k1 + P k2) are held
+// per lane in registers (4P more), one complex product each; CT = 2 also
+// e^{i pi/4} ph_k (2P more).  Otherwise each is a lane constant times a
+// literal: two products and no register.
+template <typename T, int N, int CT = 0>
 struct QuadLine {
     static constexpr int M = N / 2;
     static constexpr int P = M / 4;
     static constexpr int LOGP = ilog2(P);
-    static constexpr int PC = CT ? P : 1;
+    static constexpr int PC = CT >= 1 ? P : 1, PG = CT >= 2 ? P : 1;
     static_assert(P >= 2 && (1 << LOGP) == P, "N must be a power of two >= 16");
 
     // Per-lane constants, computed once per kernel.
@@ -129,7 +130,7 @@ struct QuadLine {
         T be_r, be_i;         // exp(-i pi P k2 / (2N))
         T w_r[PC], w_i[PC];   // CT: w_k = exp(-2 pi i k / N)
         T ph_r[PC], ph_i[PC]; // CT: ph_k = exp(-i pi k / 2N)
-        T g_r[PC], g_i[PC];   // CT: e^{i pi/4} ph_k = exp(-i pi (k - N/2) / 2N)
+        T g_r[PG], g_i[PG];   // CT = 2: e^{i pi/4} ph_k = exp(-i pi (k - N/2) / 2N)
     };
 
     // The lane constants, selected from compile-time values (exact to the
@@ -159,7 +160,7 @@ struct QuadLine {
         L.al_i = k2 == 0 ? T(0) : (k2 == 1 ? a1i : (k2 == 2 ? a2i : a3i));
         L.be_r = k2 == 0 ? T(1) : (k2 == 1 ? b1r : (k2 == 2 ? b2r : b3r));
         L.be_i = k2 == 0 ? T(0) : (k2 == 1 ? b1i : (k2 == 2 ? b2i : b3i));
-        if constexpr (CT) {
+        if constexpr (CT >= 1) {
             // each rounded once from its exact value, selected by k2
             static_for<0, P>([&](auto Ki) {
                 constexpr int k1 = Ki;
@@ -173,10 +174,12 @@ struct QuadLine {
                 L.ph_i[k1] = sel((T)-ce_sinpi(k1, 2 * N), (T)-ce_sinpi(k1 + P, 2 * N), (T)-ce_sinpi(k1 + 2 * P, 2 * N),
                                  (T)-ce_sinpi(k1 + 3 * P, 2 * N));
                 constexpr int h = N / 2;
+                if constexpr (CT >= 2) {
                 L.g_r[k1] = sel((T)ce_cospi(k1 - h, 2 * N), (T)ce_cospi(k1 + P - h, 2 * N),
                                 (T)ce_cospi(k1 + 2 * P - h, 2 * N), (T)ce_cospi(k1 + 3 * P - h, 2 * N));
                 L.g_i[k1] = sel((T)-ce_sinpi(k1 - h, 2 * N), (T)-ce_sinpi(k1 + P - h, 2 * N),
                                 (T)-ce_sinpi(k1 + 2 * P - h, 2 * N), (T)-ce_sinpi(k1 + 3 * P - h, 2 * N));
+                }
             });
         }
     }
@@ -312,7 +315,7 @@ struct QuadLine {
             // The lane constant multiplies the data first, then the literal:
             // the same operation count as forming w and ph, and no per-k1 lane
             // twiddles that the compiler could precompute and keep live.
-            if constexpr (CT) {
+            if constexpr (CT >= 1) {
                 const T Vr = Er + (L.w_r[k1] * Or - L.w_i[k1] * Oi), Vi = Ei + (L.w_r[k1] * Oi + L.w_i[k1] * Or);
                 xa[k1] = L.ph_r[k1] * Vr - L.ph_i[k1] * Vi;
                 xb[k1] = -(L.ph_r[k1] * Vi + L.ph_i[k1] * Vr);
@@ -364,7 +367,7 @@ struct QuadLine {
             }
             const T a = zr[k1], b = zi[k1];
             const T Er = a + c, Ei = b + d, Or = b - d, Oi = c - a;
-            if constexpr (CT) {
+            if constexpr (CT >= 1) {
                 vr[k1] = Er + (L.w_r[k1] * Or - L.w_i[k1] * Oi);
                 vi[k1] = Ei + (L.w_r[k1] * Oi + L.w_i[k1] * Or);
             } else {
@@ -403,7 +406,7 @@ struct QuadLine {
             const T Er = vr[k1] + mr, Ei = vi[k1] - mi;
             const T pr = vr[k1] - mr, pi = vi[k1] + mi;
             T Or, Oi;
-            if constexpr (CT) {                                                            // p conj(w)
+            if constexpr (CT >= 1) {                                                       // p conj(w)
                 Or = pr * L.w_r[k1] + pi * L.w_i[k1];
                 Oi = pi * L.w_r[k1] - pr * L.w_i[k1];
             } else {
@@ -453,10 +456,21 @@ struct QuadLine {
     template <int K1>
     __device__ __forceinline__ static void build_z_c(const Lane &L, T xk, T xn, T ym, T yp, T (&zr)[P], T (&zi)[P])
     {
-        if constexpr (CT) {
+        if constexpr (CT >= 1) {
             // conj(ph) (xk - i xn); conj(g (ym - i yp)), g = e^{i pi/4} ph; O = p conj(w)
             const T ar = L.ph_r[K1] * xk - L.ph_i[K1] * xn, ai = -(L.ph_r[K1] * xn + L.ph_i[K1] * xk);
-            const T c = L.g_r[K1] * ym + L.g_i[K1] * yp, d = L.g_r[K1] * yp - L.g_i[K1] * ym;
+            T c, d;
+            if constexpr (CT >= 2) {
+                c = L.g_r[K1] * ym + L.g_i[K1] * yp;
+                d = L.g_r[K1] * yp - L.g_i[K1] * ym;
+            } else {                   // beta (ym - i yp), then e^{i pi/4} lit2, conjugated
+                constexpr T l2r = (T)ce_cospi(K1, 2 * N), l2i = (T)(-ce_sinpi(K1, 2 * N));
+                constexpr T c4 = (T)ce_cospi(1, 4);
+                constexpr T gr = c4 * (l2r - l2i), gi = c4 * (l2r + l2i);
+                const T t2r = L.be_r * ym + L.be_i * yp, t2i = L.be_i * ym - L.be_r * yp;
+                c = gr * t2r - gi * t2i;
+                d = -(gr * t2i + gi * t2r);
+            }
             const T Er = ar + c, Ei = ai + d;
             const T pr = ar - c, pi = ai - d;
             const T Or = pr * L.w_r[K1] + pi * L.w_i[K1], Oi = pi * L.w_r[K1] - pr * L.w_i[K1];

@@ -41,8 +41,8 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
 {
     static_assert(!RF || std::is_same<T, float>::value, "the refinement form steps its correction in FP32");
     // split-step twiddles in registers where the register budget allows
-    // (not in the refinement form, whose FP64 re-basing state fills it)
-    constexpr bool CT = !RF && sizeof(T) * N <= 256;
+    // (the refinement form keeps U in registers: w and ph only)
+    constexpr int CT = sizeof(T) * N > 256 ? 0 : (RF ? 1 : 2);
     using Q = QuadLine<T, N, CT>;
     constexpr int P = Q::P, M = N / 2;
     constexpr int LD = N + 1, SP = N * LD, NN = N * N;
@@ -102,9 +102,16 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
         });
     }
     // refinement form: U rounded to T (own species c at (m1, h); o32 the other
-    // species at the same points when SPL == 1) and R rounded to T
+    // species at the same points when SPL == 1) in registers, and R rounded to
+    // T in the half of the LDS that the FP32 steps leave free (2 N (N + 1)
+    // doubles hold the 2 N^2 floats of the transposes and the 2 N^2 of R):
+    // lane-major in groups of four m1, so that each lane's reads are 16-byte
+    // and a wavefront's are consecutive.
     constexpr int RP = RF ? P : 1;
-    T u32[SPL][2][RP], r32[SPL][2][RP], o32[2][(RF && SPL == 1) ? P : 1];
+    static_assert(!RF || P % 4 == 0, "R is stored in groups of four values");
+    T u32[SPL][2][RP], o32[2][(RF && SPL == 1) ? P : 1];
+    float4 *const rq = RF ? reinterpret_cast<float4 *>(sm + 2 * SP) + tid : nullptr;
+    auto rq_at = [&](int c, int h, int j) -> float4 & { return rq[((c * 2 + h) * (P / 4) + j) * THREADS]; };
     const auto u64r = make_rsrc(RF ? u64 + s.off : nullptr, RF ? 2 * NN * sizeof(double) : 0);
     const unsigned du0 = (sp0 * NN + g * N + lo) * sizeof(double), du1 = (sp0 * NN + g * N + hi0) * sizeof(double);
     auto rebase = [&](bool first) __attribute__((always_inline)) {
@@ -131,6 +138,7 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
                 });
             });
             __syncthreads();
+            T r32[SPL][2][RP];
             const double pd[4] = {s.p[0], s.p[1], s.p[2], s.p[3]};
             const int gu = g > 0 ? g - 1 : 0, gd = g < N - 1 ? g + 1 : N - 1;
             static_for<0, P>([&](auto Mi) {
@@ -156,7 +164,17 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
                     }
                 });
             });
-            __syncthreads();                                   // the row forward writes the LDS next
+            __syncthreads();                                   // the FP64 field's last readers are done
+#pragma unroll
+            for (int c = 0; c < SPL; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int j = 0; j < P / 4; ++j)
+                        rq_at(c, h, j) = make_float4(r32[c][h][4 * j], r32[c][h][4 * j + 1], r32[c][h][4 * j + 2],
+                                                     r32[c][h][4 * j + 3]);
+            // the row forward writes the LDS's first half next, which these
+            // stores do not touch; each lane reads back only its own values
         }
     };
     const long long start = step;
@@ -229,6 +247,21 @@ __device__ __forceinline__ int fused_q_solve(T *sm, double *red, int *sbad, cons
         }
         // explicit reaction from old values, into bit-reversed order for the forward
         T xr[SPL][P], xi[SPL][P];
+        T r32[SPL][2][RP];                                 // refinement form: R, from the LDS
+        if constexpr (RF) {
+#pragma unroll
+            for (int c = 0; c < SPL; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int j = 0; j < P / 4; ++j) {
+                        const float4 v = rq_at(c, h, j);
+                        r32[c][h][4 * j] = v.x;
+                        r32[c][h][4 * j + 1] = v.y;
+                        r32[c][h][4 * j + 2] = v.z;
+                        r32[c][h][4 * j + 3] = v.w;
+                    }
+        }
         static_for<0, P>([&](auto Mi) {
             constexpr int m1 = Mi;
             constexpr int pb = bitrev(m1, Q::LOGP);
@@ -426,7 +459,7 @@ __global__ __launch_bounds__((8 / SPL) * N) __attribute__((amdgpu_waves_per_eu(2
     double dt, PersistArgs pa32, PersistArgs pa64, long long *switch_step, int mode)
 {
     constexpr int LD = N + 1, SP = N * LD, WAVES = (8 / SPL) * N / 64, P = N / 8;
-    __shared__ double sm[2 * SP];
+    __shared__ __align__(16) double sm[2 * SP];
     __shared__ double red[2 * WAVES];
     __shared__ int sbad[WAVES];
     const int b = list[blockIdx.x];
