@@ -205,8 +205,8 @@ def main():
     idxB = torch.from_numpy(ib).to(dev)
     bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
     pat32 = torch.empty((B, d), dtype=torch.float32, device=dev)
-    y_pin = torch.empty(M, dtype=torch.float64, pin_memory=True)     # the observed vector, staged
     y_obs = torch.empty(M, dtype=torch.float64, device=dev)
+    Ybuf = torch.empty((n_boot, M), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -231,11 +231,10 @@ def main():
         else:
             pats = state.reshape(B, d)
         A, Bs = pats[:half], pats[half:]
-        lo, hi, radii, _, counts = cil.cil_pair_bins_adaptive(A, Bs, M, bins=bins)
-        _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
-        y_pin.copy_(torch.from_numpy(counts / float(half * half)))
-        y_obs.copy_(y_pin, non_blocking=True)
-        out = cil.cil_gaussian_loglik(Y, y_obs)
+        # range, radii, bins, bootstrap, observed vector and likelihood in one
+        # call (two host round trips: the radii, and the checks at the end)
+        lo, hi, radii, counts, _, Y, _, out = cil.cil_statistic_adaptive(A, Bs, M, idxA, idxB, bins=bins,
+                                                                         Y=Ybuf, y_obs=y_obs)
         ev1.record(stream)
         return rep, counts, ev0, ev1, out
 
@@ -413,15 +412,13 @@ def features_main(args):
     bins = torch.empty((half, half), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
     pairs = half * half
-    y_pin = torch.empty(M, dtype=torch.float64, pin_memory=True)
     y_obs = torch.empty(M, dtype=torch.float64, device=dev)
+    Ybuf = torch.empty((n_boot, M), dtype=torch.float64, device=dev)
 
     def one_step():
-        lo, hi, radii, _, counts = cil.cil_pair_bins_adaptive(A, Bs, M, bins=bins)
-        _, Y = cil.cil_bootstrap_features(bins, idxA, idxB, M, want_counts=False)
-        y_pin.copy_(torch.from_numpy(counts / float(pairs)))
-        y_obs.copy_(y_pin, non_blocking=True)
-        return cil.cil_gaussian_loglik(Y, y_obs), counts
+        lo, hi, radii, counts, _, Y, _, out = cil.cil_statistic_adaptive(A, Bs, M, idxA, idxB, bins=bins, Y=Ybuf,
+                                                                         y_obs=y_obs)
+        return out, counts
 
     for _ in range(args.warmup):
         one_step()

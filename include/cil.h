@@ -391,6 +391,27 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
                         const double *y_obs, double *f, double *loglik, int32_t *m_eff,
                         int32_t *status, void *hip_stream);
 
+/* The synthetic-likelihood statistic of two pattern sets in one call
+ * (Alg. 2bst: correlation integral vectors of the cross pairs and their
+ * bootstrap, then the Gaussian likelihood of eqs. cil:CF, cil:CF_synth):
+ *   d2min, d2max, radii, bins, counts as cil_pair_bins_adaptive (cross pairs,
+ *     no diagonal exclusion);
+ *   Y as cil_bootstrap_features (idxA, idxB, kA, kB, n_boot as there);
+ *   y_obs[m] = counts[m] / (nA nB), the observed vector, formed on the device;
+ *   f, loglik, m_eff, status as cil_gaussian_loglik for P = 1 (Y, y_obs).
+ * Same results as those calls in sequence, bit for bit, with one stream
+ * synchronisation for the radii (they are formed on the host, as
+ * cil_radii) and one at the end, where the re-check list's length and the
+ * bootstrap indices are checked (CIL_EDEVICE, CIL_EINVAL; outputs are then
+ * undefined).  Host: d2min, d2max, radii[M], counts[M] (or NULL).  Device:
+ * bins uint8[nA][nB], Y double[n_boot][M], y_obs double[M], f, loglik
+ * double[1], m_eff, status int32[1].  1 <= M <= 64, n_boot >= 2. */
+int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                           cil_precision prec, int32_t M, int32_t law, const int32_t *idxA, int32_t kA,
+                           const int32_t *idxB, int32_t kB, int32_t n_boot, double *d2min, double *d2max,
+                           double *radii, int64_t *counts, uint8_t *bins, double *Y, double *y_obs, double *f,
+                           double *loglik, int32_t *m_eff, int32_t *status, void *hip_stream);
+
 /* Library options (host only; they apply to later calls).
  * CIL_OPT_FORCE_EXACT_SUM (value 0/1): every canonical distance is taken by
  *   the exact (slow) summation instead of the certified double-double one;

@@ -111,6 +111,9 @@ def lib() -> ctypes.CDLL:
         L.cil_bootstrap_features.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp]
         L.cil_bootstrap_features_noalloc.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp]
         L.cil_gaussian_loglik.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.cil_statistic_adaptive.argtypes = [vp, i64, vp, i64, i64, ctypes.c_int, i32, i32, vp, i32, vp, i32, i32,
+                                             vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cil_statistic_adaptive.restype = ctypes.c_int
         L.cil_set_option.argtypes = [i32, i64]
         L.cil_profile.argtypes = [i32]
         L.cil_profile_read.argtypes = [ctypes.c_char_p, vp, vp]
@@ -453,6 +456,44 @@ def cil_gaussian_loglik(Y, y_obs):
     _check(lib().cil_gaussian_loglik(_dev(Y, "Y"), P, n, M, _dev(y_obs, "y_obs"), _dev(f, "f"), _dev(ll, "loglik"),
                                      _dev(me, "m_eff"), _dev(stt, "status"), _stream(Y)))
     return f, ll, me, stt
+
+
+def cil_statistic_adaptive(A, B, M: int, idxA, idxB, law: int = 0, bins=None, Y=None, y_obs=None):
+    """Alg. 2bst in one call: range, radii, bins and counts of the cross pairs,
+    the bootstrap vectors Y, the observed vector y_obs = counts / (nA nB) and
+    its Gaussian log-likelihood.  Returns (d2min, d2max, radii host float64[M],
+    counts int64[M], bins, Y, y_obs, (f, loglik, m_eff, status)) with device
+    tensors for bins [nA, nB] uint8, Y [n_boot, M], y_obs [M] and the
+    likelihood outputs [1]."""
+    import torch
+    A2, B2 = _sets(A, B)
+    nA, nB = A2.shape[0], B2.shape[0]
+    dev = A2.device
+    idxA = idxA.to(device=dev, dtype=torch.int32).contiguous()
+    idxB = idxB.to(device=dev, dtype=torch.int32).contiguous()
+    n_boot, kA = idxA.shape
+    kB = idxB.shape[1]
+    if idxB.shape[0] != n_boot:
+        raise ValueError("index lists must have the same number of resamples")
+    if bins is None:
+        bins = torch.empty((nA, nB), dtype=torch.uint8, device=dev)
+    if Y is None:
+        Y = torch.empty((n_boot, M), dtype=torch.float64, device=dev)
+    if y_obs is None:
+        y_obs = torch.empty(M, dtype=torch.float64, device=dev)
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    me = torch.empty(1, dtype=torch.int32, device=dev)
+    stt = torch.empty(1, dtype=torch.int32, device=dev)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    radii = np.zeros(M, dtype=np.float64)
+    counts = np.zeros(M, dtype=np.int64)
+    _check(lib().cil_statistic_adaptive(_dev(A2, "A"), nA, _dev(B2, "B"), nB, A2.shape[1], _prec(A2), M, law,
+                                        _dev(idxA, "idxA"), kA, _dev(idxB, "idxB"), kB, n_boot, ctypes.byref(lo),
+                                        ctypes.byref(hi), radii.ctypes.data, counts.ctypes.data, _dev(bins, "bins"),
+                                        _dev(Y, "Y"), _dev(y_obs, "y_obs"), _dev(f, "f"), _dev(ll, "loglik"),
+                                        _dev(me, "m_eff"), _dev(stt, "status"), _stream(A2)))
+    return lo.value, hi.value, radii, counts, bins, Y, y_obs, (f, ll, me, stt)
 
 
 # ------------------------------------------------ further features (Sec. 3.1)

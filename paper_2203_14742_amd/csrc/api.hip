@@ -41,6 +41,13 @@ int bootstrap_noalloc_impl(const uint8_t *, long long, long long, int, const int
                    long long *, double *, hipStream_t);
 int loglik_impl(const double *, int, int, int, const double *, double *, double *, int *, int *,
                 hipStream_t);
+template <typename T>
+int adaptive_bins_async(const T *, long long, const T *, long long, long long, int, int, double *, double *,
+                        double *, uint8_t *, AsyncBins *, hipStream_t);
+int bootstrap_deferred(const uint8_t *, long long, long long, int, const int *, int, const int *, int, int, double *,
+                       hipStream_t, int **);
+int observed_from_hist(const unsigned long long *, int, double, double *, hipStream_t);
+void set_distance_stats(long long, long long, long long);
 int last_distance_stats(int64_t *, int64_t *, int64_t *);
 void set_force_exact(int);
 int set_quad_shape(int64_t);
@@ -641,6 +648,59 @@ int cil_pair_bins_adaptive(const void *setA, int64_t nA, const void *setB, int64
             counts[m - 1] = (int64_t)run;
         }
     }
+    return CIL_OK;
+}
+
+int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
+                           cil_precision prec, int32_t M, int32_t law, const int32_t *idxA, int32_t kA,
+                           const int32_t *idxB, int32_t kB, int32_t n_boot, double *d2min, double *d2max,
+                           double *radii, int64_t *counts, uint8_t *bins, double *Y, double *y_obs, double *f,
+                           double *loglik, int32_t *m_eff, int32_t *status, void *hip_stream)
+{
+    API_BEGIN();
+    CIL_TRY(check_sets(setA, nA, setB, nB, dim, prec));
+    if (!d2min || !d2max || !radii) return set_error(CIL_EINVAL, "null output");
+    if (M < 1 || M > 64) return set_error(CIL_EINVAL, "M must be in [1, 64]");
+    if (law != 0 && law != 1) return set_error(CIL_EINVAL, "unknown radius law %d", law);
+    if (nA * nB <= 0) return set_error(CIL_EINVAL, "no pairs");
+    if (kA <= 0 || kB <= 0 || n_boot < 2) return set_error(CIL_EINVAL, "need kA, kB >= 1 and n_boot >= 2");
+    if (!idxA || !idxB || !bins || !Y || !y_obs || !f || !loglik || !m_eff || !status)
+        return set_error(CIL_EINVAL, "null pointer");
+    CIL_TRY(check_device());
+    hipStream_t st = (hipStream_t)hip_stream;
+    AsyncBins ab;
+    if (prec == CIL_FP64)
+        CIL_TRY(adaptive_bins_async<double>((const double *)setA, nA, (const double *)setB, nB, dim, M, law, d2min,
+                                            d2max, radii, bins, &ab, st));
+    else
+        CIL_TRY(adaptive_bins_async<float>((const float *)setA, nA, (const float *)setB, nB, dim, M, law, d2min,
+                                           d2max, radii, bins, &ab, st));
+    int *bflags = nullptr;
+    CIL_TRY(bootstrap_deferred(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, Y, st, &bflags));
+    CIL_TRY(observed_from_hist(ab.hist, M, (double)nA * (double)nB, y_obs, st));
+    CIL_TRY(loglik_impl(Y, 1, n_boot, M, y_obs, f, loglik, m_eff, status, st));
+    // the one read-back: histogram, re-check list counters, bootstrap index
+    // flags (pinned staging past the radii's squares, whose upload may still
+    // be pending)
+    char *hs;
+    CIL_TRY(host_stage(HS_DIST, 4096 + 64, (void **)&hs));
+    unsigned long long *hh = (unsigned long long *)(hs + 2048);
+    unsigned long long *cnt = (unsigned long long *)(hs + 4096);
+    int *hb = (int *)(hs + 4096 + 16);
+    CIL_HIP(hipMemcpyAsync(hh, ab.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(cnt, ab.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(hb, bflags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CIL_TRY(stream_wait(st));
+    if ((long long)cnt[0] > ab.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
+    if (hb[0] || hb[1]) return set_error(CIL_EINVAL, "bootstrap index out of range");
+    if (counts) {
+        unsigned long long run = 0;
+        for (int m = M; m >= 1; --m) {
+            run += hh[m];
+            counts[m - 1] = (int64_t)run;
+        }
+    }
+    set_distance_stats(nA * nB, ab.nrange + (long long)cnt[0], ab.nrange_exact + (long long)cnt[1]);
     return CIL_OK;
 }
 

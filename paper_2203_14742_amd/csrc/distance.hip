@@ -360,6 +360,7 @@ struct CanonOut {
     const unsigned long long *npairs_dev;   // count for the list (clamped to cap)
     long long cap;
     long long first;            // list mode: the launch covers pairs first, first + 1, ...
+    long long stride;           // list mode: > 0 loops each wave (WPP 1) or block over w, w + stride, ...
     const long long *ia, *jb;
     long long npairs;
     long long nA;               // index bounds for the ia/jb source
@@ -380,17 +381,38 @@ struct CanonOut {
 // latency-bound).  The certified rounding makes the result independent of
 // the summation order, so both give the same doubles.
 template <typename T, int WPP>
+__device__ __forceinline__ void canonical_pair(const T *A, const T *B, long long dim, const CanonOut &o, long long w,
+                                               int lane, int sub);
+
+template <typename T, int WPP>
 __global__ __launch_bounds__(WPP == 1 ? 256 : 64 * WPP) void k_canonical(const T *A, const T *B, long long dim,
                                                                          CanonOut o)
 {
     const int lane = threadIdx.x & 63;
     const int sub = WPP == 1 ? 0 : threadIdx.x / 64;
     // list mode: the grid may be sized before the list count is known (an
-    // upper bound); waves past the count leave at once
+    // upper bound); waves past the count leave at once, or with a stride
+    // (the grid's pair slots) each wave or block takes every stride-th pair
     const long long w = (WPP == 1 ? (long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64
                                   : (long long)blockIdx.x) + (o.pairs ? o.first : 0);
     const long long np = o.pairs ? (long long)min((unsigned long long)o.cap, *o.npairs_dev) : o.npairs;
+    if (o.pairs && o.stride > 0) {       // the trip count is uniform over a block
+        for (long long v = w; v < np; v += o.stride) {
+            canonical_pair<T, WPP>(A, B, dim, o, v, lane, sub);
+            if constexpr (WPP > 1) __syncthreads();   // wave 0 is done with the pair's partials
+        }
+        return;
+    }
     if (w >= np) return;
+    canonical_pair<T, WPP>(A, B, dim, o, w, lane, sub);
+}
+
+// The canonical squared distance of pair w (of the list or the index arrays)
+// and its sinks, by one wave (WPP 1) or the block's WPP waves.
+template <typename T, int WPP>
+__device__ __forceinline__ void canonical_pair(const T *A, const T *B, long long dim, const CanonOut &o, long long w,
+                                               int lane, int sub)
+{
     long long i, j;
     if (o.pairs) {
         i = o.pairs[w].x;
@@ -596,6 +618,13 @@ int classify(ClassifyArgs &c, long long nA, long long nB, hipStream_t st)
 
 void set_force_exact(int v) { g_force_exact = v; }
 
+void set_distance_stats(long long pairs, long long rechecked, long long exact)
+{
+    t_pairs = pairs;
+    t_rechecked = rechecked;
+    t_exact = exact;
+}
+
 int last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact)
 {
     if (pairs) *pairs = t_pairs;
@@ -782,6 +811,83 @@ int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long 
     t_exact += nrange_exact;
     return CIL_OK;
 }
+
+// The same without the bins' read-back: the re-check list is finished on the
+// device whatever its length (strided launches), and the
+// histogram and list counters stay on the device for the caller's one
+// read-back at the end of a longer chain (AsyncBins).  The range and its
+// read-back, which the radii need, are as in adaptive_bins_impl.
+template <typename T>
+int adaptive_bins_async(const T *A, long long nA, const T *B, long long nB, long long dim, int M, int law,
+                        double *dmin, double *dmax, double *radii, uint8_t *bins, AsyncBins *ab, hipStream_t st)
+{
+    DistScratch s;
+    CIL_TRY(scratch(nA * nB, &s));
+    Approx ap;
+    CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
+    CIL_TRY(range_from_approx(A, nA, B, nB, dim, ap, s, 0, dmin, dmax, st));
+    ab->nrange = t_rechecked;
+    ab->nrange_exact = t_exact;
+    CIL_TRY(radii_ladder(*dmin, *dmax, M, law, radii));
+    char *hs;
+    CIL_TRY(host_stage(HS_DIST, 4096 + 64, (void **)&hs));
+    double *thr = (double *)hs;
+    for (int m = 0; m < M; ++m) thr[m] = radii[m] * radii[m];
+    CIL_HIP(hipMemcpyAsync(s.thr, thr, sizeof(double) * M, hipMemcpyHostToDevice, st));
+    CIL_TRY(fill_zero(s.hist, (char *)(s.nlist + 2) - (char *)s.hist, st));
+    ClassifyArgs &c = ap.c;
+    c.exclude_diag = 0;
+    c.mode = MODE_BINS;
+    c.thr = s.thr;
+    c.M = M;
+    c.hist = s.hist;
+    c.bins = bins;
+    c.list = s.list;
+    c.nlist = s.nlist;
+    c.cap = s.cap;
+    CIL_TRY(classify(c, nA, nB, st));
+    CanonOut co{};
+    co.pairs = s.list;
+    co.npairs_dev = s.nlist;
+    co.cap = s.cap;
+    co.thr = s.thr;
+    co.M = M;
+    co.hist = s.hist;
+    co.bins = bins;
+    co.nB = nB;
+    co.nexact = s.nexact;
+    co.force_exact = g_force_exact;
+    // Any list length without reading it back.  Short vectors: one strided
+    // launch, 2048 waves, one pair each at a time.  Long vectors: the first
+    // launch as in bins_from_approx (256 pairs, 16 waves each: the usual
+    // short list at the latency of one pair), then a strided launch of 8192
+    // single-wave slots for the rest, which leaves at once when there is none.
+    if (dim < 4096) {
+        co.stride = 2048;
+        CIL_TRY(run_canonical(A, B, dim, co, 2048, st));
+    } else {
+        const long long first = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
+        CIL_TRY(run_canonical(A, B, dim, co, first, st));
+        if (s.cap > first) {
+            constexpr long long TAIL = 8192;
+            co.first = first;
+            co.stride = TAIL;
+            const ProfMark pm = prof_begin("k_canonical", st);
+            hipLaunchKernelGGL((k_canonical<T, 1>), dim3((unsigned)(TAIL / 4)), dim3(256), 0, st, A, B, dim, co);
+            prof_end(pm, st);
+            CIL_TRY(check_launch("k_canonical"));
+        }
+    }
+    ab->hist = s.hist;
+    ab->nlist = s.nlist;
+    ab->cap = s.cap;
+    return CIL_OK;
+}
+
+template int adaptive_bins_async<double>(const double *, long long, const double *, long long, long long, int, int,
+                                         double *, double *, double *, uint8_t *, AsyncBins *, hipStream_t);
+template int adaptive_bins_async<float>(const float *, long long, const float *, long long, long long, int, int,
+                                        double *, double *, double *, uint8_t *, AsyncBins *, hipStream_t);
 
 template int adaptive_bins_impl<double>(const double *, long long, const double *, long long, long long, int, int,
                                         int, double *, double *, double *, uint8_t *,

@@ -330,7 +330,7 @@ static bool boot_uses_mfma(int M) { return M <= 4 * BTPW && g_boot_mfma; }
 
 static int bootstrap_run(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
                          const int *idxB, int kB, int n_boot, long long *Ycount, double *Y, hipStream_t st,
-                         BootMem &mem)
+                         BootMem &mem, int **defer_flags = nullptr)
 {
     const bool work = n_boot > 0 && kA > 0 && kB > 0;
     const bool mfma = work && boot_uses_mfma(M);
@@ -390,6 +390,10 @@ static int bootstrap_run(const uint8_t *bins, long long nA, long long nB, int M,
                            Y);
         CIL_TRY(check_launch("k_boot_finish"));
     }
+    if (defer_flags) {                 // the caller reads the two index flags later
+        *defer_flags = flags;
+        return CIL_OK;
+    }
     // pinned host words keep the copy asynchronous; the allocation-free path
     // reads into the stack instead (pinned memory would be allocated)
     int hloc[2];
@@ -407,6 +411,34 @@ int bootstrap_impl(const uint8_t *bins, long long nA, long long nB, int M, const
 {
     BootMem mem;
     return bootstrap_run(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, Ycount, Y, st, mem);
+}
+
+// The bootstrap without its index-flag read-back; *flags (device int[2],
+// nonzero: an index out of range) is left for the caller to read.
+int bootstrap_deferred(const uint8_t *bins, long long nA, long long nB, int M, const int *idxA, int kA,
+                       const int *idxB, int kB, int n_boot, double *Y, hipStream_t st, int **flags)
+{
+    BootMem mem;
+    return bootstrap_run(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, nullptr, Y, st, mem, flags);
+}
+
+// The observed correlation integral vector from a bin histogram (hist[m]:
+// pairs in bin m, m = 0..M): y[m - 1] = #{pairs with bin >= m} / denom, the
+// counts accumulated from the top bin down as integers, then one division.
+__global__ void k_observed(const unsigned long long *hist, int M, double denom, double *y)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long run = 0;
+    for (int m = M; m >= 1; --m) {
+        run += hist[m];
+        y[m - 1] = (double)run / denom;
+    }
+}
+
+int observed_from_hist(const unsigned long long *hist, int M, double denom, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_observed, dim3(1), dim3(64), 0, st, hist, M, denom, y);
+    return check_launch("k_observed");
 }
 
 // ------------------------------------- bootstrap without allocation
