@@ -400,10 +400,15 @@ int cil_gaussian_loglik(const double *Y, int32_t P, int32_t n_boot, int32_t M,
  *   y_obs[m] = counts[m] / (nA nB), the observed vector, formed on the device;
  *   f, loglik, m_eff, status as cil_gaussian_loglik for P = 1 (Y, y_obs).
  * Same results as those calls in sequence, bit for bit, with one stream
- * synchronisation for the radii (they are formed on the host, as
- * cil_radii) and one at the end, where the re-check list's length and the
+ * synchronisation, at the end, where the re-check list's length and the
  * bootstrap indices are checked (CIL_EDEVICE, CIL_EINVAL; outputs are then
- * undefined).  Host: d2min, d2max, radii[M], counts[M] (or NULL).  Device:
+ * undefined).  The radii are formed on the device (powers in double-double,
+ * rounded once) and compared at the end with cil_radii's, which are the
+ * call's radii.  Where the two differ (the C library's pow is not correctly
+ * rounded for every argument: about one ladder in a hundred at M = 13) the
+ * bins stand unless a pair lies within 2^-44 R_m^2 of a threshold that
+ * differs; then the call is redone with the host's radii and one more
+ * synchronisation (CIL_OPT_STAT_DEVICE_RADII).  Host: d2min, d2max, radii[M], counts[M] (or NULL).  Device:
  * bins uint8[nA][nB], Y double[n_boot][M], y_obs double[M], f, loglik
  * double[1], m_eff, status int32[1].  1 <= M <= 64, n_boot >= 2. */
 int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
@@ -451,6 +456,11 @@ int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64
  *   kernel runs twice, the FP32 phase of the whole batch, then the polish of
  *   the solves at their floor.  Both give identical results.  (Other sides
  *   always polish in FP64 steps in a launch of their own.)
+ * CIL_OPT_STAT_DEVICE_RADII (value 0, 1 (default) or 2): cil_statistic_adaptive
+ *   forms the radii on the device and checks them against the host's at the
+ *   end (1), or on the host after reading the range back (0); 2 = as 1 with
+ *   the check always failing, so that every call takes the host's radii in a
+ *   second pass (for testing that path).
  * CIL_OPT_SYNC_SPIN_US (value 0..1e7, default 200000): where a call waits
  *   for its stream (to read back results), it polls the stream's progress for
  *   up to this many microseconds before a blocking wait; 0 = block at once.
@@ -459,7 +469,7 @@ int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64
  *   are unchanged.  CIL_EINVAL outside the range. */
 enum { CIL_OPT_FORCE_EXACT_SUM = 1, CIL_OPT_QUAD_SHAPE = 2, CIL_OPT_BOOTSTRAP_GATHER = 3, CIL_OPT_GRAM_FLUSH = 4,
        CIL_OPT_GRAM_PIPELINE = 5, CIL_OPT_WAVE_PRIORITY = 6, CIL_OPT_POLISH_SEPARATE = 7,
-       CIL_OPT_SYNC_SPIN_US = 8 };
+       CIL_OPT_SYNC_SPIN_US = 8, CIL_OPT_STAT_DEVICE_RADII = 9 };
 int cil_set_option(int32_t option, int64_t value);
 
 /* Kernel timing.  cil_profile(1) clears the accumulators and starts timing:

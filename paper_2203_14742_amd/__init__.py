@@ -32,6 +32,7 @@ CIL_OPT_GRAM_PIPELINE = 5
 CIL_OPT_WAVE_PRIORITY = 6
 CIL_OPT_POLISH_SEPARATE = 7
 CIL_OPT_SYNC_SPIN_US = 8
+CIL_OPT_STAT_DEVICE_RADII = 9
 CIL_QUAD_SHAPES = 4
 
 

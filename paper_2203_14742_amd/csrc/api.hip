@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "cil_internal.hpp"
+#include "distance_async.hpp"
 
 namespace cil {
 
@@ -42,12 +43,13 @@ int bootstrap_noalloc_impl(const uint8_t *, long long, long long, int, const int
 int loglik_impl(const double *, int, int, int, const double *, double *, double *, int *, int *,
                 hipStream_t);
 template <typename T>
-int adaptive_bins_async(const T *, long long, const T *, long long, long long, int, int, double *, double *,
+int adaptive_bins_async(const T *, long long, const T *, long long, long long, int, int, int, double *, double *,
                         double *, uint8_t *, AsyncBins *, hipStream_t);
 int bootstrap_deferred(const uint8_t *, long long, long long, int, const int *, int, const int *, int, int, double *,
                        hipStream_t, int **);
 int observed_from_hist(const unsigned long long *, int, double, double *, hipStream_t);
 void set_distance_stats(long long, long long, long long);
+int range_init_stage(unsigned long long **);
 int last_distance_stats(int64_t *, int64_t *, int64_t *);
 void set_force_exact(int);
 int set_quad_shape(int64_t);
@@ -651,6 +653,126 @@ int cil_pair_bins_adaptive(const void *setA, int64_t nA, const void *setB, int64
     return CIL_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// 1: the statistic's radii formed on the device and checked against the
+// host's at the end (default); 0: formed on the host after a read-back of
+// the range; 2: as 1 with the check always failing (tests the fallback).
+std::atomic<int> g_stat_radii{1};
+struct StatArgs {
+    const void *A, *B;
+    int64_t nA, nB, dim;
+    int prec, M, law;
+    const int32_t *idxA, *idxB;
+    int32_t kA, kB, n_boot;
+    uint8_t *bins;
+    double *Y, *y_obs, *f, *loglik;
+    int32_t *m_eff, *status;
+};
+
+// What the host needs after the stream pass: the pinned read-back locations
+// (fixed offsets of the HS_DIST staging) and the list capacity.
+struct StatPending {
+    unsigned long long *hh, *cnt, *hits;
+    int *hb;
+    RangeOut *ro;               // null: the radii were formed on the host
+    long long cap;
+    long long nrange, nrange_exact;
+};
+
+// The stream work of Alg. 2bst: range, radii, bins, bootstrap, observed
+// vector, likelihood, and the copies of what the host checks into pinned
+// staging.  With device_radii no host value enters it after the start: the
+// host waits once, at the end.
+template <typename T>
+int statistic_enqueue(const StatArgs &a, int device_radii, double *d2min, double *d2max, double *radii,
+                      hipStream_t st, StatPending *pd)
+{
+    AsyncBins ab;
+    CIL_TRY(adaptive_bins_async<T>((const T *)a.A, a.nA, (const T *)a.B, a.nB, a.dim, a.M, a.law, device_radii, d2min,
+                                   d2max, radii, a.bins, &ab, st));
+    int *bflags = nullptr;
+    CIL_TRY(bootstrap_deferred(a.bins, a.nA, a.nB, a.M, a.idxA, a.kA, a.idxB, a.kB, a.n_boot, a.Y, st, &bflags));
+    CIL_TRY(observed_from_hist(ab.hist, a.M, (double)a.nA * (double)a.nB, a.y_obs, st));
+    CIL_TRY(loglik_impl(a.Y, 1, a.n_boot, a.M, a.y_obs, a.f, a.loglik, a.m_eff, a.status, st));
+    // pinned staging past the range counters' initial values (offset 0)
+    char *hs;
+    CIL_TRY(host_stage(HS_DIST, 8192, (void **)&hs));
+    pd->hh = (unsigned long long *)(hs + 2048);
+    pd->cnt = (unsigned long long *)(hs + 4096);
+    pd->hb = (int *)(hs + 4096 + 16);
+    pd->hits = (unsigned long long *)(hs + 4096 + 32);
+    pd->ro = ab.ro ? (RangeOut *)(hs + 4096 + 64) : nullptr;
+    pd->cap = ab.cap;
+    pd->nrange = ab.nrange;
+    pd->nrange_exact = ab.nrange_exact;
+    CIL_HIP(hipMemcpyAsync(pd->hh, ab.hist, sizeof(unsigned long long) * (a.M + 1), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(pd->cnt, ab.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    CIL_HIP(hipMemcpyAsync(pd->hb, bflags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (ab.ro) {
+        CIL_HIP(hipMemcpyAsync(pd->ro, ab.ro, sizeof(RangeOut), hipMemcpyDeviceToHost, st));
+        CIL_HIP(hipMemcpyAsync(pd->hits, ab.nlist + 7, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    }
+    return CIL_OK;
+}
+
+// After the stream has drained: the checks and the host outputs.
+// *mismatch: the device's radii differ from the host's at a threshold with
+// a pair near it (the outputs are then those of the device's radii: the
+// caller redoes the call with the host's).
+int statistic_finish(const StatArgs &a, const StatPending &pd, double *d2min, double *d2max, double *radii,
+                     int64_t *counts, bool *mismatch)
+{
+    *mismatch = false;
+    long long nrange = pd.nrange, nrange_exact = pd.nrange_exact;
+    if (pd.ro) {
+        if (pd.ro->status == 2) return set_error(CIL_ENONFINITE, "non-finite distances in range computation");
+        if (pd.ro->status == 3) return set_error(CIL_EDEVICE, "range candidate overflow");
+        *d2min = pd.ro->d2min;
+        *d2max = pd.ro->d2max;
+        CIL_TRY(radii_ladder(*d2min, *d2max, a.M, a.law, radii));      // the degenerate range fails here
+        // the host's ladder is the call's; the bins stand unless it differs
+        // from the device's at a threshold that has a pair within its window
+        unsigned long long differ = 0;
+        for (int m = 0; m < a.M; ++m)
+            if (std::memcmp(&radii[m], &pd.ro->radii[m], sizeof(double)) != 0) differ |= 1ull << m;
+        *mismatch = (differ & *pd.hits) != 0 || g_stat_radii.load() == 2;
+        if (*mismatch) return CIL_OK;
+        nrange = pd.ro->nrange;
+        nrange_exact = pd.ro->nrange_exact;
+    }
+    if ((long long)pd.cnt[0] > pd.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
+    if (pd.hb[0] || pd.hb[1]) return set_error(CIL_EINVAL, "bootstrap index out of range");
+    if (counts) {
+        unsigned long long run = 0;
+        for (int m = a.M; m >= 1; --m) {
+            run += pd.hh[m];
+            counts[m - 1] = (int64_t)run;
+        }
+    }
+    set_distance_stats(a.nA * a.nB, nrange + (long long)pd.cnt[0], nrange_exact + (long long)pd.cnt[1]);
+    return CIL_OK;
+}
+
+int statistic_enqueue_any(const StatArgs &a, int device_radii, double *d2min, double *d2max, double *radii,
+                          hipStream_t st, StatPending *pd)
+{
+    if (a.prec == CIL_FP64) return statistic_enqueue<double>(a, device_radii, d2min, d2max, radii, st, pd);
+    return statistic_enqueue<float>(a, device_radii, d2min, d2max, radii, st, pd);
+}
+
+}  // namespace
+
+static int set_stat_radii(int64_t v)
+{
+    if (v < 0 || v > 2) return set_error(CIL_EINVAL, "statistic radii option must be 0, 1 or 2");
+    g_stat_radii.store((int)v);
+    return CIL_OK;
+}
+
+extern "C" {
+
 int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64_t nB, int64_t dim,
                            cil_precision prec, int32_t M, int32_t law, const int32_t *idxA, int32_t kA,
                            const int32_t *idxB, int32_t kB, int32_t n_boot, double *d2min, double *d2max,
@@ -668,40 +790,38 @@ int cil_statistic_adaptive(const void *setA, int64_t nA, const void *setB, int64
         return set_error(CIL_EINVAL, "null pointer");
     CIL_TRY(check_device());
     hipStream_t st = (hipStream_t)hip_stream;
-    AsyncBins ab;
-    if (prec == CIL_FP64)
-        CIL_TRY(adaptive_bins_async<double>((const double *)setA, nA, (const double *)setB, nB, dim, M, law, d2min,
-                                            d2max, radii, bins, &ab, st));
-    else
-        CIL_TRY(adaptive_bins_async<float>((const float *)setA, nA, (const float *)setB, nB, dim, M, law, d2min,
-                                           d2max, radii, bins, &ab, st));
-    int *bflags = nullptr;
-    CIL_TRY(bootstrap_deferred(bins, nA, nB, M, idxA, kA, idxB, kB, n_boot, Y, st, &bflags));
-    CIL_TRY(observed_from_hist(ab.hist, M, (double)nA * (double)nB, y_obs, st));
-    CIL_TRY(loglik_impl(Y, 1, n_boot, M, y_obs, f, loglik, m_eff, status, st));
-    // the one read-back: histogram, re-check list counters, bootstrap index
-    // flags (pinned staging past the radii's squares, whose upload may still
-    // be pending)
-    char *hs;
-    CIL_TRY(host_stage(HS_DIST, 4096 + 64, (void **)&hs));
-    unsigned long long *hh = (unsigned long long *)(hs + 2048);
-    unsigned long long *cnt = (unsigned long long *)(hs + 4096);
-    int *hb = (int *)(hs + 4096 + 16);
-    CIL_HIP(hipMemcpyAsync(hh, ab.hist, sizeof(unsigned long long) * (M + 1), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipMemcpyAsync(cnt, ab.nlist, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    CIL_HIP(hipMemcpyAsync(hb, bflags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    CIL_TRY(stream_wait(st));
-    if ((long long)cnt[0] > ab.cap) return set_error(CIL_EDEVICE, "re-check list overflow");
-    if (hb[0] || hb[1]) return set_error(CIL_EINVAL, "bootstrap index out of range");
-    if (counts) {
-        unsigned long long run = 0;
-        for (int m = M; m >= 1; --m) {
-            run += hh[m];
-            counts[m - 1] = (int64_t)run;
-        }
+    StatArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = setA;
+    a.B = setB;
+    a.nA = nA;
+    a.nB = nB;
+    a.dim = dim;
+    a.prec = (int)prec;
+    a.M = M;
+    a.law = law;
+    a.idxA = idxA;
+    a.idxB = idxB;
+    a.kA = kA;
+    a.kB = kB;
+    a.n_boot = n_boot;
+    a.bins = bins;
+    a.Y = Y;
+    a.y_obs = y_obs;
+    a.f = f;
+    a.loglik = loglik;
+    a.m_eff = m_eff;
+    a.status = status;
+    int dr = g_stat_radii.load() != 0;
+    bool mismatch = false;
+    for (int pass = 0; pass < 2; ++pass, dr = 0) {             // a second pass, with the host's radii, after a mismatch
+        StatPending pd;
+        CIL_TRY(statistic_enqueue_any(a, dr, d2min, d2max, radii, st, &pd));
+        CIL_TRY(stream_wait(st));
+        CIL_TRY(statistic_finish(a, pd, d2min, d2max, radii, counts, &mismatch));
+        if (!mismatch) return CIL_OK;
     }
-    set_distance_stats(nA * nB, ab.nrange + (long long)cnt[0], ab.nrange_exact + (long long)cnt[1]);
-    return CIL_OK;
+    return set_error(CIL_EDEVICE, "statistic radii check");
 }
 
 int cil_last_distance_stats(int64_t *pairs, int64_t *rechecked, int64_t *exact_fallbacks)
@@ -826,6 +946,7 @@ int cil_set_option(int32_t option, int64_t value)
     if (option == CIL_OPT_WAVE_PRIORITY) return set_wave_priority(value);
     if (option == CIL_OPT_POLISH_SEPARATE) return set_polish_separate(value);
     if (option == CIL_OPT_SYNC_SPIN_US) return set_sync_spin(value);
+    if (option == CIL_OPT_STAT_DEVICE_RADII) return set_stat_radii(value);
     return set_error(CIL_EINVAL, "unknown option %d", option);
 }
 

@@ -47,16 +47,6 @@ int ws_get(int slot, size_t bytes, void **ptr);
 // inside a call (so they run asynchronously), grow-only, one per (device,
 // slot); freed by cil_shutdown().
 enum HostSlot { HS_DIST = 0, HS_BOOT, HS_STEP, HS_NUM_SLOTS };
-
-// Adaptive bins left on the device (distance.hip) for one later read-back:
-// the histogram [M + 1] and the re-check list counters (listed pairs, exact
-// fallbacks), with the list capacity and the range pass's statistics.
-struct AsyncBins {
-    unsigned long long *hist = nullptr;
-    unsigned long long *nlist = nullptr;
-    long long cap = 0;
-    long long nrange = 0, nrange_exact = 0;
-};
 int host_stage(int slot, size_t bytes, void **ptr);
 int current_device(int *dev);
 // Wait for everything issued to `st` (polls, then blocks; CIL_OPT_SYNC_SPIN_US).

@@ -24,6 +24,8 @@
 #include <vector>
 
 #include "cil_internal.hpp"
+#include "distance_async.hpp"
+#include "radii_dd.hpp"
 
 // The error-free transformations below (two-sum, exact squares split by an
 // FMA) are only exact if no product is fused into a later sum: contraction
@@ -119,6 +121,7 @@ struct ClassifyArgs {
     int mode;
     int exclude_diag;
     const double *thr;          // bins: [M]
+    double thr_slack;           // bins: also list the pairs within thr_slack thr of a threshold
     int M;
     unsigned long long *hist;   // bins: [M+1]
     uint8_t *bins;              // bins: [nA][nB] or null
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs c, long long nA, 
             bool amb = !finite;
             for (int m = 0; m < c.M; ++m) {
                 const double t = sthr[m];
-                if (fabs(D - t) <= eps) amb = true;
+                if (fabs(D - t) <= eps + c.thr_slack * t) amb = true;
                 bin += (D < t);
             }
             if (amb) {
@@ -367,10 +370,13 @@ struct CanonOut {
     int *bad;                   // set when an ia/jb index is out of range
     // sinks
     double *d2;                 // per pair, or null
+    unsigned long long *range_mm;   // or null: [0] min, [1] max of the pairs' D (bits of non-negative doubles)
     const double *thr;
     int M;
     unsigned long long *hist;   // or null
     uint8_t *bins;              // or null
+    double win_rel;             // with win_hits: bit m set when a pair lies within win_rel thr[m] of thr[m]
+    unsigned long long *win_hits;
     long long nB;
     unsigned long long *nexact;
     int force_exact;
@@ -488,10 +494,19 @@ __device__ __forceinline__ void canonical_pair(const T *A, const T *B, long long
     }
     if (lane == 0) {
         if (o.d2) o.d2[w] = D;
+        if (o.range_mm) {       // non-negative doubles order as their bit patterns
+            atomicMin(&o.range_mm[0], (unsigned long long)__double_as_longlong(D));
+            atomicMax(&o.range_mm[1], (unsigned long long)__double_as_longlong(D));
+        }
         if (o.hist) {
             int bin = 0;
-            for (int m = 0; m < o.M; ++m) bin += (D < o.thr[m]);
+            unsigned long long near = 0;
+            for (int m = 0; m < o.M; ++m) {
+                bin += (D < o.thr[m]);
+                if (o.win_hits && fabs(D - o.thr[m]) <= o.win_rel * o.thr[m]) near |= 1ull << m;
+            }
             atomicAdd(&o.hist[bin], 1ull);
+            if (near) atomicOr(o.win_hits, near);
             if (o.bins) o.bins[i * o.nB + j] = (uint8_t)bin;
         }
     }
@@ -511,6 +526,8 @@ struct DistScratch {
     unsigned long long *nexact = nullptr;
     unsigned long long *minmax = nullptr;
     unsigned long long *flag = nullptr;
+    unsigned long long *cmm = nullptr;      // canonical extremes of the range candidates (bits)
+    RangeOut *ro = nullptr;
     int2 *list = nullptr;
     long long cap = 0;
 };
@@ -526,6 +543,9 @@ int scratch(long long cap, DistScratch *s)
     s->nexact = s->nlist + 1;
     s->minmax = s->nlist + 2;
     s->flag = s->nlist + 4;
+    s->cmm = s->nlist + 5;
+    s->ro = (RangeOut *)(c + 4096 + 64);
+    static_assert(4096 + 64 + sizeof(RangeOut) <= 4096 + sizeof(double) * 512, "range output fits the workspace");
     CIL_TRY(ws_get(WS_DIST_RECHECK, sizeof(int2) * (size_t)std::max<long long>(cap, 1), &p));
     s->list = (int2 *)p;
     s->cap = cap;
@@ -812,6 +832,144 @@ int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long 
     return CIL_OK;
 }
 
+// R_0 - m h rounded as two operations, as the host forms it (no contraction).
+__device__ __forceinline__ double linear_radius(double R0, int m, double h)
+{
+#pragma clang fp contract(off)
+    return R0 - (double)m * h;
+}
+
+// The device range pass's initial counters, staged in pinned host memory
+// (HS_DIST, offset 0; the caller's read-back uses the same buffer further
+// on): list count, exact fallbacks, classify bounds (+inf, 0), non-finite
+// flag, canonical extremes (+inf, 0), thresholds with a pair near them.
+int range_init_stage(unsigned long long **out)
+{
+    char *hs;
+    CIL_TRY(host_stage(HS_DIST, 8192, (void **)&hs));
+    unsigned long long *init = (unsigned long long *)hs;
+    init[0] = 0ull;
+    init[1] = 0ull;
+    init[2] = (unsigned long long)0x7ff0000000000000ull;
+    init[3] = 0ull;
+    init[4] = 0ull;
+    init[5] = (unsigned long long)0x7ff0000000000000ull;
+    init[6] = 0ull;
+    init[7] = 0ull;
+    *out = init;
+    return CIL_OK;
+}
+
+// Range and radii on the device from the range pass's counters (cnt: [0]
+// candidates, [1] exact fallbacks, [4] non-finite flag, [5], [6] the
+// candidates' canonical extremes): the ladder as the host forms it
+// (cil_radii), powers by pow_dd; thr[m] = R_m^2.  A bad range leaves every
+// threshold 0 and its status in ro.
+__global__ void k_range_radii(const unsigned long long *cnt, long long cap, int M, int law, double *thr, RangeOut *ro)
+{
+    __shared__ double sR0, sb;
+    __shared__ DD slogb;
+    __shared__ int sst;
+    __shared__ DDTables tab;
+    {                                    // the series' coefficients, one per thread
+        const int k = threadIdx.x;
+        if (k < kLogTerms) tab.inv_odd[k] = dd_inv(2 * k + 1);
+        else if (k < kLogTerms + kExpTerms) tab.inv_n[k - kLogTerms + 1] = dd_inv(k - kLogTerms + 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double lo = __longlong_as_double((long long)cnt[5]), hi = __longlong_as_double((long long)cnt[6]);
+        ro->d2min = lo;
+        ro->d2max = hi;
+        ro->nrange = (long long)cnt[0];
+        ro->nrange_exact = (long long)cnt[1];
+        int st = 0;
+        if (cnt[4]) st = 2;
+        else if ((long long)cnt[0] > cap) st = 3;
+        const double R0 = sqrt_dd(hi), RM = sqrt_dd(lo);
+        if (st == 0 && !(RM > 0.0 && R0 > RM && isfinite(R0))) st = 1;
+        ro->status = st;
+        sst = st;
+        sR0 = R0;
+        DD lb{0.0, 0.0};
+        sb = st != 0 ? 0.0 : (law == 0 ? root_dd(R0 / RM, M, tab, &lb) : (R0 - RM) / M);
+        slogb = lb;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        double r = 0.0;
+        if (sst == 0)
+            r = law == 0 ? sR0 * pow_dd_from_log(slogb, (double)-(m + 1), tab) : linear_radius(sR0, m + 1, sb);
+        ro->radii[m] = r;
+        thr[m] = r * r;
+    }
+}
+
+// Re-check launches over a list whose length stays on the device: for
+// d < 4096 one launch of 2048 waves striding over it; for longer vectors a
+// first launch of 256 pairs at sixteen waves each (the usual short list at
+// the latency of one pair), then a strided launch of 8192 single-wave slots
+// for the rest, which leaves at once when there is none.
+template <typename T>
+int canonical_any_length(const T *A, const T *B, long long dim, CanonOut co, long long cap, hipStream_t st)
+{
+    if (dim < 4096) {
+        co.stride = 2048;
+        return run_canonical(A, B, dim, co, 2048, st);
+    }
+    const long long first = std::min(recheck_guess(dim), std::max(cap, 1LL));
+    CIL_TRY(run_canonical(A, B, dim, co, first, st));
+    if (cap > first) {
+        constexpr long long TAIL = 8192;
+        co.first = first;
+        co.stride = TAIL;
+        const ProfMark pm = prof_begin("k_canonical", st);
+        hipLaunchKernelGGL((k_canonical<T, 1>), dim3((unsigned)(TAIL / 4)), dim3(256), 0, st, A, B, dim, co);
+        prof_end(pm, st);
+        CIL_TRY(check_launch("k_canonical"));
+    }
+    return CIL_OK;
+}
+
+// The range pass without its read-back: candidates listed as in
+// range_from_approx, their canonical distances folded into the device's
+// extremes, then the radii and thresholds formed on the device.
+template <typename T>
+int range_radii_device(const T *A, long long nA, const T *B, long long nB, long long dim, Approx &ap,
+                       DistScratch &s, int M, int law, hipStream_t st)
+{
+    unsigned long long *init;
+    CIL_TRY(range_init_stage(&init));
+    CIL_HIP(hipMemcpyAsync(s.nlist, init, 8 * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+    ClassifyArgs &c = ap.c;
+    c.exclude_diag = 0;
+    c.minmax = s.minmax;
+    c.flag = s.flag;
+    c.list = s.list;
+    c.nlist = s.nlist;
+    c.cap = s.cap;
+    if (c.S > 1) CIL_TRY(ws_get(WS_DIST_REDUCED, sizeof(double) * (size_t)std::max(nA * nB, 1LL), (void **)&c.reduced));
+    c.mode = MODE_RANGE1;
+    CIL_TRY(classify(c, nA, nB, st));
+    if (c.reduced) {
+        c.P = c.reduced;
+        c.S = 1;
+        c.reduced = nullptr;
+    }
+    c.mode = MODE_RANGE2;
+    CIL_TRY(classify(c, nA, nB, st));
+    CanonOut co{};
+    co.pairs = s.list;
+    co.npairs_dev = s.nlist;
+    co.cap = s.cap;
+    co.range_mm = s.cmm;
+    co.nexact = s.nexact;
+    co.force_exact = g_force_exact;
+    CIL_TRY(canonical_any_length(A, B, dim, co, s.cap, st));
+    hipLaunchKernelGGL(k_range_radii, dim3(1), dim3(64), 0, st, s.nlist, s.cap, M, law, s.thr, s.ro);
+    return check_launch("k_range_radii");
+}
+
 // The same without the bins' read-back: the re-check list is finished on the
 // device whatever its length (strided launches), and the
 // histogram and list counters stay on the device for the caller's one
@@ -819,26 +977,37 @@ int adaptive_bins_impl(const T *A, long long nA, const T *B, long long nB, long 
 // read-back, which the radii need, are as in adaptive_bins_impl.
 template <typename T>
 int adaptive_bins_async(const T *A, long long nA, const T *B, long long nB, long long dim, int M, int law,
-                        double *dmin, double *dmax, double *radii, uint8_t *bins, AsyncBins *ab, hipStream_t st)
+                        int device_radii, double *dmin, double *dmax, double *radii, uint8_t *bins, AsyncBins *ab,
+                        hipStream_t st)
 {
     DistScratch s;
     CIL_TRY(scratch(nA * nB, &s));
     Approx ap;
     CIL_TRY(approx_pass(A, nA, B, nB, dim, &ap, st));
-    CIL_TRY(range_from_approx(A, nA, B, nB, dim, ap, s, 0, dmin, dmax, st));
-    ab->nrange = t_rechecked;
-    ab->nrange_exact = t_exact;
-    CIL_TRY(radii_ladder(*dmin, *dmax, M, law, radii));
-    char *hs;
-    CIL_TRY(host_stage(HS_DIST, 4096 + 64, (void **)&hs));
-    double *thr = (double *)hs;
-    for (int m = 0; m < M; ++m) thr[m] = radii[m] * radii[m];
-    CIL_HIP(hipMemcpyAsync(s.thr, thr, sizeof(double) * M, hipMemcpyHostToDevice, st));
+    if (device_radii) {
+        CIL_TRY(range_radii_device(A, nA, B, nB, dim, ap, s, M, law, st));
+    } else {
+        CIL_TRY(range_from_approx(A, nA, B, nB, dim, ap, s, 0, dmin, dmax, st));
+        ab->nrange = t_rechecked;
+        ab->nrange_exact = t_exact;
+        CIL_TRY(radii_ladder(*dmin, *dmax, M, law, radii));
+        char *hs;
+        CIL_TRY(host_stage(HS_DIST, 4096 + 64, (void **)&hs));
+        double *thr = (double *)hs;
+        for (int m = 0; m < M; ++m) thr[m] = radii[m] * radii[m];
+        CIL_HIP(hipMemcpyAsync(s.thr, thr, sizeof(double) * M, hipMemcpyHostToDevice, st));
+    }
     CIL_TRY(fill_zero(s.hist, (char *)(s.nlist + 2) - (char *)s.hist, st));
     ClassifyArgs &c = ap.c;
     c.exclude_diag = 0;
     c.mode = MODE_BINS;
     c.thr = s.thr;
+    // With the device's radii, every pair within 2^-44 thr of a threshold is
+    // re-checked and its threshold marked: the host's ladder differs from the
+    // device's by a few units in the last place at most (where the C
+    // library's pow misrounds), so the bins are those of either ladder unless
+    // a marked threshold is one where they differ.
+    c.thr_slack = device_radii ? 0x1p-44 : 0.0;
     c.M = M;
     c.hist = s.hist;
     c.bins = bins;
@@ -857,37 +1026,22 @@ int adaptive_bins_async(const T *A, long long nA, const T *B, long long nB, long
     co.nB = nB;
     co.nexact = s.nexact;
     co.force_exact = g_force_exact;
-    // Any list length without reading it back.  Short vectors: one strided
-    // launch, 2048 waves, one pair each at a time.  Long vectors: the first
-    // launch as in bins_from_approx (256 pairs, 16 waves each: the usual
-    // short list at the latency of one pair), then a strided launch of 8192
-    // single-wave slots for the rest, which leaves at once when there is none.
-    if (dim < 4096) {
-        co.stride = 2048;
-        CIL_TRY(run_canonical(A, B, dim, co, 2048, st));
-    } else {
-        const long long first = std::min(recheck_guess(dim), std::max(s.cap, 1LL));
-        CIL_TRY(run_canonical(A, B, dim, co, first, st));
-        if (s.cap > first) {
-            constexpr long long TAIL = 8192;
-            co.first = first;
-            co.stride = TAIL;
-            const ProfMark pm = prof_begin("k_canonical", st);
-            hipLaunchKernelGGL((k_canonical<T, 1>), dim3((unsigned)(TAIL / 4)), dim3(256), 0, st, A, B, dim, co);
-            prof_end(pm, st);
-            CIL_TRY(check_launch("k_canonical"));
-        }
+    if (device_radii) {
+        co.win_rel = 0x1p-44;
+        co.win_hits = s.nlist + 7;
     }
+    CIL_TRY(canonical_any_length(A, B, dim, co, s.cap, st));
     ab->hist = s.hist;
     ab->nlist = s.nlist;
     ab->cap = s.cap;
+    ab->ro = device_radii ? s.ro : nullptr;
     return CIL_OK;
 }
 
 template int adaptive_bins_async<double>(const double *, long long, const double *, long long, long long, int, int,
-                                         double *, double *, double *, uint8_t *, AsyncBins *, hipStream_t);
+                                         int, double *, double *, double *, uint8_t *, AsyncBins *, hipStream_t);
 template int adaptive_bins_async<float>(const float *, long long, const float *, long long, long long, int, int,
-                                        double *, double *, double *, uint8_t *, AsyncBins *, hipStream_t);
+                                        int, double *, double *, double *, uint8_t *, AsyncBins *, hipStream_t);
 
 template int adaptive_bins_impl<double>(const double *, long long, const double *, long long, long long, int, int,
                                         int, double *, double *, double *, uint8_t *,

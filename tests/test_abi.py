@@ -138,6 +138,13 @@ def test_statistic_argument_validation():
         assert L.cil_set_option(cil.CIL_OPT_SYNC_SPIN_US, bad) == cil.CIL_EINVAL
     for good in (0, 200000):
         assert L.cil_set_option(cil.CIL_OPT_SYNC_SPIN_US, good) == cil.CIL_OK
+    for bad in (-1, 3):
+        assert L.cil_set_option(cil.CIL_OPT_STAT_DEVICE_RADII, bad) == cil.CIL_EINVAL
+    for good in (0, 2, 1):
+        assert L.cil_set_option(cil.CIL_OPT_STAT_DEVICE_RADII, good) == cil.CIL_OK
+    # the one-call statistic checks its sizes before touching the device
+    assert L.cil_statistic_adaptive(None, 0, None, 4, 8, cil.CIL_FP32, 3, 0, None, 1, None, 1, 2, None, None, None,
+                                    None, None, None, None, None, None, None, None, None) == cil.CIL_EINVAL
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

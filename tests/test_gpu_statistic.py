@@ -80,13 +80,24 @@ def check_same(cil, oracle_mod, A, B, M, n_boot, law, seed):
     return got
 
 
+@pytest.fixture(params=[1, 0, 2], ids=["device_radii", "host_radii", "forced_second_pass"])
+def radii_mode(cil, request):
+    """The radii formed on the device and checked (the default), formed on the
+    host, or the device's check forced to fail so that the call redoes the
+    statistic with the host's radii."""
+    cil.cil_set_option(cil.CIL_OPT_STAT_DEVICE_RADII, request.param)
+    yield request.param
+    cil.cil_set_option(cil.CIL_OPT_STAT_DEVICE_RADII, 1)
+
+
 @pytest.mark.parametrize("dtype,nA,nB,d,M,n_boot,law", [
     (np.float32, 250, 250, 8192, 13, 200, 0),      # the shape of the benchmarked statistic
     (np.float64, 70, 90, 515, 16, 50, 1),
     (np.float32, 37, 61, 200, 5, 9, 0),
     (np.float64, 1, 300, 64, 7, 2, 0),
+    (np.float32, 120, 140, 4096, 64, 20, 1),
 ])
-def test_statistic_matches_separate_calls_and_oracle(cil, oracle_mod, dtype, nA, nB, d, M, n_boot, law):
+def test_statistic_matches_separate_calls_and_oracle(cil, oracle_mod, radii_mode, dtype, nA, nB, d, M, n_boot, law):
     g = np.random.default_rng(nA + d)
     A = (0.3 * g.standard_normal((nA, d)) + 1.0).astype(dtype)
     B = (0.3 * g.standard_normal((nB, d)) + 1.0).astype(dtype)
@@ -123,7 +134,7 @@ def radius_heavy_sets(dtype, d=515, copies=60, M=6):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_statistic_with_a_long_recheck_list(cil, oracle_mod, dtype):
+def test_statistic_with_a_long_recheck_list(cil, oracle_mod, radii_mode, dtype):
     """3481 pairs on a radius: longer than the first canonical launch covers,
     so the strided launch after it finishes the list on the device (the call
     does not read the list's length in between); bins and counts stay the
@@ -143,7 +154,7 @@ def test_statistic_twice_smaller_second(cil, oracle_mod):
     check_same(cil, oracle_mod, A[:17], B[:23], 4, 5, 0, seed=2)
 
 
-def test_statistic_rejects_bad_bootstrap_index(cil):
+def test_statistic_rejects_bad_bootstrap_index(cil, radii_mode):
     g = np.random.default_rng(6)
     A = dev(g.standard_normal((4, 16)))
     B = dev(g.standard_normal((5, 16)))
@@ -157,7 +168,7 @@ def test_statistic_rejects_bad_bootstrap_index(cil):
     cil.cil_statistic_adaptive(A, B, 3, ia, ib)
 
 
-def test_statistic_rejects_bad_sizes(cil):
+def test_statistic_rejects_bad_sizes(cil, radii_mode):
     A = dev(np.ones((3, 8)))
     ia = torch.zeros((2, 3), dtype=torch.int32)
     with pytest.raises(cil.CilError):
@@ -167,3 +178,71 @@ def test_statistic_rejects_bad_sizes(cil):
     with pytest.raises(cil.CilError) as e:
         cil.cil_statistic_adaptive(A, A, 3, ia, ia)           # every distance 0: degenerate range
     assert e.value.code == cil.CIL_EINVAL
+
+
+def test_statistic_radii_across_many_ranges(cil):
+    """Over 200 random ranges, both laws and M up to 64, the call's radii are
+    the host's ladder (cil_radii, the oracle's expression), whether the
+    device's ladder agreed or the call took its second pass."""
+    g = np.random.default_rng(11)
+    ia = torch.zeros((2, 3), dtype=torch.int32)
+    calls = 200
+    cil.cil_profile(1)
+    try:
+        for t in range(calls):
+            d = 1 + int(g.integers(1, 40))
+            A = dev(g.standard_normal((3, d)) * float(np.exp(g.uniform(-3, 3))))
+            B = dev(g.standard_normal((3, d)) * float(np.exp(g.uniform(-3, 3))) + float(g.uniform(-2, 2)))
+            M = int(g.integers(1, 65))
+            law = int(t % 2)
+            lo, hi, radii, counts, *_ = cil.cil_statistic_adaptive(A, B, M, ia, ia, law=law)
+            assert np.array_equal(radii, cil.cil_radii(lo, hi, M, law=law))
+        passes = cil.cil_profile_read("k_classify_range1")[0]      # one range pass per call, two after a mismatch
+    finally:
+        cil.cil_profile(0)
+    assert calls <= passes <= calls + calls // 10
+
+
+def _cr_pow(x, y):
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    return float(str((Decimal(x).ln() * Decimal(y)).exp()))
+
+
+def _ladders_differ(lo, hi, M):
+    """Whether the device's ladder (correctly rounded powers) differs from
+    the host's (the C library's pow) for this range."""
+    R0, RM = math.sqrt(hi), math.sqrt(lo)
+    bh, bd = math.pow(R0 / RM, 1.0 / M), _cr_pow(R0 / RM, 1.0 / M)
+    return any(R0 * math.pow(bh, -m) != R0 * _cr_pow(bd, -m) for m in range(1, M + 1))
+
+
+def _range_passes(cil, A, B, M, ia, ib):
+    cil.cil_profile(1)
+    try:
+        got = cil.cil_statistic_adaptive(A, B, M, ia, ib)
+        return got, cil.cil_profile_read("k_classify_range1")[0]
+    finally:
+        cil.cil_profile(0)
+
+
+@pytest.mark.parametrize("near_pair", [False, True])
+def test_statistic_when_the_ladders_differ(cil, oracle_mod, near_pair):
+    """1-D sets with squared distances 56^2 .. 206^2 and M = 9: there the C
+    library's pow misrounds b^-6, and R_6 = R_0 b^-6 with it, by one unit, so
+    the device's ladder differs from the host's.  With no pair near a
+    threshold the bins stand and the call makes one pass; with a pair at R_6
+    (from the host's ladder) it makes a second pass with the host's radii.
+    Either way the results are the separate calls' and the oracle's."""
+    M = 9
+    A = np.zeros((1, 1))
+    B = np.array([[56.0], [206.0], [80.0], [120.0], [170.0]])
+    r = cil.cil_radii(56.0 ** 2, 206.0 ** 2, M)
+    if near_pair:
+        B = np.vstack([B, [[r[5]]]])
+    differ = _ladders_differ(56.0 ** 2, 206.0 ** 2, M)
+    assert differ
+    ia, ib = cs.resample_halves(1, B.shape[0], 1, B.shape[0], 6, seed=4)
+    _, passes = _range_passes(cil, dev(A), dev(B), M, torch.from_numpy(ia), torch.from_numpy(ib))
+    assert passes == (2 if (differ and near_pair) else 1)
+    check_same(cil, oracle_mod, A, B, M, 6, 0, seed=4)
