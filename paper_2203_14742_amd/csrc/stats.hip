@@ -622,6 +622,65 @@ __global__ __launch_bounds__(256) void k_loglik(const double *Y, int n, int M, c
     }
     wsync();
     const int K = nk;
+    if (K <= 16) {
+        // Up to 16 kept bins: lane i holds row i of Sigma in registers and
+        // reads other lanes' entries with readlane, so no step waits on the
+        // LDS.  Right-looking Cholesky and solve: every entry subtracts its
+        // terms in index order, the operations of the left-looking form.
+        constexpr int R = 16;
+        auto bcast = [](double x, int src) {               // src is a compile-time lane after unrolling
+            const long long v = __double_as_longlong(x);
+            const int lo = __builtin_amdgcn_readlane((int)v, src);
+            const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+            return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        };
+        const int kl = lane < K ? keep[lane] : 0;
+        double r[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) r[j] = (lane < K && j < K) ? S[kl][keep[j < K ? j : 0]] : 0.0;
+        const double dg_own = lane < K ? S[kl][kl] : 0.0;
+        double diag_own = 0.0;
+        int ok = 1;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (j < K) {
+                const double sv = bcast(r[j], j), dgj = bcast(dg_own, j);
+                const double d = (sv > K * 0x1p-52 * dgj) ? sqrt(sv) : NAN;
+                if (!(d > 0.0)) ok = 0;
+                if (lane == j) {
+                    r[j] = d;
+                    diag_own = d;
+                }
+                if (lane > j && lane < K) r[j] = r[j] / d;
+#pragma unroll
+                for (int c = j + 1; c < R; ++c) {
+                    if (c < K) {
+                        const double lcj = bcast(r[j], c);
+                        if (lane >= c && lane < K) r[c] -= r[j] * lcj;
+                    }
+                }
+            }
+        }
+        const double lg_own = (ok && lane < K) ? log(diag_own) : 0.0;
+        double rhs = lane < K ? yobs[(size_t)p * M + kl] - mu[kl] : 0.0;
+        double acc = 0.0, ld = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k < K) {
+                const double zk = bcast(rhs, k) / bcast(diag_own, k);
+                if (lane > k && lane < K) rhs -= r[k] * zk;
+                acc += zk * zk;
+                ld += bcast(lg_own, k);
+            }
+        }
+        if (lane == 0) {
+            f[p] = ok ? acc : NAN;
+            loglik[p] = ok ? -0.5 * acc - ld - 0.5 * K * log(2.0 * M_PI) : NAN;
+            meff[p] = K;
+            status[p] = ok ? CIL_OK : CIL_ENOTSPD;
+        }
+        return;
+    }
     // compact the kept rows/columns into the leading K x K block (in place:
     // keep[] is increasing so keep[a] >= a); lane c moves column c
     for (int a = 0; a < K; ++a) {
