@@ -316,14 +316,15 @@ struct QuadLine {
             // the same operation count as forming w and ph, and no per-k1 lane
             // twiddles that the compiler could precompute and keep live.
             if constexpr (CT >= 1) {
-                const T Vr = Er + (L.w_r[k1] * Or - L.w_i[k1] * Oi), Vi = Ei + (L.w_r[k1] * Oi + L.w_i[k1] * Or);
+                const T Vr = fma(L.w_r[k1], Or, fma(-L.w_i[k1], Oi, Er));
+                const T Vi = fma(L.w_r[k1], Oi, fma(L.w_i[k1], Or, Ei));
                 xa[k1] = L.ph_r[k1] * Vr - L.ph_i[k1] * Vi;
                 xb[k1] = -(L.ph_r[k1] * Vi + L.ph_i[k1] * Vr);
             } else {
                 constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
                 constexpr T l2r = (T)ce_cospi(k1, 2 * N), l2i = (T)(-ce_sinpi(k1, 2 * N));
                 const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
-                const T Vr = Er + (l1r * ar - l1i * ai), Vi = Ei + (l1r * ai + l1i * ar);
+                const T Vr = fma(l1r, ar, fma(-l1i, ai, Er)), Vi = fma(l1r, ai, fma(l1i, ar, Ei));
                 const T br = L.be_r * Vr - L.be_i * Vi, bi = L.be_r * Vi + L.be_i * Vr;      // beta V
                 xa[k1] = l2r * br - l2i * bi;
                 xb[k1] = -(l2r * bi + l2i * br);
@@ -368,13 +369,13 @@ struct QuadLine {
             const T a = zr[k1], b = zi[k1];
             const T Er = a + c, Ei = b + d, Or = b - d, Oi = c - a;
             if constexpr (CT >= 1) {
-                vr[k1] = Er + (L.w_r[k1] * Or - L.w_i[k1] * Oi);
-                vi[k1] = Ei + (L.w_r[k1] * Oi + L.w_i[k1] * Or);
+                vr[k1] = fma(L.w_r[k1], Or, fma(-L.w_i[k1], Oi, Er));
+                vi[k1] = fma(L.w_r[k1], Oi, fma(L.w_i[k1], Or, Ei));
             } else {
                 constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
                 const T ar = L.al_r * Or - L.al_i * Oi, ai = L.al_r * Oi + L.al_i * Or;      // alpha O
-                vr[k1] = Er + (l1r * ar - l1i * ai);
-                vi[k1] = Ei + (l1r * ai + l1i * ar);
+                vr[k1] = fma(l1r, ar, fma(-l1i, ai, Er));
+                vi[k1] = fma(l1r, ai, fma(l1i, ar, Ei));
             }
             if constexpr (k1 == 0) {
                 constexpr T c4 = (T)ce_cospi(1, 4);
@@ -405,19 +406,17 @@ struct QuadLine {
             }
             const T Er = vr[k1] + mr, Ei = vi[k1] - mi;
             const T pr = vr[k1] - mr, pi = vi[k1] + mi;
-            T Or, Oi;
-            if constexpr (CT >= 1) {                                                       // p conj(w)
-                Or = pr * L.w_r[k1] + pi * L.w_i[k1];
-                Oi = pi * L.w_r[k1] - pr * L.w_i[k1];
+            // Z = E + i O, O = p conj(w): each part one chain of multiply-adds into E
+            constexpr int p = bitrev(k1, LOGP);
+            if constexpr (CT >= 1) {
+                zr[p] = fma(-pi, L.w_r[k1], fma(pr, L.w_i[k1], Er));
+                zi[p] = fma(pr, L.w_r[k1], fma(pi, L.w_i[k1], Ei));
             } else {
                 constexpr T l1r = (T)ce_cospi(2 * k1, N), l1i = (T)(-ce_sinpi(2 * k1, N));
                 const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;   // p conj(alpha)
-                Or = l1r * t3r + l1i * t3i;
-                Oi = l1r * t3i - l1i * t3r;
+                zr[p] = fma(-l1r, t3i, fma(l1i, t3r, Er));
+                zi[p] = fma(l1r, t3r, fma(l1i, t3i, Ei));
             }
-            constexpr int p = bitrev(k1, LOGP);
-            zr[p] = Er - Oi;
-            zi[p] = Ei + Or;
         });
         inverse_core(L, zr, zi);
     }
@@ -473,10 +472,9 @@ struct QuadLine {
             }
             const T Er = ar + c, Ei = ai + d;
             const T pr = ar - c, pi = ai - d;
-            const T Or = pr * L.w_r[K1] + pi * L.w_i[K1], Oi = pi * L.w_r[K1] - pr * L.w_i[K1];
-            constexpr int p = bitrev(K1, LOGP);
-            zr[p] = Er - Oi;
-            zi[p] = Ei + Or;
+            constexpr int p = bitrev(K1, LOGP);          // Z = E + i p conj(w)
+            zr[p] = fma(-pi, L.w_r[K1], fma(pr, L.w_i[K1], Er));
+            zi[p] = fma(pr, L.w_r[K1], fma(pi, L.w_i[K1], Ei));
             return;
         }
         constexpr T l2r = (T)ce_cospi(K1, 2 * N), l2i = (T)(-ce_sinpi(K1, 2 * N));
@@ -493,10 +491,9 @@ struct QuadLine {
         const T pr = ar - c, pi = ai - d;
         // O = p conj(alpha) conj(lit1)
         const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;
-        const T Or = l1r * t3r + l1i * t3i, Oi = l1r * t3i - l1i * t3r;
-        constexpr int p = bitrev(K1, LOGP);
-        zr[p] = Er - Oi;
-        zi[p] = Ei + Or;
+        constexpr int p = bitrev(K1, LOGP);              // Z = E + i O
+        zr[p] = fma(-l1r, t3i, fma(l1i, t3r, Er));
+        zi[p] = fma(l1r, t3r, fma(l1i, t3i, Ei));
     }
 
     // zr/zi arrive bit-reversed in k1; the cross-lane stage works elementwise,
