@@ -215,10 +215,17 @@ struct QuadLine {
                         tr = (SIGN > 0) ? -im[b] : im[b];
                         ti = (SIGN > 0) ? re[b] : -re[b];
                     } else {
+                        // a + w b as multiply-add chains into a, then a - w b as
+                        // 2 a - (a + w b): three instructions per part instead of
+                        // four, within one rounding of the sum
                         constexpr T wr = (T)ce_cospi(2 * j, m);
                         constexpr T wi = (T)(SIGN * ce_sinpi(2 * j, m));
-                        tr = wr * re[b] - wi * im[b];
-                        ti = wr * im[b] + wi * re[b];
+                        const T ar = re[a], ai = im[a];
+                        re[a] = fma(wr, re[b], fma(-wi, im[b], ar));
+                        im[a] = fma(wr, im[b], fma(wi, re[b], ai));
+                        re[b] = fma(T(2), ar, -re[a]);
+                        im[b] = fma(T(2), ai, -im[a]);
+                        return;
                     }
                     re[b] = re[a] - tr;
                     im[b] = im[a] - ti;
@@ -458,20 +465,20 @@ struct QuadLine {
         if constexpr (CT >= 1) {
             // conj(ph) (xk - i xn); conj(g (ym - i yp)), g = e^{i pi/4} ph; O = p conj(w)
             const T ar = L.ph_r[K1] * xk - L.ph_i[K1] * xn, ai = -(L.ph_r[K1] * xn + L.ph_i[K1] * xk);
-            T c, d;
+            // E = a + (c + i d), p = a - (c + i d): E by multiply-add chains into a, p as 2 a - E
+            T Er, Ei;
             if constexpr (CT >= 2) {
-                c = L.g_r[K1] * ym + L.g_i[K1] * yp;
-                d = L.g_r[K1] * yp - L.g_i[K1] * ym;
+                Er = fma(L.g_r[K1], ym, fma(L.g_i[K1], yp, ar));
+                Ei = fma(L.g_r[K1], yp, fma(-L.g_i[K1], ym, ai));
             } else {                   // beta (ym - i yp), then e^{i pi/4} lit2, conjugated
                 constexpr T l2r = (T)ce_cospi(K1, 2 * N), l2i = (T)(-ce_sinpi(K1, 2 * N));
                 constexpr T c4 = (T)ce_cospi(1, 4);
                 constexpr T gr = c4 * (l2r - l2i), gi = c4 * (l2r + l2i);
                 const T t2r = L.be_r * ym + L.be_i * yp, t2i = L.be_i * ym - L.be_r * yp;
-                c = gr * t2r - gi * t2i;
-                d = -(gr * t2i + gi * t2r);
+                Er = fma(gr, t2r, fma(-gi, t2i, ar));
+                Ei = fma(-gr, t2i, fma(-gi, t2r, ai));
             }
-            const T Er = ar + c, Ei = ai + d;
-            const T pr = ar - c, pi = ai - d;
+            const T pr = fma(T(2), ar, -Er), pi = fma(T(2), ai, -Ei);
             constexpr int p = bitrev(K1, LOGP);          // Z = E + i p conj(w)
             zr[p] = fma(-pi, L.w_r[K1], fma(pr, L.w_i[K1], Er));
             zi[p] = fma(pr, L.w_r[K1], fma(pi, L.w_i[K1], Ei));
@@ -486,9 +493,8 @@ struct QuadLine {
         const T ar = l2r * t1r + l2i * t1i, ai = l2r * t1i - l2i * t1r;
         // beta (ym - i yp), then e^{i pi/4} lit2; c + i d = conj(V_{M-k})
         const T t2r = L.be_r * ym + L.be_i * yp, t2i = L.be_i * ym - L.be_r * yp;
-        const T c = gr * t2r - gi * t2i, d = -(gr * t2i + gi * t2r);
-        const T Er = ar + c, Ei = ai + d;
-        const T pr = ar - c, pi = ai - d;
+        const T Er = fma(gr, t2r, fma(-gi, t2i, ar)), Ei = fma(-gr, t2i, fma(-gi, t2r, ai));
+        const T pr = fma(T(2), ar, -Er), pi = fma(T(2), ai, -Ei);          // a - (c + i d)
         // O = p conj(alpha) conj(lit1)
         const T t3r = pr * L.al_r + pi * L.al_i, t3i = pi * L.al_r - pr * L.al_i;
         constexpr int p = bitrev(K1, LOGP);              // Z = E + i O
